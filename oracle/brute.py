@@ -1,0 +1,127 @@
+"""Brute force over a dense pattern, for tiny matrices only.
+
+Test infrastructure (see the package docstring).  Each communication set is
+evaluated straight from its quantifiers ("there exist i in R(t) and j in R(r)
+with A_ij != 0"), by looping over ranks, nodes and dense row/column ranges.
+This is a different route from ``plan_ref`` (which walks the stored entries
+once) and is used to pin it.  The product is the dense matrix times the
+vector with NumPy (a library matmul), which pins the CSR SpMV of ``spmv``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def dense(csr) -> np.ndarray:
+    """Dense float64 matrix; duplicate stored entries are summed."""
+    a = np.zeros((csr.n, csr.n))
+    for i in range(csr.n):
+        for k in range(int(csr.rowptr[i]), int(csr.rowptr[i + 1])):
+            a[i, csr.col[k]] += csr.val[k]
+    return a
+
+
+def pattern(csr) -> np.ndarray:
+    """Structural pattern: True where an entry is stored (even a stored zero)."""
+    s = np.zeros((csr.n, csr.n), dtype=bool)
+    for i in range(csr.n):
+        s[i, csr.col[csr.rowptr[i]:csr.rowptr[i + 1]]] = True
+    return s
+
+
+def matvec(csr, v: np.ndarray) -> np.ndarray:
+    return dense(csr) @ np.asarray(v, dtype=np.float64)
+
+
+def blocks(n: int, n_p: int, row_starts=None):
+    """R(r) as Python ranges, with the remainder rows on the last rank."""
+    if row_starts is None:
+        b = n // n_p
+        row_starts = [b * r for r in range(n_p)] + [n]
+    return [range(int(row_starts[r]), int(row_starts[r + 1])) for r in range(n_p)]
+
+
+def _exists(S, rows, cols) -> bool:
+    return any(S[i, j] for i in rows for j in cols)
+
+
+def standard_sets(csr, n_p: int, ppn: int, row_starts=None) -> dict:
+    """P(r) and D(r, t), straight from their quantifiers."""
+    S = pattern(csr)
+    R = blocks(csr.n, n_p, row_starts)
+    P = {r: [t for t in range(n_p) if t != r and _exists(S, R[t], R[r])] for r in range(n_p)}
+    D = {}
+    for r in range(n_p):
+        for t in P[r]:
+            D[(r, t)] = [j for j in R[r] if any(S[i, j] for i in R[t])]
+    return {"P": P, "D": D}
+
+
+def node_sets(csr, n_p: int, ppn: int, row_starts=None):
+    """N(n) and E(n, m), straight from their quantifiers over (p, q)."""
+    S = pattern(csr)
+    R = blocks(csr.n, n_p, row_starts)
+    nodes = n_p // ppn
+    rank = lambda p, n: n * ppn + p  # noqa: E731
+    E = {}
+    for n in range(nodes):
+        for m in range(nodes):
+            if m == n:
+                continue
+            idx = [j for p in range(ppn) for j in R[rank(p, n)]
+                   if any(S[i, j] for q in range(ppn) for i in R[rank(q, m)])]
+            if idx:
+                E[(n, m)] = sorted(idx)
+    N = {n: sorted(m for (a, m) in E if a == n) for n in range(nodes)}
+    return N, E
+
+
+def mapping(n_p: int, ppn: int, E: dict):
+    """The T/U assignment, from a dense node-to-node volume matrix and
+    ``numpy.lexsort`` (a second route to the rule of ``plan_ref.mapping``)."""
+    nodes = n_p // ppn
+    vol = np.zeros((nodes, nodes), dtype=np.int64)
+    for (n, m), idx in E.items():
+        vol[n, m] = len(idx)
+    send_rank, recv_rank = {}, {}
+    for n in range(nodes):
+        partners = np.flatnonzero(vol[n] > 0)
+        order = partners[np.lexsort((partners, -vol[n, partners]))]
+        for k, m in enumerate(order):
+            send_rank[(n, int(m))] = n * ppn + k % ppn
+        senders = np.flatnonzero(vol[:, n] > 0)
+        order = senders[np.lexsort((senders, -vol[n, senders]))]
+        for k, m in enumerate(order):
+            recv_rank[(int(m), n)] = n * ppn + ppn - 1 - k % ppn
+    return send_rank, recv_rank
+
+
+def nap_sets(csr, n_p: int, ppn: int, row_starts=None) -> dict:
+    """I, and J of the three local steps, from their quantifiers, given E and
+    the mapping."""
+    S = pattern(csr)
+    R = blocks(csr.n, n_p, row_starts)
+    N, E = node_sets(csr, n_p, ppn, row_starts)
+    send_rank, recv_rank = mapping(n_p, ppn, E)
+    node = lambda r: r // ppn  # noqa: E731
+    I = {(send_rank[k], recv_rank[k]): E[k] for k in E}
+    J0, J1, J2 = {}, {}, {}
+    for p in range(n_p):
+        for s in range(n_p):
+            if s == p or node(s) != node(p):
+                continue
+            # J0: values of R(p) that s sends off-node.
+            out = [j for j in R[p] if any(j in idx for (a, b), idx in I.items() if a == s)]
+            if out:
+                J0[(p, s)] = out
+            # J1: values p received off-node that a row of s uses.
+            got = sorted({j for (a, b), idx in I.items() if b == p for j in idx})
+            fw = [j for j in got if any(S[i, j] for i in R[s])]
+            if fw:
+                J1[(p, s)] = fw
+            # J2: values of R(p) that a row of s uses.
+            loc = [j for j in R[p] if any(S[i, j] for i in R[s])]
+            if loc:
+                J2[(p, s)] = loc
+    return {"N": N, "E": E, "send_rank": send_rank, "recv_rank": recv_rank,
+            "I": I, "J0": J0, "J1": J1, "J2": J2}

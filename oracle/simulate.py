@@ -1,0 +1,160 @@
+"""Delivery of vector values along a plan's messages, rank by rank, and the
+split local SpMVs, following algorithms standard_spmv (section 2.1) and
+local_comm / NAPSpMV (section 4.3).
+
+Test infrastructure (see the package docstring).  Every rank gets its own
+host buffers; a "message" is a Python list of values copied from the sender's
+buffer; nothing is shared between ranks except what a message carries.  The
+simulation asserts that every slot of every ghost list is written exactly
+once, with the owner's value, bit for bit.
+
+The split product sums, per row and in stored order, first the on-process
+block and then the off-process block (standard), or the on_process, on_node
+and off_node blocks in that order (NAPSpMV).
+"""
+from __future__ import annotations
+
+from collections import defaultdict
+
+import numpy as np
+
+from .plan_ref import Layout, ghosts
+
+
+class DeliveryError(AssertionError):
+    pass
+
+
+def _local_v(lay: Layout, v):
+    return [np.asarray(v[lay.R(r).start:lay.R(r).stop], dtype=np.float64)
+            for r in range(lay.n_p)]
+
+
+def _send(lay, v_loc, r, idx):
+    """The pack loop: values of R(r) at global indices idx, read from r's own
+    slice of v."""
+    base = lay.R(r).start
+    return [float(v_loc[r][j - base]) for j in idx]
+
+
+def _receive(slots, counts, idx, vals, expect=None):
+    for j, x in zip(idx, vals):
+        if j not in slots:
+            continue
+        counts[j] += 1
+        slots[j] = x
+
+
+def simulate_standard(csr, lay: Layout, plan: dict, v):
+    """standard_spmv on every rank.  Returns (ghost values per rank, w)."""
+    gh = ghosts(csr, lay)
+    v_loc = _local_v(lay, v)
+    inbox = defaultdict(list)
+    for phase in ("INTER", "L2"):
+        for r, t, idx in plan["phases"][phase]:
+            inbox[t].append((idx, _send(lay, v_loc, r, idx)))
+    ghost_vals = []
+    for t in range(lay.n_p):
+        slots = {j: None for j in gh[t]}
+        counts = defaultdict(int)
+        for idx, vals in inbox[t]:
+            for j in idx:
+                if j not in slots:
+                    raise DeliveryError(f"rank {t} received unneeded index {j}")
+            _receive(slots, counts, idx, vals)
+        _check(t, gh[t], counts, slots, v)
+        ghost_vals.append(slots)
+    w = _split_product(csr, lay, v_loc, ghost_vals, three_way=False)
+    return ghost_vals, w
+
+
+def simulate_nap(csr, lay: Layout, plan: dict, v):
+    """NAPSpMV on every rank.  Returns (ghost values per rank, w)."""
+    gh = ghosts(csr, lay)
+    v_loc = _local_v(lay, v)
+    ph = plan["phases"]
+
+    # local_comm(on_node -> on_node): b_{l->l}.
+    b_ll = [dict() for _ in range(lay.n_p)]
+    for r, t, idx in ph["L2"]:
+        assert lay.node(r) == lay.node(t)
+        for j, x in zip(idx, _send(lay, v_loc, r, idx)):
+            b_ll[t][j] = b_ll[t].get(j, ()) + (x,)
+    # local_comm(on_node -> off_node): b_{l->nl}.
+    b_lnl = [dict() for _ in range(lay.n_p)]
+    for p, s, idx in ph["L0"]:
+        assert lay.node(p) == lay.node(s)
+        for j, x in zip(idx, _send(lay, v_loc, p, idx)):
+            b_lnl[s][j] = x
+    # Inter-node pack: own values from v|R, the rest from b_{l->nl}.
+    g_recv = [dict() for _ in range(lay.n_p)]
+    for s, q, idx in ph["INTER"]:
+        assert lay.node(s) != lay.node(q)
+        g_send = []
+        for j in idx:
+            if lay.owner(j) == s:
+                g_send.append(float(v_loc[s][j - lay.R(s).start]))
+            elif j in b_lnl[s]:
+                g_send.append(b_lnl[s][j])
+            else:
+                raise DeliveryError(f"rank {s} must send {j} but never received it")
+        for j, x in zip(idx, g_send):
+            if j in g_recv[q]:
+                raise DeliveryError(f"rank {q} received {j} twice off-node")
+            g_recv[q][j] = x
+    # local_comm(off_node -> on_node): forwards from g_recv.
+    b_nll = [dict() for _ in range(lay.n_p)]
+    for q, t, idx in ph["L1"]:
+        assert lay.node(q) == lay.node(t)
+        for j in idx:
+            if j not in g_recv[q]:
+                raise DeliveryError(f"rank {q} forwards {j} it never received")
+            b_nll[t][j] = b_nll[t].get(j, ()) + (g_recv[q][j],)
+
+    ghost_vals = []
+    for t in range(lay.n_p):
+        slots = {j: None for j in gh[t]}
+        counts = defaultdict(int)
+        for src in (b_ll[t], b_nll[t]):
+            for j, xs in src.items():
+                if j not in slots:
+                    raise DeliveryError(f"rank {t} received unneeded index {j}")
+                for x in xs:
+                    counts[j] += 1
+                    slots[j] = x
+        for j, x in g_recv[t].items():       # the receiver's own use
+            if j in slots:
+                counts[j] += 1
+                slots[j] = x
+        _check(t, gh[t], counts, slots, v)
+        ghost_vals.append(slots)
+    w = _split_product(csr, lay, v_loc, ghost_vals, three_way=True)
+    return ghost_vals, w
+
+
+def _check(t, gh_t, counts, slots, v):
+    for j in gh_t:
+        if counts.get(j, 0) != 1:
+            raise DeliveryError(f"rank {t}: ghost {j} written {counts.get(j, 0)} times")
+        if np.float64(slots[j]).tobytes() != np.float64(v[j]).tobytes():
+            raise DeliveryError(f"rank {t}: ghost {j} holds a wrong value")
+
+
+def _split_product(csr, lay, v_loc, ghost_vals, three_way: bool):
+    """local_spmv on the split blocks of every rank."""
+    w = np.zeros(csr.n)
+    for t in range(lay.n_p):
+        base = lay.R(t).start
+        for i in lay.R(t):
+            parts = [0.0, 0.0, 0.0]
+            for k in range(int(csr.rowptr[i]), int(csr.rowptr[i + 1])):
+                j, a = int(csr.col[k]), float(csr.val[k])
+                r = lay.owner(j)
+                if r == t:
+                    parts[0] += a * float(v_loc[t][j - base])
+                elif three_way and lay.node(r) == lay.node(t):
+                    parts[1] += a * ghost_vals[t][j]
+                else:
+                    parts[2] += a * ghost_vals[t][j]
+            w[i] = (parts[0] + parts[1]) + parts[2] if three_way else parts[0] + parts[2]
+    return w
