@@ -1,0 +1,242 @@
+"""Benchmark of the node-aware SpMV hot path on one MI355X.
+
+One step = one apply of the plan: the exchange that fills every process's
+ghost buffer from v (section 2.1 / section 4 messages as device gathers) and
+the split product w = A_on v + A_off ghost, over the largest paper-shaped
+workload (KKT-like random matrix, N = 2^22, n_p = 2048, ppn = 16, float64),
+inputs resident in HBM.  Prints ONE JSON line on stdout; progress goes to
+stderr.
+
+value = algorithmic bytes of one apply / time per apply (GB/s).  The bytes
+count every array element the method must touch once:
+  product:  nnz*(s_a + 4) + (N+1)*4 + N*s_v (v) + G*s_v (ghosts) + N*s_v (w)
+  gather:   G*(4 + 2*s_v)                      (standard mode)
+  NAP:      E*(4 + 2*s_v) + H*(8 + 2*s_v) + G_on*(8 + 2*s_v)  (+2*E*s_v if copied)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(st, s_a, s_v):
+    n, nnz, g = st["n"], st["nnz"], st["ghosts"]
+    return nnz * (s_a + 4) + (n + 1) * 4 + n * s_v + g * s_v + n * s_v
+
+
+def exchange_bytes(st, s_v, exchange_copy=False):
+    ph = st["phases"]
+    if st["mode"] == "standard":
+        return st["ghosts"] * (4 + 2 * s_v)
+    e = ph["INTER"]["elems"]
+    g_on = ph["L2"]["elems"]
+    h = st["ghosts"] - g_on
+    b = e * (4 + 2 * s_v) + h * (8 + 2 * s_v) + g_on * (8 + 2 * s_v)
+    return b + (2 * e * s_v if exchange_copy else 0)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "napspmv.hip"):
+        with open(os.path.join(ROOT, "paper_1612_08060_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str, launch_bytes: float):
+    """HBM traffic of the dominant kernel from the committed counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_apply(plan, v, w, steps, warmup, torch, nap):
+    """Warm up, then time exactly `steps` applies; events bracket each stage
+    on the stream the kernels run on."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.apply(v, w, stream=stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        plan.apply_stage(nap.STAGE_EXCHANGE, v, w, stream=stream)
+        ev[k][1].record(stream)
+        plan.apply_stage(nap.STAGE_SPMV, v, w, stream=stream)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    exch = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    spmv = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+    return (t1 - t0) * 1e3 / steps, sum(exch) / steps, sum(spmv) / steps
+
+
+def cpu_baseline(wl, budget_s):
+    """The oracle's float64 CSR SpMV (plain C, OpenMP) on the host cores."""
+    import numpy as np
+    from oracle import spmv as oracle_spmv
+    a = wl.csr
+    threads = len(os.sched_getaffinity(0))
+    used = oracle_spmv.threads_used(threads)
+    w = np.empty(a.n)
+    oracle_spmv.spmv(a, wl.v, threads=threads, out=w)          # warm-up
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle_spmv.spmv(a, wl.v, threads=threads, out=w)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    nbytes = a.nnz * 12 + (a.n + 1) * 8 + 2 * a.n * 8
+    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": used,
+            "kind": "oracle",
+            "sample": f"{reps} float64 CSR SpMVs of the full workload matrix "
+                      f"({a.nnz} nnz), {dt * 1e3:.1f} ms each; bytes nnz*12+(N+1)*8+2*N*8"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--extras", type=int, default=1, help="also time NAP mode and reduced precision")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the whole hot path lives on one device); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1612_08060_amd as nap
+    from workloads import bf16_bits, config, digest, to_f32
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    nap.load_library()
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    wl = config(args.config)
+    a = wl.csr
+    log(f"workload {wl.name}: n={a.n} nnz={a.nnz} ({time.perf_counter() - t:.1f}s) "
+        f"sha256={digest(a.rowptr, a.col, a.val, wl.v)[:16]}")
+
+    t = time.perf_counter()
+    plan = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="standard", dtype="f64",
+                    row_starts=wl.row_starts)
+    if args.lanes:
+        plan.lanes = args.lanes
+    st = plan.stats
+    log(f"standard plan: build {st['build_seconds']:.2f}s upload {st['upload_seconds']:.2f}s "
+        f"lanes {plan.lanes}")
+    v = torch.from_numpy(wl.v).to(dev)
+    w = torch.empty_like(v)
+
+    ms, exch_ms, spmv_ms = time_apply(plan, v, w, args.steps, args.warmup, torch, nap)
+    s_bytes = spmv_bytes(st, 8, 8)
+    x_bytes = exchange_bytes(st, 8)
+    total = s_bytes + x_bytes
+    log(f"apply {ms:.4f} ms  (exchange {exch_ms:.4f} ms, product {spmv_ms:.4f} ms)")
+
+    achieved = s_bytes / (spmv_ms * 1e-3) / 1e9
+    traffic = measured_traffic("spmv_kkt_f64", s_bytes)
+    result = {
+        "metric": "SpMV GB/s vs HBM peak (split SpMV + ghost gather)",
+        "value": round(total / (ms * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": a.n, "nnz": a.nnz, "n_p": wl.n_p, "ppn": wl.ppn,
+                   "mode": "standard", "bytes_per_step": total},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "kernel": "k_spmv",
+                     "kernel_ms": round(spmv_ms, 5), "kernel_bytes": s_bytes},
+        "frac_of_hbm_peak": round(total / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "gflops": round(2 * a.nnz / (ms * 1e-3) / 1e9, 1),
+        "exchange": {"ms": round(exch_ms, 5), "bytes": x_bytes,
+                     "gbs": round(x_bytes / (exch_ms * 1e-3) / 1e9, 1)},
+        "plan_build_s": {"standard": round(st["build_seconds"], 3)},
+    }
+    plan.close()
+
+    if args.extras:
+        ext = {}
+        # NAP mode: same ghosts, node-aware messages
+        pn = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="nap", dtype="f64",
+                      row_starts=wl.row_starts)
+        sn = pn.stats
+        w2 = torch.empty_like(v)
+        ms_n, ex_n, sp_n = time_apply(pn, v, w2, max(10, args.steps // 2), 2, torch, nap)
+        bn = spmv_bytes(sn, 8, 8) + exchange_bytes(sn, 8)
+        torch.cuda.synchronize()
+        ext["nap_f64"] = {"ms": round(ms_n, 5), "gbs": round(bn / (ms_n * 1e-3) / 1e9, 1),
+                          "exchange_ms": round(ex_n, 5),
+                          "bitwise_equal_to_standard": bool(torch.equal(w, w2))}
+        result["plan_build_s"]["nap"] = round(sn["build_seconds"], 3)
+        sph, nph = st["phases"], sn["phases"]
+        result["ghost_bytes"] = {
+            "standard_inter": {"msgs": sph["INTER"]["msgs"], "bytes": sph["INTER"]["elems"] * 8,
+                               "max_msgs_sent": sph["INTER"]["max_msgs_sent"],
+                               "max_bytes_sent": sph["INTER"]["max_elems_sent"] * 8},
+            "nap_inter": {"msgs": nph["INTER"]["msgs"], "bytes": nph["INTER"]["elems"] * 8,
+                          "max_msgs_sent": nph["INTER"]["max_msgs_sent"],
+                          "max_bytes_sent": nph["INTER"]["max_elems_sent"] * 8},
+            "standard_intra_bytes": sph["L2"]["elems"] * 8,
+            "nap_intra_bytes": (nph["L0"]["elems"] + nph["L1"]["elems"] + nph["L2"]["elems"]) * 8,
+        }
+        pn.close()
+        del w2
+        # reduced-precision values, float32 accumulation; error against the
+        # float64 apply above (itself checked against the oracle by the tests)
+        ref = w.cpu().numpy()
+        vf = torch.from_numpy(to_f32(wl.v)).to(dev)
+        for dt, vals in (("f32", to_f32(a.val)), ("bf16", bf16_bits(a.val))):
+            pr = nap.Plan(a.rowptr, a.col, vals, a.n, wl.n_p, wl.ppn, mode="standard",
+                          dtype=dt, row_starts=wl.row_starts)
+            wr = torch.empty_like(vf)
+            ms_r, ex_r, sp_r = time_apply(pr, vf, wr, max(10, args.steps // 2), 2, torch, nap)
+            sr = pr.stats
+            br = spmv_bytes(sr, 4 if dt == "f32" else 2, 4) + exchange_bytes(sr, 4)
+            got = wr.cpu().numpy().astype(np.float64)
+            ext[dt] = {"ms": round(ms_r, 5), "gbs": round(br / (ms_r * 1e-3) / 1e9, 1),
+                       "speedup_vs_f64": round(ms / ms_r, 3),
+                       "rel_err_vs_f64_apply": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+            pr.close()
+        result["extras"] = ext
+
+    if args.cpu_seconds > 0:
+        log("timing the CPU oracle ...")
+        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

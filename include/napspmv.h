@@ -1,0 +1,210 @@
+/*
+ * napspmv.h -- node-aware parallel sparse matrix-vector multiplication on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library computes w = A v (section 1 of Bienz, Gropp, Olson, "Node aware
+ * sparse matrix-vector multiplication") with the rows of the N x N matrix A
+ * split into n_p contiguous blocks, one per simulated process, and the
+ * processes grouped ppn per node in SMP order: rank r is the pair
+ * (r mod ppn, r div ppn) (section 2).  Every block's rows are split into an
+ * on-process part (columns the process owns) and an off-process part
+ * (columns owned elsewhere, the process's "ghosts") (section 2, the
+ * on_process / off_process definitions).  All processes live on one GPU, so
+ * every message of the paper's algorithms becomes a device gather or scatter
+ * over index lists that a communication plan holds:
+ *
+ *   standard mode  -- the reference scheme of section 2.1 (algorithm
+ *                     standard_spmv): one message per (owner, user) pair.
+ *   NAP mode       -- the node-aware scheme of section 4 (algorithm
+ *                     NAPSpMV): ghosts deduplicated per destination node,
+ *                     gathered on the source node, sent in one inter-node
+ *                     message per node pair, scattered on the destination
+ *                     node; on-node ghosts go directly.
+ *
+ * Both modes fill the same ghost buffer (each process's ghosts in ascending
+ * column order) and run the same split product
+ *     w_i = sum_on a_ij v_j + sum_off a_ij ghost_t(j),
+ * so their results are bitwise identical.
+ *
+ * Conventions for every call:
+ *   - Return 0 (NAPSPMV_OK) on success or a negative NAPSPMV_E* code; nothing
+ *     throws across this interface.  napspmv_last_error() gives a message
+ *     for the last failure on the calling thread.
+ *   - Host arrays passed in are borrowed for the duration of the call only.
+ *   - "device" pointers are HIP device allocations of the GPU that was
+ *     current when the plan was created; "stream" is a hipStream_t passed as
+ *     void* (NULL is the default stream).
+ */
+#ifndef NAPSPMV_H
+#define NAPSPMV_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define NAPSPMV_API __attribute__((visibility("default")))
+#else
+#define NAPSPMV_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define NAPSPMV_OK            0
+#define NAPSPMV_EINVAL       (-1)  /* bad argument: invalid CSR, partition, mode, dtype, pointer */
+#define NAPSPMV_ENOMEM       (-2)  /* host or device allocation failed, or device budget exceeded */
+#define NAPSPMV_EHIP         (-3)  /* a HIP runtime call failed */
+#define NAPSPMV_EUNSUPPORTED (-4)  /* valid but outside this build's limits (e.g. nnz >= 2^31) */
+
+/* Modes. */
+#define NAPSPMV_STANDARD 0
+#define NAPSPMV_NAP      1
+
+/* Value types of A.  The input vector v and the result w are float64 for
+ * F64 plans and float32 for F32 and BF16 plans; F32 and BF16 plans
+ * accumulate in float32. */
+#define NAPSPMV_F64  0
+#define NAPSPMV_F32  1
+#define NAPSPMV_BF16 2   /* values passed as raw bfloat16 bit patterns (uint16) */
+
+/* Message phases (section 4.2).  A standard plan reports its inter-node
+ * messages as INTER and its intra-node messages as L2, so "standard
+ * intra-node == NAP fully local" is a field-by-field comparison. */
+#define NAPSPMV_PHASE_INTER 0   /* inter-node: standard off-node messages, or NAP node-to-node */
+#define NAPSPMV_PHASE_L0    1   /* NAP on_node -> off_node: owner to inter-node sender */
+#define NAPSPMV_PHASE_L1    2   /* NAP off_node -> on_node: inter-node receiver to user */
+#define NAPSPMV_PHASE_L2    3   /* on_node -> on_node: direct on-node messages */
+
+/* Plan flags. */
+#define NAPSPMV_HOST_ONLY     0x1u  /* build the plan on the host only (no GPU needed):
+                                       stats and exports work, apply is refused */
+#define NAPSPMV_EXCHANGE_COPY 0x2u  /* NAP: copy the send buffer to a separate receive
+                                       buffer (models the inter-node hop) instead of
+                                       receiving in place */
+
+/* Stages of an apply (napspmv_apply runs EXCHANGE then SPMV). */
+#define NAPSPMV_STAGE_EXCHANGE 0    /* fill the ghost buffer from v */
+#define NAPSPMV_STAGE_SPMV     1    /* w = A_on v + A_off ghost */
+
+typedef struct napspmv_plan_s *napspmv_plan_t;
+
+/* Per-phase message statistics (section 5 reports the per-process maxima).
+ * Element counts are vector values; bytes moved = elems * value_bytes. */
+typedef struct {
+    int64_t msgs;            /* messages in the phase */
+    int64_t elems;           /* vector values carried, summed over messages */
+    int64_t max_msgs_sent;   /* most messages sent by one process */
+    int64_t max_elems_sent;  /* most values sent by one process */
+    int64_t max_msgs_recv;   /* most messages received by one process */
+    int64_t max_elems_recv;  /* most values received by one process */
+    int64_t max_msg_elems;   /* largest single message */
+} napspmv_phase_stats_t;
+
+typedef struct {
+    int64_t n, nnz, n_p, ppn, n_nodes;
+    int32_t mode, dtype;
+    int64_t value_bytes;     /* size of one vector element: 8 (F64) or 4 (F32, BF16) */
+    int64_t nnz_on;          /* stored entries whose column the row's process owns */
+    int64_t nnz_off;         /* stored entries whose column is a ghost */
+    int64_t ghosts;          /* G: sum over processes of their unique ghost columns */
+    napspmv_phase_stats_t phase[4];   /* indexed by NAPSPMV_PHASE_* */
+    int64_t device_bytes;    /* device memory held by the plan (0 for host-only) */
+    double build_seconds;    /* host wall time of the plan build */
+    double upload_seconds;   /* host wall time of the device upload */
+} napspmv_stats_t;
+
+/*
+ * Build a plan for w = A v.
+ *
+ * rowptr[n+1], col[nnz], val[nnz]: A in CSR form on the host; nnz = rowptr[n].
+ *   rowptr[0] must be 0 and rowptr nondecreasing; 0 <= col[k] < n.  Entries
+ *   of a row may come in any order and may repeat a column (repeats are
+ *   summed by the product and counted once by the plan).  A stored entry is
+ *   a nonzero even if its value is 0: the plan depends on the pattern only.
+ *   val holds `dtype` elements (double, float, or uint16 bfloat16 bits); the
+ *   library never rounds values.
+ * n_p, ppn: processes and processes per node; need n_p >= 1, ppn >= 1,
+ *   ppn dividing n_p and n >= n_p.
+ * row_starts: NULL for the even contiguous partition of section 2, rank r
+ *   owning rows [r*floor(n/n_p), (r+1)*floor(n/n_p)) and the last rank also
+ *   the n mod n_p remainder; or n_p+1 strictly increasing boundaries from 0
+ *   to n.
+ * mode: NAPSPMV_STANDARD or NAPSPMV_NAP.  flags: NAPSPMV_* plan flags.
+ * plan_out: receives the plan (set to NULL on failure; nothing leaks).
+ * stats_out: optional (may be NULL).
+ *
+ * Limits: n, nnz and the ghost count must be below 2^31 (EUNSUPPORTED).
+ * Without NAPSPMV_HOST_ONLY the plan copies the split matrix and its index
+ * lists to the current GPU and allocates its ghost, send and receive buffers
+ * there; this call synchronizes with the device.
+ */
+NAPSPMV_API int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *val,
+                        int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
+                        const int64_t *row_starts, uint32_t flags,
+                        napspmv_plan_t *plan_out, napspmv_stats_t *stats_out);
+
+/*
+ * w = A v on the GPU, asynchronously on `stream` (standard_spmv or NAPSpMV,
+ * sections 2.1 and 4.3): fill the ghost buffer from v along the plan's
+ * messages, then the split product.
+ *
+ * v, w: device arrays of n elements (double for F64 plans, float otherwise),
+ *   caller-owned, not overlapping.  No allocation, no host synchronization,
+ *   no host-device copy.  The plan's ghost/send/receive buffers are reused,
+ *   so at most one apply per plan may be in flight at a time (applies on one
+ *   stream are ordered, which suffices).
+ */
+NAPSPMV_API int napspmv_apply(napspmv_plan_t plan, const void *v, void *w, void *stream);
+
+/* One stage of napspmv_apply (NAPSPMV_STAGE_*), for per-stage timing.
+ * STAGE_SPMV reads the ghost buffer the last STAGE_EXCHANGE wrote. */
+NAPSPMV_API int napspmv_apply_stage(napspmv_plan_t plan, int stage, const void *v, void *w,
+                        void *stream);
+
+/* Copy the plan's statistics into *out. */
+NAPSPMV_API int napspmv_plan_stats(napspmv_plan_t plan, napspmv_stats_t *out);
+
+/*
+ * Canonical export of one phase's messages, for bit-exact comparison:
+ * messages sorted by (src, dst), indices ascending by global column inside a
+ * message, one message per (src, dst) pair.  Two-call pattern: pass NULL
+ * arrays to get *n_msgs and *n_idx, then arrays of n_msgs (src, dst),
+ * n_msgs+1 (ptr) and n_idx (idx) elements.
+ */
+NAPSPMV_API int napspmv_plan_export(napspmv_plan_t plan, int phase, int64_t *n_msgs, int64_t *n_idx,
+                        int32_t *src, int32_t *dst, int64_t *ptr, int32_t *idx);
+
+/* The ghost lists gh(t): ghost_ptr[n_p+1] offsets into ghost_col[G], each
+ * list ascending.  Either array may be NULL. */
+NAPSPMV_API int napspmv_plan_ghosts(napspmv_plan_t plan, int64_t *ghost_ptr, int32_t *ghost_col);
+
+/* Diagnostic: copy the device ghost buffer (G elements of the vector type)
+ * into host memory `out`; synchronizes `stream` first. */
+NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, void *out, void *stream);
+
+/* Kernel tuning of the split product: lanes per row (1, 2, 4, 8, 16, 32 or
+ * 64; 0 = pick from the mean row length).  Takes effect on the next apply. */
+NAPSPMV_API int napspmv_plan_set_lanes(napspmv_plan_t plan, int lanes_per_row);
+NAPSPMV_API int napspmv_plan_get_lanes(napspmv_plan_t plan);
+
+/* Release the plan and its device memory.  NULL is accepted.  The caller
+ * must not destroy a plan with an apply in flight. */
+NAPSPMV_API int napspmv_plan_destroy(napspmv_plan_t plan);
+
+/* Process-wide cap on device memory held by all live plans; 0 (the
+ * default) means no cap.  A create that would exceed it fails with
+ * NAPSPMV_ENOMEM before allocating anything. */
+NAPSPMV_API int napspmv_set_device_budget(int64_t bytes);
+NAPSPMV_API int64_t napspmv_device_bytes_in_use(void);
+
+/* Message for the last failed call on this thread ("" if none). */
+NAPSPMV_API const char *napspmv_last_error(void);
+
+/* Interface version (major * 100 + minor). */
+NAPSPMV_API int napspmv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NAPSPMV_H */

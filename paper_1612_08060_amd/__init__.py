@@ -1,0 +1,240 @@
+"""Node-aware parallel SpMV (Bienz, Gropp, Olson, arXiv 1612.08060) on one
+MI355X: Python binding of ``libnapspmv.so``.
+
+This module only marshals arguments to the C ABI declared in
+``include/napspmv.h``; every step of the plan build and of the apply runs in
+the library (host C++ and gfx950 HIP kernels).  PyTorch is used only to pass
+device memory and HIP streams.  If the library is not built, loading fails
+loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Plan", "NapspmvError", "load_library", "LIB_PATH", "MODES", "DTYPES", "PHASES",
+           "STAGE_EXCHANGE", "STAGE_SPMV", "set_device_budget", "device_bytes_in_use"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnapspmv.so")
+MODES = {"standard": 0, "nap": 1}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
+PHASES = ("INTER", "L0", "L1", "L2")
+STAGE_EXCHANGE, STAGE_SPMV = 0, 1
+HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
+_VAL_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}
+_ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
+
+
+class NapspmvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"napspmv {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PhaseStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "msgs", "elems", "max_msgs_sent", "max_elems_sent", "max_msgs_recv",
+        "max_elems_recv", "max_msg_elems")]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_p", ctypes.c_int64),
+                ("ppn", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("mode", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("value_bytes", ctypes.c_int64), ("nnz_on", ctypes.c_int64),
+                ("nnz_off", ctypes.c_int64), ("ghosts", ctypes.c_int64),
+                ("phase", PhaseStats * 4), ("device_bytes", ctypes.c_int64),
+                ("build_seconds", ctypes.c_double), ("upload_seconds", ctypes.c_double)]
+
+
+_lib = None
+P, I64, I32, U32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
+_SIGS = {
+    "napspmv_plan_create": (I32, [P, P, P, I32, I64, I64, I64, I32, P, U32, P, P]),
+    "napspmv_apply": (I32, [P, P, P, P]),
+    "napspmv_apply_stage": (I32, [P, I32, P, P, P]),
+    "napspmv_plan_stats": (I32, [P, P]),
+    "napspmv_plan_export": (I32, [P, I32, P, P, P, P, P, P]),
+    "napspmv_plan_ghosts": (I32, [P, P, P]),
+    "napspmv_plan_read_ghost_values": (I32, [P, P, P]),
+    "napspmv_plan_set_lanes": (I32, [P, I32]),
+    "napspmv_plan_get_lanes": (I32, [P]),
+    "napspmv_plan_destroy": (I32, [P]),
+    "napspmv_set_device_budget": (I32, [I64]),
+    "napspmv_device_bytes_in_use": (I64, []),
+    "napspmv_last_error": (ctypes.c_char_p, []),
+    "napspmv_version": (I32, []),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnapspmv.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(
+                f"{path} is missing: build it first (python -m paper_1612_08060_amd.build "
+                "or __graft_entry__.build()); there is no fallback path")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise NapspmvError(rc, load_library().napspmv_last_error().decode())
+
+
+def set_device_budget(nbytes: int):
+    _check(load_library().napspmv_set_device_budget(int(nbytes)))
+
+
+def device_bytes_in_use() -> int:
+    return int(load_library().napspmv_device_bytes_in_use())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A communication plan plus the split matrix on the GPU.
+
+    ``rowptr`` (int64, n+1), ``col`` (int32) and ``val`` (float64 for "f64",
+    float32 for "f32", uint16 bfloat16 bits for "bf16") describe A in CSR.
+    ``mode`` is "standard" or "nap".  ``host_only`` builds the plan on the
+    host without touching a GPU (stats and exports only).
+    """
+
+    def __init__(self, rowptr, col, val, n: int, n_p: int, ppn: int, mode: str = "standard",
+                 dtype: str = "f64", row_starts=None, host_only: bool = False,
+                 exchange_copy: bool = False):
+        lib = load_library()
+        if mode not in MODES:
+            raise ValueError(f"mode must be one of {list(MODES)}")
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {list(DTYPES)}")
+        self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self._col = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.asarray(val)
+        if v.dtype != _VAL_NP[dtype]:
+            raise TypeError(f"val must be {np.dtype(_VAL_NP[dtype]).name} for dtype {dtype!r} "
+                            "(the library never rounds values)")
+        self._val = np.ascontiguousarray(v)
+        self._starts = None if row_starts is None else np.ascontiguousarray(row_starts, np.int64)
+        self.n, self.n_p, self.ppn, self.mode, self.dtype = int(n), int(n_p), int(ppn), mode, dtype
+        self.host_only = bool(host_only)
+        flags = (HOST_ONLY if host_only else 0) | (EXCHANGE_COPY if exchange_copy else 0)
+        handle = ctypes.c_void_p()
+        st = Stats()
+        self._h = None
+        rc = lib.napspmv_plan_create(
+            self._rowptr.ctypes.data, self._col.ctypes.data, self._val.ctypes.data,
+            DTYPES[dtype], self.n, self.n_p, self.ppn, MODES[mode],
+            None if self._starts is None else self._starts.ctypes.data, flags,
+            ctypes.byref(handle), ctypes.byref(st))
+        _check(rc)
+        self._h = handle
+        # the plan has copied everything it needs
+        self._rowptr = self._col = self._val = None
+
+    # -- plan data -------------------------------------------------------
+    @property
+    def stats(self) -> dict:
+        st = Stats()
+        _check(load_library().napspmv_plan_stats(self._h, ctypes.byref(st)))
+        out = {k: getattr(st, k) for k, _ in Stats._fields_ if k != "phase"}
+        out["mode"] = {v: k for k, v in MODES.items()}[out["mode"]]
+        out["dtype"] = {v: k for k, v in DTYPES.items()}[out["dtype"]]
+        out["phases"] = {PHASES[i]: {k: getattr(st.phase[i], k) for k, _ in PhaseStats._fields_}
+                         for i in range(4)}
+        return out
+
+    def export(self, phase: str):
+        """(src int32, dst int32, ptr int64, idx int32) of a phase, canonical."""
+        lib = load_library()
+        ph = PHASES.index(phase)
+        nm, ni = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.napspmv_plan_export(self._h, ph, ctypes.byref(nm), ctypes.byref(ni),
+                                       None, None, None, None))
+        src = np.empty(nm.value, np.int32)
+        dst = np.empty(nm.value, np.int32)
+        ptr = np.empty(nm.value + 1, np.int64)
+        idx = np.empty(ni.value, np.int32)
+        _check(lib.napspmv_plan_export(self._h, ph, None, None, src.ctypes.data,
+                                       dst.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
+        return src, dst, ptr, idx
+
+    def ghosts(self):
+        """(ghost_ptr int64[n_p+1], ghost_col int32[G])."""
+        gp = np.empty(self.n_p + 1, np.int64)
+        _check(load_library().napspmv_plan_ghosts(self._h, gp.ctypes.data, None))
+        gc = np.empty(int(gp[-1]), np.int32)
+        _check(load_library().napspmv_plan_ghosts(self._h, None, gc.ctypes.data))
+        return gp, gc
+
+    @property
+    def lanes(self) -> int:
+        r = load_library().napspmv_plan_get_lanes(self._h)
+        if r < 0:
+            _check(r)
+        return r
+
+    @lanes.setter
+    def lanes(self, value: int):
+        _check(load_library().napspmv_plan_set_lanes(self._h, int(value)))
+
+    # -- apply -----------------------------------------------------------
+    def _vec_check(self, t, name):
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != want or t.numel() != self.n or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {want} tensor of {self.n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply(self, v, w, stream=None):
+        """w = A v on the GPU (asynchronous on ``stream``, default: current)."""
+        _check(load_library().napspmv_apply(self._h, self._vec_check(v, "v"),
+                                            self._vec_check(w, "w"), _stream_handle(stream)))
+        return w
+
+    def apply_stage(self, stage: int, v, w, stream=None):
+        _check(load_library().napspmv_apply_stage(self._h, int(stage), self._vec_check(v, "v"),
+                                                  self._vec_check(w, "w"),
+                                                  _stream_handle(stream)))
+
+    def read_ghosts(self, stream=None) -> np.ndarray:
+        """The device ghost buffer after the last exchange (synchronizes)."""
+        g = int(self.stats["ghosts"])
+        out = np.empty(g, np.float64 if self.dtype == "f64" else np.float32)
+        _check(load_library().napspmv_plan_read_ghost_values(self._h, out.ctypes.data,
+                                                             _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().napspmv_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

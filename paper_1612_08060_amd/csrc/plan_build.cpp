@@ -1,0 +1,460 @@
+// Host construction of the communication plans.  See plan_build.hpp.
+//
+// Everything is built by sorting and cutting runs, never by sets of sets:
+//  * gh(t), the off-process columns of process t, sorted and unique, is the
+//    union over its rows of the off_process block (section 2).
+//  * Standard messages (section 2.1): since gh(t) is sorted and every owner
+//    holds a contiguous column range, the runs of gh(t) with equal owner r
+//    are exactly D(r, t), and the ghost buffer of t is t's receive buffer in
+//    arrival order.
+//  * E(n, m) (section 4.1): for destination node m, the off-node columns of
+//    gh(t) over the processes t of m, sorted and unique; its runs by source
+//    node are E(n, m) for every n.
+//  * T/U mapping (rule stated after the definitions of T and U): the partners
+//    of node n sorted by (|E(n, m)| descending, m ascending), the k-th sent
+//    by local process k mod ppn; the senders to node n sorted by the same key
+//    (what n sends to each of them, 0 if nothing), the k-th received by local
+//    process ppn - 1 - (k mod ppn).  No partner is split over processes.
+//  * I((p, n), (q, m)) = E(n, m) between the T-process and the U-process.
+//  * on_node -> off_node (L0): the indices of the inter-node messages sent by
+//    s that s does not own, unique per (owner, s).
+//  * off_node -> on_node (L1): every off-node ghost j of t arrives at the
+//    U-process q of its node pair; if q != t, q forwards it to t.
+//  * on_node -> on_node (L2): the runs of gh(t) owned by another process of
+//    t's node (the standard intra-node messages).
+#include "plan_build.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include <omp.h>
+
+#include "napspmv.h"
+
+namespace napspmv {
+namespace {
+
+constexpr int64_t kInt32Max = 0x7fffffff;
+
+struct Owner {
+    const std::vector<int64_t> &starts;
+    int64_t block;     // > 0 for the even partition (fast path)
+    int64_t n_p;
+    int64_t operator()(int64_t j) const {
+        if (block > 0) {
+            int64_t r = j / block;
+            return r < n_p ? r : n_p - 1;
+        }
+        return (std::upper_bound(starts.begin(), starts.end(), j) - starts.begin()) - 1;
+    }
+};
+
+// A message before canonical ordering: `len` indices at `data`.
+struct MsgRef {
+    int32_t src, dst;
+    const int32_t *data;
+    int64_t len;
+};
+
+void finalize_phase(std::vector<MsgRef> &refs, Phase &ph) {
+    std::sort(refs.begin(), refs.end(), [](const MsgRef &a, const MsgRef &b) {
+        return a.src != b.src ? a.src < b.src : a.dst < b.dst;
+    });
+    const size_t m = refs.size();
+    ph.src.resize(m);
+    ph.dst.resize(m);
+    ph.ptr.assign(m + 1, 0);
+    for (size_t k = 0; k < m; ++k) {
+        ph.src[k] = refs[k].src;
+        ph.dst[k] = refs[k].dst;
+        ph.ptr[k + 1] = ph.ptr[k] + refs[k].len;
+    }
+    ph.idx.resize(ph.ptr[m]);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < (int64_t)m; ++k)
+        std::memcpy(ph.idx.data() + ph.ptr[k], refs[k].data, sizeof(int32_t) * refs[k].len);
+}
+
+PhaseStats phase_stats(const Phase &ph, int64_t n_p) {
+    PhaseStats s;
+    const size_t m = ph.src.size();
+    s.msgs = (int64_t)m;
+    s.elems = ph.ptr.back();
+    std::vector<int64_t> ms(n_p, 0), es(n_p, 0), mr(n_p, 0), er(n_p, 0);
+    for (size_t k = 0; k < m; ++k) {
+        int64_t len = ph.ptr[k + 1] - ph.ptr[k];
+        ms[ph.src[k]] += 1;
+        es[ph.src[k]] += len;
+        mr[ph.dst[k]] += 1;
+        er[ph.dst[k]] += len;
+        s.max_msg_elems = std::max(s.max_msg_elems, len);
+    }
+    for (int64_t r = 0; r < n_p; ++r) {
+        s.max_msgs_sent = std::max(s.max_msgs_sent, ms[r]);
+        s.max_elems_sent = std::max(s.max_elems_sent, es[r]);
+        s.max_msgs_recv = std::max(s.max_msgs_recv, mr[r]);
+        s.max_elems_recv = std::max(s.max_elems_recv, er[r]);
+    }
+    return s;
+}
+
+void validate(const int64_t *rowptr, const int32_t *col, const void *val, int dtype, int64_t n,
+              int64_t n_p, int64_t ppn, int mode, const int64_t *row_starts) {
+    if (!rowptr) throw Error(NAPSPMV_EINVAL, "rowptr is NULL");
+    if (dtype != NAPSPMV_F64 && dtype != NAPSPMV_F32 && dtype != NAPSPMV_BF16)
+        throw Error(NAPSPMV_EINVAL, "dtype must be F64, F32 or BF16");
+    if (mode != NAPSPMV_STANDARD && mode != NAPSPMV_NAP)
+        throw Error(NAPSPMV_EINVAL, "mode must be STANDARD or NAP");
+    if (n_p < 1 || ppn < 1) throw Error(NAPSPMV_EINVAL, "need n_p >= 1 and ppn >= 1");
+    if (n_p % ppn != 0) throw Error(NAPSPMV_EINVAL, "ppn must divide n_p");
+    if (n < n_p) throw Error(NAPSPMV_EINVAL, "need n >= n_p (one row per process at least)");
+    if (n > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "n must be below 2^31");
+    if (rowptr[0] != 0) throw Error(NAPSPMV_EINVAL, "rowptr[0] must be 0");
+    bool mono = true;
+#pragma omp parallel for reduction(&& : mono)
+    for (int64_t i = 0; i < n; ++i) mono = mono && rowptr[i + 1] >= rowptr[i];
+    if (!mono) throw Error(NAPSPMV_EINVAL, "rowptr must be nondecreasing");
+    const int64_t nnz = rowptr[n];
+    if (nnz > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "nnz must be below 2^31");
+    if (nnz > 0 && (!col || !val)) throw Error(NAPSPMV_EINVAL, "col or val is NULL");
+    bool inrange = true;
+#pragma omp parallel for reduction(&& : inrange)
+    for (int64_t k = 0; k < nnz; ++k) inrange = inrange && col[k] >= 0 && col[k] < n;
+    if (!inrange) throw Error(NAPSPMV_EINVAL, "column index out of range [0, n)");
+    if (row_starts) {
+        if (row_starts[0] != 0 || row_starts[n_p] != n)
+            throw Error(NAPSPMV_EINVAL, "row_starts must run from 0 to n");
+        for (int64_t r = 0; r < n_p; ++r)
+            if (row_starts[r + 1] <= row_starts[r])
+                throw Error(NAPSPMV_EINVAL, "row_starts must be strictly increasing");
+    }
+}
+
+}  // namespace
+
+void release_device_arrays(HostPlan &hp) {
+    std::vector<int32_t>().swap(hp.rowptr);
+    std::vector<int32_t>().swap(hp.col);
+    std::vector<uint8_t>().swap(hp.val);
+    std::vector<int32_t>().swap(hp.gather_idx);
+    std::vector<int32_t>().swap(hp.pack_idx);
+    std::vector<int32_t>().swap(hp.scat_src);
+    std::vector<int32_t>().swap(hp.scat_dst);
+    std::vector<int32_t>().swap(hp.l2_src);
+    std::vector<int32_t>().swap(hp.l2_dst);
+}
+
+void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
+                int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
+                const int64_t *row_starts) {
+    validate(rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts);
+    hp.n = n;
+    hp.nnz = rowptr[n];
+    hp.n_p = n_p;
+    hp.ppn = ppn;
+    hp.n_nodes = n_p / ppn;
+    hp.mode = mode;
+    hp.dtype = dtype;
+    hp.value_size = dtype == NAPSPMV_F64 ? 8 : dtype == NAPSPMV_F32 ? 4 : 2;
+
+    // Row blocks R(r) (section 2): even partition, remainder on the last rank.
+    hp.starts.resize(n_p + 1);
+    int64_t block = 0;
+    if (row_starts) {
+        std::copy(row_starts, row_starts + n_p + 1, hp.starts.begin());
+    } else {
+        block = n / n_p;
+        for (int64_t r = 0; r < n_p; ++r) hp.starts[r] = block * r;
+        hp.starts[n_p] = n;
+    }
+    const Owner owner{hp.starts, block, n_p};
+    auto node_of = [&](int64_t r) { return r / ppn; };
+
+    // gh(t): sorted unique off-process columns of each process.
+    std::vector<std::vector<int32_t>> gh(n_p);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < n_p; ++t) {
+        const int64_t lo = hp.starts[t], hi = hp.starts[t + 1];
+        std::vector<int32_t> g;
+        g.reserve((size_t)(rowptr[hi] - rowptr[lo]) / 2);
+        for (int64_t k = rowptr[lo]; k < rowptr[hi]; ++k)
+            if (col[k] < lo || col[k] >= hi) g.push_back(col[k]);
+        std::sort(g.begin(), g.end());
+        g.erase(std::unique(g.begin(), g.end()), g.end());
+        gh[t].swap(g);
+    }
+    hp.ghost_ptr.assign(n_p + 1, 0);
+    for (int64_t t = 0; t < n_p; ++t) hp.ghost_ptr[t + 1] = hp.ghost_ptr[t] + (int64_t)gh[t].size();
+    const int64_t G = hp.ghost_ptr[n_p];
+    if (G > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "ghost count must be below 2^31");
+    hp.ghost_col.resize(G);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < n_p; ++t)
+        std::copy(gh[t].begin(), gh[t].end(), hp.ghost_col.begin() + hp.ghost_ptr[t]);
+
+    // Split CSR, on-process entries first in each row, off-process after.
+    const int64_t vs = hp.value_size;
+    hp.rowptr.resize(n + 1);
+    hp.col.resize(hp.nnz);
+    hp.val.resize((size_t)(hp.nnz * vs));
+    const uint8_t *vbytes = static_cast<const uint8_t *>(val);
+    int64_t on_total = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : on_total)
+    for (int64_t t = 0; t < n_p; ++t) {
+        const int64_t lo = hp.starts[t], hi = hp.starts[t + 1];
+        const std::vector<int32_t> &g = gh[t];
+        const int64_t gbase = hp.ghost_ptr[t];
+        for (int64_t i = lo; i < hi; ++i) {
+            hp.rowptr[i] = (int32_t)rowptr[i];
+            int64_t o = rowptr[i];
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                    const int32_t j = col[k];
+                    const bool on = j >= lo && j < hi;
+                    if (on != (pass == 0)) continue;
+                    if (on) {
+                        hp.col[o] = j;
+                        ++on_total;
+                    } else {
+                        const int64_t pos = std::lower_bound(g.begin(), g.end(), j) - g.begin();
+                        hp.col[o] = (int32_t)(0x80000000u | (uint32_t)(gbase + pos));
+                    }
+                    std::memcpy(&hp.val[(size_t)(o * vs)], vbytes + k * vs, (size_t)vs);
+                    ++o;
+                }
+            }
+        }
+    }
+    hp.rowptr[n] = (int32_t)hp.nnz;
+    hp.nnz_on = on_total;
+    hp.nnz_off = hp.nnz - on_total;
+
+    // Runs of gh(t) by owner: the standard messages D(r, t).
+    std::vector<std::vector<MsgRef>> runs(n_p);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < n_p; ++t) {
+        const std::vector<int32_t> &g = gh[t];
+        const int32_t *base = hp.ghost_col.data() + hp.ghost_ptr[t];
+        size_t a = 0;
+        while (a < g.size()) {
+            const int64_t r = owner(g[a]);
+            size_t b = a + 1;
+            while (b < g.size() && g[b] < hp.starts[r + 1]) ++b;
+            runs[t].push_back(MsgRef{(int32_t)r, (int32_t)t, base + a, (int64_t)(b - a)});
+            a = b;
+        }
+    }
+    {
+        std::vector<MsgRef> inter, intra;
+        for (int64_t t = 0; t < n_p; ++t)
+            for (const MsgRef &m : runs[t]) {
+                if (node_of(m.src) == node_of(m.dst))
+                    intra.push_back(m);
+                else if (mode == NAPSPMV_STANDARD)
+                    inter.push_back(m);
+            }
+        if (mode == NAPSPMV_STANDARD) finalize_phase(inter, hp.phase[NAPSPMV_PHASE_INTER]);
+        finalize_phase(intra, hp.phase[NAPSPMV_PHASE_L2]);
+    }
+    std::vector<std::vector<MsgRef>>().swap(runs);
+
+    if (mode == NAPSPMV_STANDARD) {
+        hp.gather_idx = hp.ghost_col;   // the ghost buffer is every receive buffer in order
+    } else {
+        const int64_t nn = hp.n_nodes;
+        // E(., m) for every destination node m: sorted unique off-node ghosts.
+        std::vector<std::vector<int32_t>> Em(nn);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t m = 0; m < nn; ++m) {
+            std::vector<int32_t> e;
+            for (int64_t t = m * ppn; t < (m + 1) * ppn; ++t)
+                for (int32_t j : gh[t])
+                    if (node_of(owner(j)) != m) e.push_back(j);
+            std::sort(e.begin(), e.end());
+            e.erase(std::unique(e.begin(), e.end()), e.end());
+            Em[m].swap(e);
+        }
+        // Node pairs (n -> m) with |E(n, m)|, grouped by destination m, n ascending.
+        struct Pair {
+            int32_t n, m;
+            int64_t start, len;     // range in Em[m]
+            int32_t send_rank, recv_rank;
+            int64_t send_off;       // offset of the message in the send buffer
+        };
+        std::vector<Pair> pairs;
+        std::vector<int64_t> pairs_of_m(nn + 1, 0);
+        for (int64_t m = 0; m < nn; ++m) {
+            const std::vector<int32_t> &e = Em[m];
+            size_t a = 0;
+            while (a < e.size()) {
+                const int64_t src_node = node_of(owner(e[a]));
+                const int64_t end_row = hp.starts[(src_node + 1) * ppn];
+                size_t b = a + 1;
+                while (b < e.size() && e[b] < end_row) ++b;
+                pairs.push_back(Pair{(int32_t)src_node, (int32_t)m, (int64_t)a, (int64_t)(b - a),
+                                     -1, -1, 0});
+                a = b;
+            }
+            pairs_of_m[m + 1] = (int64_t)pairs.size();
+        }
+        const int64_t np_ = (int64_t)pairs.size();
+        // |E(a, b)| lookup through pairs sorted by (n, m).
+        std::vector<int64_t> by_src(np_);
+        std::iota(by_src.begin(), by_src.end(), 0);
+        std::sort(by_src.begin(), by_src.end(), [&](int64_t x, int64_t y) {
+            return pairs[x].n != pairs[y].n ? pairs[x].n < pairs[y].n : pairs[x].m < pairs[y].m;
+        });
+        auto vol = [&](int64_t a, int64_t b) -> int64_t {
+            auto it = std::lower_bound(by_src.begin(), by_src.end(), 0, [&](int64_t x, int) {
+                return pairs[x].n != a ? pairs[x].n < a : pairs[x].m < b;
+            });
+            if (it != by_src.end() && pairs[*it].n == a && pairs[*it].m == b) return pairs[*it].len;
+            return 0;
+        };
+        // T: partners of n by (|E(n, m)| desc, m asc) -> local k mod ppn.
+        std::vector<int64_t> ord(by_src);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+            const Pair &a = pairs[x], &b = pairs[y];
+            if (a.n != b.n) return a.n < b.n;
+            if (a.len != b.len) return a.len > b.len;
+            return a.m < b.m;
+        });
+        for (int64_t k = 0, run = 0; k < np_; ++k) {
+            run = (k > 0 && pairs[ord[k]].n == pairs[ord[k - 1]].n) ? run + 1 : 0;
+            Pair &p = pairs[ord[k]];
+            p.send_rank = (int32_t)(p.n * ppn + run % ppn);
+        }
+        // U: senders of m by (|E(m, n)| desc, n asc) -> local ppn-1-(k mod ppn).
+        std::vector<int64_t> back(np_);
+        for (int64_t x = 0; x < np_; ++x) back[x] = vol(pairs[x].m, pairs[x].n);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+            const Pair &a = pairs[x], &b = pairs[y];
+            if (a.m != b.m) return a.m < b.m;
+            if (back[x] != back[y]) return back[x] > back[y];
+            return a.n < b.n;
+        });
+        for (int64_t k = 0, run = 0; k < np_; ++k) {
+            run = (k > 0 && pairs[ord[k]].m == pairs[ord[k - 1]].m) ? run + 1 : 0;
+            Pair &p = pairs[ord[k]];
+            p.recv_rank = (int32_t)(p.m * ppn + ppn - 1 - run % ppn);
+        }
+        // INTER messages in canonical order define the send buffer layout.
+        std::vector<int64_t> canon(np_);
+        std::iota(canon.begin(), canon.end(), 0);
+        std::sort(canon.begin(), canon.end(), [&](int64_t x, int64_t y) {
+            const Pair &a = pairs[x], &b = pairs[y];
+            return a.send_rank != b.send_rank ? a.send_rank < b.send_rank
+                                              : a.recv_rank < b.recv_rank;
+        });
+        {
+            std::vector<MsgRef> refs(np_);
+            int64_t off = 0;
+            for (int64_t k = 0; k < np_; ++k) {
+                Pair &p = pairs[canon[k]];
+                p.send_off = off;
+                off += p.len;
+                refs[k] = MsgRef{p.send_rank, p.recv_rank, Em[p.m].data() + p.start, p.len};
+            }
+            finalize_phase(refs, hp.phase[NAPSPMV_PHASE_INTER]);
+            hp.pack_idx = hp.phase[NAPSPMV_PHASE_INTER].idx;
+        }
+        // L0: per inter-node sender s, the indices it sends but does not own.
+        {
+            std::vector<std::vector<int64_t>> pairs_of_s(n_p);
+            for (int64_t x = 0; x < np_; ++x) pairs_of_s[pairs[x].send_rank].push_back(x);
+            std::vector<std::vector<int32_t>> l0(n_p);
+            std::vector<std::vector<MsgRef>> l0runs(n_p);
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t s = 0; s < n_p; ++s) {
+                std::vector<int32_t> &d = l0[s];
+                for (int64_t x : pairs_of_s[s]) {
+                    const Pair &p = pairs[x];
+                    for (int64_t a = p.start; a < p.start + p.len; ++a) {
+                        const int32_t j = Em[p.m][a];
+                        if (j < hp.starts[s] || j >= hp.starts[s + 1]) d.push_back(j);
+                    }
+                }
+                std::sort(d.begin(), d.end());
+                d.erase(std::unique(d.begin(), d.end()), d.end());
+                size_t a = 0;
+                while (a < d.size()) {
+                    const int64_t r = owner(d[a]);
+                    size_t b = a + 1;
+                    while (b < d.size() && d[b] < hp.starts[r + 1]) ++b;
+                    l0runs[s].push_back(MsgRef{(int32_t)r, (int32_t)s, d.data() + a, (int64_t)(b - a)});
+                    a = b;
+                }
+            }
+            std::vector<MsgRef> refs;
+            for (int64_t s = 0; s < n_p; ++s) refs.insert(refs.end(), l0runs[s].begin(), l0runs[s].end());
+            finalize_phase(refs, hp.phase[NAPSPMV_PHASE_L0]);
+        }
+        // Per destination t: scatter entries (off-node ghosts), fully local
+        // gathers (on-node ghosts) and the L1 forwards.
+        {
+            std::vector<std::vector<int32_t>> ssrc(n_p), sdst(n_p), lsrc(n_p), ldst(n_p);
+            std::vector<std::vector<int32_t>> l1j(n_p);
+            std::vector<std::vector<MsgRef>> l1runs(n_p);
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t t = 0; t < n_p; ++t) {
+                const int64_t m = node_of(t);
+                const std::vector<int32_t> &g = gh[t];
+                std::vector<std::pair<int32_t, int32_t>> fwd;   // (q, j)
+                for (size_t pos = 0; pos < g.size(); ++pos) {
+                    const int32_t j = g[pos];
+                    const int64_t n_src = node_of(owner(j));
+                    const int32_t slot = (int32_t)(hp.ghost_ptr[t] + (int64_t)pos);
+                    if (n_src == m) {
+                        lsrc[t].push_back(j);
+                        ldst[t].push_back(slot);
+                        continue;
+                    }
+                    // the pair (n_src -> m) among the pairs of m (n ascending)
+                    auto lo = pairs.begin() + pairs_of_m[m], hi = pairs.begin() + pairs_of_m[m + 1];
+                    auto it = std::lower_bound(lo, hi, n_src,
+                                               [](const Pair &p, int64_t v) { return p.n < v; });
+                    const Pair &p = *it;
+                    const int32_t *e = Em[m].data() + p.start;
+                    const int64_t rank = std::lower_bound(e, e + p.len, j) - e;
+                    ssrc[t].push_back((int32_t)(p.send_off + rank));
+                    sdst[t].push_back(slot);
+                    if (p.recv_rank != t) fwd.emplace_back(p.recv_rank, j);
+                }
+                std::stable_sort(fwd.begin(), fwd.end(),
+                                 [](const std::pair<int32_t, int32_t> &a,
+                                    const std::pair<int32_t, int32_t> &b) { return a.first < b.first; });
+                l1j[t].resize(fwd.size());
+                for (size_t k = 0; k < fwd.size(); ++k) l1j[t][k] = fwd[k].second;
+                size_t a = 0;
+                while (a < fwd.size()) {
+                    size_t b = a + 1;
+                    while (b < fwd.size() && fwd[b].first == fwd[a].first) ++b;
+                    l1runs[t].push_back(MsgRef{fwd[a].first, (int32_t)t, l1j[t].data() + a, (int64_t)(b - a)});
+                    a = b;
+                }
+            }
+            std::vector<MsgRef> refs;
+            for (int64_t t = 0; t < n_p; ++t) refs.insert(refs.end(), l1runs[t].begin(), l1runs[t].end());
+            finalize_phase(refs, hp.phase[NAPSPMV_PHASE_L1]);
+            auto flatten = [&](std::vector<std::vector<int32_t>> &parts, std::vector<int32_t> &out) {
+                std::vector<int64_t> off(n_p + 1, 0);
+                for (int64_t t = 0; t < n_p; ++t) off[t + 1] = off[t] + (int64_t)parts[t].size();
+                out.resize(off[n_p]);
+#pragma omp parallel for schedule(dynamic, 16)
+                for (int64_t t = 0; t < n_p; ++t) {
+                    std::copy(parts[t].begin(), parts[t].end(), out.begin() + off[t]);
+                    std::vector<int32_t>().swap(parts[t]);
+                }
+            };
+            flatten(ssrc, hp.scat_src);
+            flatten(sdst, hp.scat_dst);
+            flatten(lsrc, hp.l2_src);
+            flatten(ldst, hp.l2_dst);
+        }
+    }
+    for (int ph = 0; ph < 4; ++ph) hp.stats[ph] = phase_stats(hp.phase[ph], n_p);
+}
+
+}  // namespace napspmv

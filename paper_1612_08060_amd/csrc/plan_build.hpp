@@ -1,0 +1,70 @@
+// Host-side construction of standard and node-aware communication plans.
+//
+// Section 2 (row blocks, ranks as (local, node) pairs), section 2.1 (the
+// standard messages P(r), D(r, t)) and section 4 (node sets N, E; the T/U
+// mapping; inter-node messages G, I; the three local steps) of Bienz, Gropp,
+// Olson, "Node aware sparse matrix-vector multiplication".
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace napspmv {
+
+// Error raised by the builder; `code` is a NAPSPMV_E* value.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &msg) : std::runtime_error(msg), code(c) {}
+};
+
+// One phase in canonical order: messages sorted by (src, dst), indices of a
+// message ascending, message k's indices are idx[ptr[k] .. ptr[k+1]).
+struct Phase {
+    std::vector<int32_t> src, dst;
+    std::vector<int64_t> ptr{0};
+    std::vector<int32_t> idx;
+};
+
+struct PhaseStats {
+    int64_t msgs = 0, elems = 0, max_msgs_sent = 0, max_elems_sent = 0;
+    int64_t max_msgs_recv = 0, max_elems_recv = 0, max_msg_elems = 0;
+};
+
+struct HostPlan {
+    int64_t n = 0, nnz = 0, n_p = 0, ppn = 0, n_nodes = 0;
+    int mode = 0, dtype = 0;
+    int64_t value_size = 8;            // bytes of one stored value of A
+    std::vector<int64_t> starts;       // row block boundaries, n_p + 1
+    std::vector<int64_t> ghost_ptr;    // n_p + 1
+    std::vector<int32_t> ghost_col;    // G, each process's list ascending
+    int64_t nnz_on = 0, nnz_off = 0;
+
+    // Split CSR as the device reads it.  Each row holds its on-process
+    // entries (stored order), then its off-process entries (stored order).
+    // col >= 0 is a column of v; col < 0 encodes ghost position
+    // (col & 0x7fffffff) in the concatenated ghost buffer.
+    std::vector<int32_t> rowptr;       // n + 1
+    std::vector<int32_t> col;          // nnz
+    std::vector<uint8_t> val;          // nnz * value_size
+
+    Phase phase[4];                    // INTER, L0, L1, L2
+    PhaseStats stats[4];
+
+    // Device index lists.
+    std::vector<int32_t> gather_idx;              // standard: ghost[k] = v[gather_idx[k]]
+    std::vector<int32_t> pack_idx;                // NAP: send[k] = v[pack_idx[k]]
+    std::vector<int32_t> scat_src, scat_dst;      // NAP: ghost[scat_dst[k]] = recv[scat_src[k]]
+    std::vector<int32_t> l2_src, l2_dst;          // NAP: ghost[l2_dst[k]] = v[l2_src[k]]
+};
+
+// Validates the inputs and builds the plan.  Throws Error or std::bad_alloc.
+void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
+                int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
+                const int64_t *row_starts);
+
+// Frees the host copies of the split matrix and device lists (after upload).
+void release_device_arrays(HostPlan &hp);
+
+}  // namespace napspmv

@@ -1,0 +1,205 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+its host plan builder (NAPSPMV_HOST_ONLY plans, no GPU needed) matches the
+oracle bit for bit: every phase's messages and indices, the ghost lists, the
+on/off split counts and all statistics."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1612_08060_amd as lib
+from oracle import plan_ref, plan_vec
+from tests.helpers import arrays_to_triples, example_2_1, triples
+from workloads import CSR, bf16_bits, config, kkt_like, random_pattern
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "napspmv.h")
+
+
+def test_library_exports_every_declared_symbol():
+    decl = re.findall(r"NAPSPMV_API[^;]*?\b(napspmv_\w+)\s*\(", open(HEADER).read(), re.S)
+    assert len(decl) >= 14
+    so = lib.load_library()
+    for name in decl:
+        assert hasattr(so, name), name
+    assert so.napspmv_version() == 100
+
+
+def _host_plan(a, n_p, ppn, mode, row_starts=None, dtype="f64"):
+    val = {"f64": a.val, "f32": a.val.astype(np.float32), "bf16": bf16_bits(a.val)}[dtype]
+    return lib.Plan(a.rowptr, a.col, val, a.n, n_p, ppn, mode=mode, dtype=dtype,
+                    row_starts=row_starts, host_only=True)
+
+
+def _compare(a, n_p, ppn, mode, row_starts=None, dtype="f64"):
+    ref = plan_vec.plan(a, n_p, ppn, mode, row_starts)
+    with _host_plan(a, n_p, ppn, mode, row_starts, dtype) as p:
+        for ph in lib.PHASES:
+            got = p.export(ph)
+            exp = ref["phases"][ph]
+            for g, e in zip(got, exp):
+                assert np.array_equal(g, e), (ph, mode)
+        st = p.stats
+        for ph in lib.PHASES:
+            assert st["phases"][ph] == plan_vec.phase_stats(ref["phases"][ph], n_p), ph
+        gp, gc = p.ghosts()
+        assert np.array_equal(gc, ref["ghost_j"])
+        assert np.array_equal(np.diff(gp), np.bincount(ref["ghost_t"], minlength=n_p))
+        rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+        on = plan_vec.owner(ref["starts"], rows) == plan_vec.owner(ref["starts"], a.col)
+        assert st["nnz_on"] == int(on.sum()) and st["nnz_off"] == int((~on).sum())
+        assert st["ghosts"] == ref["ghost_t"].size
+        assert st["n_nodes"] == n_p // ppn and st["mode"] == mode
+        assert st["value_bytes"] == (8 if dtype == "f64" else 4)
+        assert st["device_bytes"] == 0
+    return st
+
+
+@pytest.mark.parametrize("mode", ["standard", "nap"])
+def test_example_2_1(mode):
+    g, a = example_2_1()
+    with _host_plan(a, 6, 2, mode) as p:
+        lit = plan_ref.plan(a, plan_ref.Layout(6, 6, 2), mode)
+        for ph in lib.PHASES:
+            assert arrays_to_triples(p.export(ph)) == triples(lit["phases"][ph])
+    if mode == "nap":
+        with _host_plan(a, 6, 2, mode) as p:
+            assert arrays_to_triples(p.export("INTER")) == triples(g["corrected"]["I"]["value"])
+
+
+@pytest.mark.parametrize("n_p,ppn", [(1, 1), (2, 1), (2, 2), (3, 1), (4, 2), (6, 3), (6, 2),
+                                     (8, 4), (8, 2), (8, 8), (12, 3), (16, 4)])
+@pytest.mark.parametrize("mode", ["standard", "nap"])
+def test_random_patterns(n_p, ppn, mode):
+    for seed in range(3):
+        n = 3 * n_p + 11 * seed + 5
+        a = random_pattern(n, 0.1 + 0.05 * seed, seed=seed + 17 * n_p,
+                           empty_rows=seed, duplicates=2 * seed)
+        _compare(a, n_p, ppn, mode)
+
+
+def test_many_partner_nodes():
+    """More partner nodes than processes per node: round-robin assignment."""
+    a = random_pattern(240, 0.05, seed=4)
+    for mode in ("standard", "nap"):
+        _compare(a, 48, 2, mode)
+        _compare(a, 48, 4, mode)
+
+
+def test_explicit_row_starts_and_remainder():
+    a = random_pattern(101, 0.06, seed=8, duplicates=5)
+    starts = np.array([0, 1, 7, 30, 31, 60, 77, 90, 101], np.int64)
+    for mode in ("standard", "nap"):
+        _compare(a, 8, 4, mode, starts)
+        _compare(a, 8, 2, mode)                     # 101 = 8*12 + 5 remainder rows
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_dtypes_share_the_plan(dtype):
+    a = kkt_like(1 << 12, 9)
+    _compare(a, 32, 8, "nap", dtype=dtype)
+
+
+@pytest.mark.parametrize("k,scale", [(1, 0), (2, 0), (3, 4), (4, 2)])
+@pytest.mark.parametrize("mode", ["standard", "nap"])
+def test_paper_shaped_configs(k, scale, mode):
+    wl = config(k, scale=scale)
+    _compare(wl.csr, wl.n_p, wl.ppn, mode, wl.row_starts)
+
+
+def test_laplace3d_closed_form_stats():
+    wl = config(2)
+    st = _host_plan(wl.csr, wl.n_p, wl.ppn, "nap").stats
+    ph = st["phases"]
+    assert (ph["INTER"]["msgs"], ph["INTER"]["elems"]) == (126, 2064384)
+    assert (ph["L0"]["msgs"], ph["L0"]["elems"]) == (945, 1935360)
+    assert (ph["L1"]["msgs"], ph["L1"]["elems"]) == (945, 1935360)
+    assert (ph["L2"]["msgs"], ph["L2"]["elems"]) == (2816, 2326528)
+    assert st["ghosts"] == 4390912 and st["nnz_off"] == 4390912
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mode", ["standard", "nap"])
+def test_kkt_like_full_size(mode, kkt_full):
+    a, n_p, ppn = kkt_full
+    _compare(a, n_p, ppn, mode)
+
+
+@pytest.fixture(scope="module")
+def kkt_full():
+    wl = config(3)
+    return wl.csr, wl.n_p, wl.ppn
+
+
+# -- argument validation -----------------------------------------------------
+
+def _tiny():
+    return random_pattern(10, 0.3, seed=1)
+
+
+def _expect(code, **kw):
+    a = _tiny()
+    args = dict(rowptr=a.rowptr, col=a.col, val=a.val, n=a.n, n_p=2, ppn=1,
+                mode="standard", host_only=True)
+    args.update(kw)
+    with pytest.raises(lib.NapspmvError) as e:
+        lib.Plan(**args)
+    assert e.value.code == code
+
+
+def test_invalid_arguments():
+    a = _tiny()
+    bad = a.rowptr.copy()
+    bad[0] = 1
+    _expect(-1, rowptr=bad)
+    bad = a.rowptr.copy()
+    bad[3], bad[4] = bad[4] + 1, bad[3]
+    _expect(-1, rowptr=bad)
+    bad = a.col.copy()
+    bad[0] = 10
+    _expect(-1, col=bad)
+    bad[0] = -1
+    _expect(-1, col=bad)
+    _expect(-1, n_p=3, ppn=2)                 # ppn must divide n_p
+    _expect(-1, n_p=11, ppn=1)                # more processes than rows
+    _expect(-1, n_p=0, ppn=1)
+    _expect(-1, row_starts=np.array([0, 0, 10], np.int64))
+    _expect(-1, row_starts=np.array([0, 5, 9], np.int64))
+    with pytest.raises(ValueError):
+        lib.Plan(a.rowptr, a.col, a.val, a.n, 2, 1, mode="bogus", host_only=True)
+    with pytest.raises(TypeError):
+        lib.Plan(a.rowptr, a.col, a.val.astype(np.float32), a.n, 2, 1, dtype="f64",
+                 host_only=True)
+
+
+def test_host_only_plan_refuses_apply():
+    a = _tiny()
+    p = lib.Plan(a.rowptr, a.col, a.val, a.n, 2, 1, host_only=True)
+    so = lib.load_library()
+    rc = so.napspmv_apply(p._h, 1, 2, None)
+    assert rc == -1 and b"HOST_ONLY" in so.napspmv_last_error()
+    assert so.napspmv_apply(None, 1, 2, None) == -1
+    p.close()
+    assert so.napspmv_plan_destroy(None) == 0
+
+
+def test_lanes_setting():
+    a = kkt_like(1 << 10, 2)
+    p = lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, host_only=True)
+    assert p.lanes == 16                       # about two entries per lane at ~31 per row
+    p.lanes = 4
+    assert p.lanes == 4
+    with pytest.raises(lib.NapspmvError):
+        p.lanes = 3
+    p.lanes = 0
+    assert p.lanes == 16
+
+
+def test_duplicates_and_stored_zeros_are_structure():
+    a = random_pattern(40, 0.1, seed=3, duplicates=9)
+    z = CSR(a.n, a.rowptr, a.col, np.zeros_like(a.val))
+    for mode in ("standard", "nap"):
+        s1 = _compare(a, 8, 2, mode)
+        s2 = _compare(z, 8, 2, mode)
+        assert s1["phases"] == s2["phases"]
