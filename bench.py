@@ -9,9 +9,14 @@ stderr.
 
 value = algorithmic bytes of one apply / time per apply (GB/s).  The bytes
 count every array element the method must touch once:
-  product:  nnz*(s_a + 4) + (N+1)*4 + N*s_v (v) + G*s_v (ghosts) + N*s_v (w)
-  gather:   G*(4 + 2*s_v)                      (standard mode)
+  product:  nnz*(s_a + 4) + 2*(N+1)*4 (two row pointers) + N*s_v (v)
+            + G*s_v (ghosts) + N*s_v (w)
+  gather:   G*(4 + 2*s_v)                                  (standard mode)
   NAP:      E*(4 + 2*s_v) + H*(8 + 2*s_v) + G_on*(8 + 2*s_v)  (+2*E*s_v if copied)
+An apply is two launches (LOCAL: exchange gather with the on-process product;
+REMOTE: [NAP scatter and] the off-process product); each launch's bytes for
+the roofline count what that launch must touch, the REMOTE launch reading and
+rewriting the partial w of the rows that have off-process entries.
 """
 from __future__ import annotations
 
@@ -34,7 +39,7 @@ def log(*a):
 
 def spmv_bytes(st, s_a, s_v):
     n, nnz, g = st["n"], st["nnz"], st["ghosts"]
-    return nnz * (s_a + 4) + (n + 1) * 4 + n * s_v + g * s_v + n * s_v
+    return nnz * (s_a + 4) + 2 * (n + 1) * 4 + n * s_v + g * s_v + n * s_v
 
 
 def exchange_bytes(st, s_v, exchange_copy=False):
@@ -46,6 +51,29 @@ def exchange_bytes(st, s_v, exchange_copy=False):
     h = st["ghosts"] - g_on
     b = e * (4 + 2 * s_v) + h * (8 + 2 * s_v) + g_on * (8 + 2 * s_v)
     return b + (2 * e * s_v if exchange_copy else 0)
+
+
+def launch_bytes(st, s_a, s_v, rows_off):
+    """Algorithmic bytes of the LOCAL and REMOTE launches of a standard apply."""
+    n, g = st["n"], st["ghosts"]
+    local = (st["ghosts"] * (4 + 2 * s_v) + st["nnz_on"] * (s_a + 4) + (n + 1) * 4
+             + n * s_v + n * s_v)
+    remote = st["nnz_off"] * (s_a + 4) + (n + 1) * 4 + g * s_v + 2 * rows_off * s_v
+    return local, remote
+
+
+def rows_with_off_entries(a, n_p, row_starts):
+    import numpy as np
+    if row_starts is None:
+        b = a.n // n_p
+        starts = np.arange(n_p + 1, dtype=np.int64) * b
+        starts[-1] = a.n
+    else:
+        starts = np.asarray(row_starts, np.int64)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    own_r = np.searchsorted(starts, rows, side="right")
+    own_c = np.searchsorted(starts, a.col, side="right")
+    return int(np.unique(rows[own_r != own_c]).size)
 
 
 def source_hash() -> str:
@@ -70,8 +98,8 @@ def measured_traffic(name: str, launch_bytes: float):
 
 
 def time_apply(plan, v, w, steps, warmup, torch, nap):
-    """Warm up, then time exactly `steps` applies; events bracket each stage
-    on the stream the kernels run on."""
+    """Warm up, then time exactly `steps` applies; events bracket each of the
+    two launches on the stream they run on."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         plan.apply(v, w, stream=stream)
@@ -80,15 +108,15 @@ def time_apply(plan, v, w, steps, warmup, torch, nap):
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
-        plan.apply_stage(nap.STAGE_EXCHANGE, v, w, stream=stream)
+        plan.apply_stage(nap.STAGE_LOCAL, v, w, stream=stream)
         ev[k][1].record(stream)
-        plan.apply_stage(nap.STAGE_SPMV, v, w, stream=stream)
+        plan.apply_stage(nap.STAGE_REMOTE, v, w, stream=stream)
         ev[k][2].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    exch = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
-    spmv = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
-    return (t1 - t0) * 1e3 / steps, sum(exch) / steps, sum(spmv) / steps
+    local = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    remote = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+    return (t1 - t0) * 1e3 / steps, sum(local) / steps, sum(remote) / steps
 
 
 def cpu_baseline(wl, budget_s):
@@ -120,7 +148,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--block-nnz", type=int, default=-1)
+    ap.add_argument("--window", type=int, default=-1)
+    ap.add_argument("--bands", type=int, default=-1)
     ap.add_argument("--extras", type=int, default=1, help="also time NAP mode and reduced precision")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -146,22 +176,25 @@ def main():
     t = time.perf_counter()
     plan = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="standard", dtype="f64",
                     row_starts=wl.row_starts)
-    if args.lanes:
-        plan.lanes = args.lanes
+    tuning = {"block_nnz": args.block_nnz, "window": args.window, "bands": args.bands}
+    for k, x in tuning.items():
+        plan.set_param(k, x)
+    tuning = {k: plan.get_param(k) for k in tuning}
     st = plan.stats
     log(f"standard plan: build {st['build_seconds']:.2f}s upload {st['upload_seconds']:.2f}s "
-        f"lanes {plan.lanes}")
+        f"tuning {tuning}")
     v = torch.from_numpy(wl.v).to(dev)
     w = torch.empty_like(v)
 
-    ms, exch_ms, spmv_ms = time_apply(plan, v, w, args.steps, args.warmup, torch, nap)
-    s_bytes = spmv_bytes(st, 8, 8)
-    x_bytes = exchange_bytes(st, 8)
-    total = s_bytes + x_bytes
-    log(f"apply {ms:.4f} ms  (exchange {exch_ms:.4f} ms, product {spmv_ms:.4f} ms)")
-
-    achieved = s_bytes / (spmv_ms * 1e-3) / 1e9
-    traffic = measured_traffic("spmv_kkt_f64", s_bytes)
+    ms, local_ms, remote_ms = time_apply(plan, v, w, args.steps, args.warmup, torch, nap)
+    total = spmv_bytes(st, 8, 8) + exchange_bytes(st, 8)
+    rows_off = rows_with_off_entries(a, wl.n_p, wl.row_starts)
+    lb, rb = launch_bytes(st, 8, 8, rows_off)
+    log(f"apply {ms:.4f} ms  (local {local_ms:.4f} ms, remote {remote_ms:.4f} ms)")
+    dom = "k_local" if local_ms >= remote_ms else "k_remote"
+    dom_ms, dom_bytes = (local_ms, lb) if dom == "k_local" else (remote_ms, rb)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(f"{dom}_kkt_f64", dom_bytes)
     result = {
         "metric": "SpMV GB/s vs HBM peak (split SpMV + ghost gather)",
         "value": round(total / (ms * 1e-3) / 1e9, 2),
@@ -174,15 +207,17 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n": a.n, "nnz": a.nnz, "n_p": wl.n_p, "ppn": wl.ppn,
-                   "mode": "standard", "bytes_per_step": total},
+                   "mode": "standard", "bytes_per_step": total, "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "kernel": "k_spmv",
-                     "kernel_ms": round(spmv_ms, 5), "kernel_bytes": s_bytes},
+                     "traffic": traffic, "kernel": dom,
+                     "kernel_ms": round(dom_ms, 5), "kernel_bytes": dom_bytes},
         "frac_of_hbm_peak": round(total / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         "gflops": round(2 * a.nnz / (ms * 1e-3) / 1e9, 1),
-        "exchange": {"ms": round(exch_ms, 5), "bytes": x_bytes,
-                     "gbs": round(x_bytes / (exch_ms * 1e-3) / 1e9, 1)},
+        "launches": {"k_local": {"ms": round(local_ms, 5), "bytes": lb,
+                                 "gbs": round(lb / (local_ms * 1e-3) / 1e9, 1)},
+                     "k_remote": {"ms": round(remote_ms, 5), "bytes": rb,
+                                  "gbs": round(rb / (remote_ms * 1e-3) / 1e9, 1)}},
         "plan_build_s": {"standard": round(st["build_seconds"], 3)},
     }
     plan.close()
@@ -198,7 +233,7 @@ def main():
         bn = spmv_bytes(sn, 8, 8) + exchange_bytes(sn, 8)
         torch.cuda.synchronize()
         ext["nap_f64"] = {"ms": round(ms_n, 5), "gbs": round(bn / (ms_n * 1e-3) / 1e9, 1),
-                          "exchange_ms": round(ex_n, 5),
+                          "local_ms": round(ex_n, 5), "remote_ms": round(sp_n, 5),
                           "bitwise_equal_to_standard": bool(torch.equal(w, w2))}
         result["plan_build_s"]["nap"] = round(sn["build_seconds"], 3)
         sph, nph = st["phases"], sn["phases"]

@@ -24,7 +24,10 @@
  * Both modes fill the same ghost buffer (each process's ghosts in ascending
  * column order) and run the same split product
  *     w_i = sum_on a_ij v_j + sum_off a_ij ghost_t(j),
- * so their results are bitwise identical.
+ * so their results are bitwise identical.  Each row is summed as algorithm
+ * standard_spmv does: sequentially from 0, its on-process entries in stored
+ * order, then its off-process entries in stored order, one rounded product
+ * and one rounded add per entry.
  *
  * Conventions for every call:
  *   - Return 0 (NAPSPMV_OK) on success or a negative NAPSPMV_E* code; nothing
@@ -83,9 +86,14 @@ extern "C" {
                                        buffer (models the inter-node hop) instead of
                                        receiving in place */
 
-/* Stages of an apply (napspmv_apply runs EXCHANGE then SPMV). */
-#define NAPSPMV_STAGE_EXCHANGE 0    /* fill the ghost buffer from v */
-#define NAPSPMV_STAGE_SPMV     1    /* w = A_on v + A_off ghost */
+/* Stages of an apply; napspmv_apply runs LOCAL then REMOTE.  LOCAL is one
+ * launch: the exchange gather (standard: every ghost from its owner; NAP:
+ * the inter-node send buffer) overlapped with the on-process product
+ * w = A_on v.  REMOTE: for NAP the inter-node hop and the scatter of received
+ * and fully local values into the ghost buffer, then (both modes) the
+ * off-process product w += A_off ghost. */
+#define NAPSPMV_STAGE_LOCAL  0
+#define NAPSPMV_STAGE_REMOTE 1
 
 typedef struct napspmv_plan_s *napspmv_plan_t;
 
@@ -134,7 +142,7 @@ typedef struct {
  * plan_out: receives the plan (set to NULL on failure; nothing leaks).
  * stats_out: optional (may be NULL).
  *
- * Limits: n, nnz and the ghost count must be below 2^31 (EUNSUPPORTED).
+ * Limits: n, nnz and the ghost count must be below 2^31 - 2^16 (EUNSUPPORTED).
  * Without NAPSPMV_HOST_ONLY the plan copies the split matrix and its index
  * lists to the current GPU and allocates its ghost, send and receive buffers
  * there; this call synchronizes with the device.
@@ -183,10 +191,25 @@ NAPSPMV_API int napspmv_plan_ghosts(napspmv_plan_t plan, int64_t *ghost_ptr, int
  * into host memory `out`; synchronizes `stream` first. */
 NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, void *out, void *stream);
 
-/* Kernel tuning of the split product: lanes per row (1, 2, 4, 8, 16, 32 or
- * 64; 0 = pick from the mean row length).  Takes effect on the next apply. */
-NAPSPMV_API int napspmv_plan_set_lanes(napspmv_plan_t plan, int lanes_per_row);
-NAPSPMV_API int napspmv_plan_get_lanes(napspmv_plan_t plan);
+/* Tuning parameters of the apply kernels (NAPSPMV_PARAM_*); -1 restores the
+ * automatic value.  No parameter changes any result bit.  Setting one on a
+ * device plan rebuilds and re-uploads the launch schedules (it allocates and
+ * synchronizes the device): do not call it while an apply of the plan is in
+ * flight.
+ *   BLOCK_NNZ     entries per row block of both products: 1024, 2048, 4096
+ *                 (automatic: 4096)
+ *   GATHER_BANDS  standard exchange: column bands of v that order the ghost
+ *                 gather, 1..4096 (automatic: about 2 MiB of v per band)
+ *   VWINDOW       on-process product: most elements of v a row block stages
+ *                 in LDS, 0 (none), 1024, 2048, 4096 (automatic: 1024)
+
+ * get_param returns the value in effect, or a negative error code. */
+#define NAPSPMV_PARAM_BLOCK_NNZ    0
+#define NAPSPMV_PARAM_GATHER_BANDS 1
+#define NAPSPMV_PARAM_VWINDOW      2
+
+NAPSPMV_API int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value);
+NAPSPMV_API int napspmv_plan_get_param(napspmv_plan_t plan, int param);
 
 /* Release the plan and its device memory.  NULL is accepted.  The caller
  * must not destroy a plan with an apply in flight. */

@@ -1,6 +1,13 @@
-"""Float64 CSR SpMV of the oracle: the C routine ``spmv_ref_f64`` (sequential
-row sums in stored order, no fused multiply-add) and a row-by-row Python
-evaluation for sampled rows.  Test infrastructure (see the package docstring).
+"""Float64 CSR SpMV of the oracle.  Test infrastructure (see the package
+docstring).
+
+spmv        the definition w = A v: each row summed sequentially in stored
+            order, no fused multiply-add (C routine spmv_ref_f64).
+spmv_split  the same product in the order algorithm standard_spmv of section
+            2.1 forms it on each process: local_spmv(A_on_process, v), then
+            local_spmv(A_off_process, b_recv) accumulated into w (C routine
+            spmv_split_ref_f64).
+*_rows      the same sums for sampled rows, in Python float64 arithmetic.
 """
 from __future__ import annotations
 
@@ -33,6 +40,9 @@ def _load():
         lib = ctypes.CDLL(LIB_PATH)
         lib.spmv_ref_f64.restype = None
         lib.spmv_ref_f64.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 5 + [ctypes.c_int]
+        lib.spmv_split_ref_f64.restype = None
+        lib.spmv_split_ref_f64.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 5
+                                           + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int])
         lib.spmv_ref_threads.restype = ctypes.c_int
         lib.spmv_ref_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -54,6 +64,50 @@ def spmv(csr, v, threads: int = 0, out=None) -> np.ndarray:
     lib.spmv_ref_f64(csr.n, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
                      x.ctypes.data, w.ctypes.data, int(threads))
     return w
+
+
+def block_starts(n: int, n_p: int, row_starts=None) -> np.ndarray:
+    """Row block boundaries: the even contiguous partition of section 2 with
+    the remainder rows on the last process, unless given explicitly."""
+    if row_starts is not None:
+        return np.ascontiguousarray(row_starts, dtype=np.int64)
+    b = n // n_p
+    s = np.arange(n_p + 1, dtype=np.int64) * b
+    s[-1] = n
+    return s
+
+
+def spmv_split(csr, v, n_p: int, row_starts=None, threads: int = 0, out=None) -> np.ndarray:
+    """w = A v summed as standard_spmv does on every process: the
+    on-process block first, then the off-process block, each in stored
+    order (C routine spmv_split_ref_f64)."""
+    lib = _load()
+    rp = np.ascontiguousarray(csr.rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(csr.col, dtype=np.int32)
+    val = np.ascontiguousarray(csr.val, dtype=np.float64)
+    x = np.ascontiguousarray(v, dtype=np.float64)
+    st = block_starts(csr.n, n_p, row_starts)
+    w = np.empty(csr.n, dtype=np.float64) if out is None else out
+    lib.spmv_split_ref_f64(csr.n, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                           x.ctypes.data, w.ctypes.data, int(n_p), st.ctypes.data, int(threads))
+    return w
+
+
+def spmv_split_rows(csr, v, n_p: int, rows, row_starts=None) -> np.ndarray:
+    """spmv_split for selected rows only, in Python float64 arithmetic."""
+    st = block_starts(csr.n, n_p, row_starts)
+    out = np.empty(len(rows))
+    for o, i in enumerate(rows):
+        r = int(np.searchsorted(st, i, side="right") - 1)
+        lo, hi = int(st[r]), int(st[r + 1])
+        ks = range(int(csr.rowptr[i]), int(csr.rowptr[i + 1]))
+        on = [k for k in ks if lo <= int(csr.col[k]) < hi]
+        off = [k for k in ks if not lo <= int(csr.col[k]) < hi]
+        s = 0.0
+        for k in on + off:
+            s = s + float(csr.val[k]) * float(v[int(csr.col[k])])
+        out[o] = s
+    return out
 
 
 def spmv_rows(csr, v, rows) -> np.ndarray:

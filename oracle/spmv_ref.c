@@ -28,6 +28,40 @@ void spmv_ref_f64(int64_t n, const int64_t *rowptr, const int32_t *col,
     }
 }
 
+/*
+ * The same product as algorithm standard_spmv of section 2.1 computes it on
+ * every process r: local_spmv(A_on_process, v) into w, then
+ * local_spmv(A_off_process, b_recv) accumulated into w.  Row i of block r
+ * (rows [starts[r], starts[r+1])) adds, sequentially from 0, first the
+ * products of its stored entries whose column lies in the same block, in
+ * stored order, then the products of the other entries, in stored order.
+ * b_recv holds copies of v, so the received value of column j is v[j].
+ */
+void spmv_split_ref_f64(int64_t n, const int64_t *rowptr, const int32_t *col,
+                        const double *val, const double *v, double *w,
+                        int64_t n_p, const int64_t *starts, int threads)
+{
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n_p; ++r) {
+        const int64_t lo = starts[r], hi = starts[r + 1];
+        for (int64_t i = lo; i < hi; ++i) {
+            double s = 0.0;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                if (col[k] < lo || col[k] >= hi) continue;
+                double prod = val[k] * v[col[k]];
+                s = s + prod;
+            }
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                if (col[k] >= lo && col[k] < hi) continue;
+                double prod = val[k] * v[col[k]];
+                s = s + prod;
+            }
+            w[i] = s;
+        }
+    }
+}
+
 /* Number of threads an OpenMP parallel region actually uses. */
 int spmv_ref_threads(int threads)
 {

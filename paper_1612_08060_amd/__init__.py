@@ -15,14 +15,15 @@ import os
 import numpy as np
 
 __all__ = ["Plan", "NapspmvError", "load_library", "LIB_PATH", "MODES", "DTYPES", "PHASES",
-           "STAGE_EXCHANGE", "STAGE_SPMV", "set_device_budget", "device_bytes_in_use"]
+           "STAGE_LOCAL", "STAGE_REMOTE", "set_device_budget", "device_bytes_in_use"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnapspmv.so")
 MODES = {"standard": 0, "nap": 1}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 PHASES = ("INTER", "L0", "L1", "L2")
-STAGE_EXCHANGE, STAGE_SPMV = 0, 1
+STAGE_LOCAL, STAGE_REMOTE = 0, 1
 HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
+PARAMS = {"block_nnz": 0, "bands": 1, "window": 2}
 _VAL_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
 
@@ -59,8 +60,8 @@ _SIGS = {
     "napspmv_plan_export": (I32, [P, I32, P, P, P, P, P, P]),
     "napspmv_plan_ghosts": (I32, [P, P, P]),
     "napspmv_plan_read_ghost_values": (I32, [P, P, P]),
-    "napspmv_plan_set_lanes": (I32, [P, I32]),
-    "napspmv_plan_get_lanes": (I32, [P]),
+    "napspmv_plan_set_param": (I32, [P, I32, I32]),
+    "napspmv_plan_get_param": (I32, [P, I32]),
     "napspmv_plan_destroy": (I32, [P]),
     "napspmv_set_device_budget": (I32, [I64]),
     "napspmv_device_bytes_in_use": (I64, []),
@@ -182,16 +183,15 @@ class Plan:
         _check(load_library().napspmv_plan_ghosts(self._h, None, gc.ctypes.data))
         return gp, gc
 
-    @property
-    def lanes(self) -> int:
-        r = load_library().napspmv_plan_get_lanes(self._h)
+    def set_param(self, name: str, value: int):
+        """Tuning parameter (a key of PARAMS); -1 = automatic."""
+        _check(load_library().napspmv_plan_set_param(self._h, PARAMS[name], int(value)))
+
+    def get_param(self, name: str) -> int:
+        r = load_library().napspmv_plan_get_param(self._h, PARAMS[name])
         if r < 0:
             _check(r)
         return r
-
-    @lanes.setter
-    def lanes(self, value: int):
-        _check(load_library().napspmv_plan_set_lanes(self._h, int(value)))
 
     # -- apply -----------------------------------------------------------
     def _vec_check(self, t, name):

@@ -1,5 +1,5 @@
 // The C ABI of include/napspmv.h: plan creation (host builder + device
-// upload), the apply path (exchange kernels + split product) and the
+// upload), the apply path (exchange kernels + split product), tuning and
 // diagnostics.  Nothing here throws across the interface.
 #include <hip/hip_runtime.h>
 
@@ -13,24 +13,38 @@
 #include "kernels.hpp"
 #include "napspmv.h"
 #include "plan_build.hpp"
+#include "schedule.hpp"
 
 using napspmv::Error;
 using napspmv::HostPlan;
+
+namespace {
+constexpr int kMaxItem = 4096;          // gather work item length
+constexpr int kMaxRowsPerBlock = napspmv::kMaxRows;  // rows of a product block
+}  // namespace
 
 struct napspmv_plan_s {
     HostPlan hp;
     uint32_t flags = 0;
     bool on_device = false;
     int device = 0;
-    int lanes = 0;           // lanes per row of the product (0 = auto)
-    int auto_lanes = 8;
+    // tuning (-1 = automatic)
+    int block_nnz = -1, bands = -1, window = -1;
+    int auto_block_nnz = 4096, auto_bands = 1, auto_window = 1024;
+    int cur_block_nnz = 0, cur_bands = 0, cur_window = -1;   // schedules on the device
     int64_t G = 0, E = 0, H = 0, Gon = 0;
-    int32_t *d_rowptr = nullptr, *d_col = nullptr;
-    void *d_val = nullptr;
+    int64_t n_on_blocks = 0, n_off_blocks = 0, n_items = 0, n_tasks = 0;
+    int32_t *d_rp_on = nullptr, *d_col_on = nullptr, *d_rp_off = nullptr, *d_col_off = nullptr;
+    void *d_val_on = nullptr, *d_val_off = nullptr;
     void *d_ghost = nullptr;
     int32_t *d_gather = nullptr, *d_pack = nullptr;
     void *d_send = nullptr, *d_recv = nullptr;
     int32_t *d_ssrc = nullptr, *d_sdst = nullptr, *d_lsrc = nullptr, *d_ldst = nullptr;
+    // schedules: on-process row blocks + windows, off-process row blocks,
+    // exchange items, the merged task list of the first launch
+    int32_t *d_onblk = nullptr, *d_onptr = nullptr, *d_win = nullptr;
+    int32_t *d_offblk = nullptr, *d_offptr = nullptr, *d_items = nullptr, *d_tasks = nullptr;
+    int64_t bytes_sched = 0;
     int64_t device_bytes = 0;
     double build_s = 0, upload_s = 0;
 };
@@ -69,10 +83,10 @@ struct DeviceGuard {
 
 int64_t vec_bytes(int dtype) { return dtype == NAPSPMV_F64 ? 8 : 4; }
 
-int pick_lanes(double mean_row) {
-    int l = 1;
-    while (l < 64 && 2 * l < mean_row) l *= 2;   // about two entries per lane
-    return l;
+// Column bands of the standard gather: about 2 MiB of v per band.
+int pick_bands(int64_t n, int64_t vb) {
+    const int64_t b = (n * vb + (2 << 20) - 1) / (2 << 20);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(64, b));
 }
 
 template <typename T>
@@ -90,12 +104,35 @@ void alloc(void *&dst, int64_t bytes, int64_t &total) {
     total += bytes;
 }
 
+void free_ptr(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+void charge(napspmv_plan_s *p, int64_t bytes) {
+    p->device_bytes += bytes;
+    g_in_use += bytes;
+}
+
+void free_schedules(napspmv_plan_s *p) {
+    void *ptrs[] = {p->d_onblk, p->d_onptr, p->d_win, p->d_offblk, p->d_offptr, p->d_items,
+                    p->d_tasks};
+    for (void *q : ptrs) free_ptr(q);
+    p->d_onblk = p->d_onptr = p->d_win = p->d_offblk = p->d_offptr = nullptr;
+    p->d_items = p->d_tasks = nullptr;
+    charge(p, -p->bytes_sched);
+    p->bytes_sched = 0;
+}
+
 void free_device(napspmv_plan_s *p) {
-    void *ptrs[] = {p->d_rowptr, p->d_col, p->d_val, p->d_ghost, p->d_gather, p->d_pack,
-                    p->d_send, p->d_recv == p->d_send ? nullptr : p->d_recv,
+    free_schedules(p);
+    void *ptrs[] = {p->d_rp_on, p->d_col_on, p->d_rp_off, p->d_col_off, p->d_val_on,
+                    p->d_val_off, p->d_ghost, p->d_gather, p->d_pack, p->d_send,
+                    p->d_recv == p->d_send ? nullptr : p->d_recv,
                     p->d_ssrc, p->d_sdst, p->d_lsrc, p->d_ldst};
-    for (void *q : ptrs)
-        if (q) (void)hipFree(q);
+    for (void *q : ptrs) free_ptr(q);
+    p->d_rp_on = p->d_col_on = p->d_rp_off = p->d_col_off = nullptr;
+    p->d_val_on = p->d_val_off = p->d_ghost = p->d_send = p->d_recv = nullptr;
+    p->d_gather = p->d_pack = p->d_ssrc = p->d_sdst = p->d_lsrc = p->d_ldst = nullptr;
     g_in_use -= p->device_bytes;
     p->device_bytes = 0;
     p->on_device = false;
@@ -103,7 +140,8 @@ void free_device(napspmv_plan_s *p) {
 
 int64_t planned_device_bytes(const HostPlan &hp, uint32_t flags) {
     const int64_t vb = vec_bytes(hp.dtype);
-    int64_t b = (int64_t)(hp.rowptr.size() + hp.col.size()) * 4 + (int64_t)hp.val.size();
+    int64_t b = (int64_t)(hp.rowptr_on.size() + hp.col_on.size() + hp.rowptr_off.size() +
+                          hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
     b += (int64_t)hp.ghost_col.size() * vb;
     b += (int64_t)(hp.gather_idx.size() + hp.pack_idx.size() + hp.scat_src.size() +
                    hp.scat_dst.size() + hp.l2_src.size() + hp.l2_dst.size()) * 4;
@@ -112,9 +150,56 @@ int64_t planned_device_bytes(const HostPlan &hp, uint32_t flags) {
     return b;
 }
 
+// (Re)build every launch schedule for the current tuning: on-process row
+// blocks with their v windows, off-process row blocks, the exchange items
+// (standard: ghost gather by column band; NAP: pack in order) and the task
+// list of the first launch.
+void refresh_schedules(napspmv_plan_s *p) {
+    const int cap = p->block_nnz >= 0 ? p->block_nnz : p->auto_block_nnz;
+    const int win = p->window >= 0 ? p->window : p->auto_window;
+    const int bands = p->bands >= 0 ? p->bands : p->auto_bands;
+    if (p->d_onblk && cap == p->cur_block_nnz && win == p->cur_window && bands == p->cur_bands)
+        return;
+    const HostPlan &hp = p->hp;
+    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks;
+    napspmv::row_blocks(hp.rowptr_on.data(), hp.n, cap, kMaxRowsPerBlock, onblk, onptr);
+    if (win > 0) napspmv::row_block_windows(onblk, hp.on_lo, hp.on_hi, hp.n, win, wins);
+    napspmv::row_blocks(hp.rowptr_off.data(), hp.n, cap, kMaxRowsPerBlock, offblk, offptr);
+    if (hp.mode == NAPSPMV_STANDARD)
+        napspmv::gather_items(hp.ghost_ptr, hp.ghost_col, hp.n, bands, kMaxItem, items);
+    else
+        napspmv::flat_items(p->E, kMaxItem, items);
+    napspmv::merge_tasks((int64_t)items.size() / 2, (int64_t)onblk.size() - 1, tasks);
+    free_schedules(p);
+    int64_t total = 0;
+    try {
+        upload(p->d_onblk, onblk, total);
+        upload(p->d_onptr, onptr, total);
+        upload(p->d_win, wins, total);
+        upload(p->d_offblk, offblk, total);
+        upload(p->d_offptr, offptr, total);
+        upload(p->d_items, items, total);
+        upload(p->d_tasks, tasks, total);
+    } catch (...) {
+        p->bytes_sched = total;
+        charge(p, total);
+        throw;
+    }
+    p->bytes_sched = total;
+    charge(p, total);
+    p->n_on_blocks = (int64_t)onblk.size() - 1;
+    p->n_off_blocks = (int64_t)offblk.size() - 1;
+    p->n_items = (int64_t)items.size() / 2;
+    p->n_tasks = (int64_t)tasks.size();
+    p->cur_block_nnz = cap;
+    p->cur_window = win;
+    p->cur_bands = bands;
+}
+
 void to_device(napspmv_plan_s *p) {
     HostPlan &hp = p->hp;
     HIP_OK(hipGetDevice(&p->device));
+
     const int64_t need = planned_device_bytes(hp, p->flags);
     const int64_t budget = g_budget.load();
     if (budget > 0 && g_in_use.load() + need > budget)
@@ -124,13 +209,18 @@ void to_device(napspmv_plan_s *p) {
     int64_t total = 0;
     try {
         const int64_t vb = vec_bytes(hp.dtype);
-        upload(p->d_rowptr, hp.rowptr, total);
-        upload(p->d_col, hp.col, total);
-        if (!hp.val.empty()) {
-            HIP_OK(hipMalloc(&p->d_val, hp.val.size()));
-            total += (int64_t)hp.val.size();
-            HIP_OK(hipMemcpy(p->d_val, hp.val.data(), hp.val.size(), hipMemcpyHostToDevice));
-        }
+        upload(p->d_rp_on, hp.rowptr_on, total);
+        upload(p->d_col_on, hp.col_on, total);
+        upload(p->d_rp_off, hp.rowptr_off, total);
+        upload(p->d_col_off, hp.col_off, total);
+        auto upload_bytes = [&](void *&dst, const std::vector<uint8_t> &src) {
+            if (src.empty()) return;
+            HIP_OK(hipMalloc(&dst, src.size()));
+            total += (int64_t)src.size();
+            HIP_OK(hipMemcpy(dst, src.data(), src.size(), hipMemcpyHostToDevice));
+        };
+        upload_bytes(p->d_val_on, hp.val_on);
+        upload_bytes(p->d_val_off, hp.val_off);
         alloc(p->d_ghost, p->G * vb, total);
         upload(p->d_gather, hp.gather_idx, total);
         upload(p->d_pack, hp.pack_idx, total);
@@ -145,89 +235,96 @@ void to_device(napspmv_plan_s *p) {
             else
                 p->d_recv = p->d_send;          // receive in place: the exchange is an alias
         }
+        charge(p, total);
+        total = 0;
+        refresh_schedules(p);
         HIP_OK(hipDeviceSynchronize());
     } catch (...) {
-        p->device_bytes = total;
-        g_in_use += total;
+        charge(p, total);
         free_device(p);
         throw;
     }
-    p->device_bytes = total;
-    g_in_use += total;
     p->on_device = true;
 }
 
 inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + napspmv::kBlock - 1) / napspmv::kBlock); }
 
-template <typename XT>
-void launch_exchange(napspmv_plan_s *p, const XT *v, hipStream_t s) {
-    using namespace napspmv;
-    if (p->hp.mode == NAPSPMV_STANDARD) {
-        if (p->G > 0)
-            k_gather<XT><<<blocks_for(p->G), kBlock, 0, s>>>((int32_t)p->G, p->d_gather, v,
-                                                           static_cast<XT *>(p->d_ghost));
-        return;
-    }
-    // NAP: pack the inter-node messages straight from the owners' values
-    // (the on_node -> off_node step and the pack of the inter-node send
-    // buffer in one gather), hop to the receive buffer, then scatter the
-    // received values to every user on the destination node together with
-    // the fully local on-node values.
-    if (p->E > 0)
-        k_gather<XT><<<blocks_for(p->E), kBlock, 0, s>>>((int32_t)p->E, p->d_pack, v,
-                                                       static_cast<XT *>(p->d_send));
-    if (p->E > 0 && p->d_recv != p->d_send)
-        k_copy<XT><<<blocks_for(p->E), kBlock, 0, s>>>((int32_t)p->E,
-                                                     static_cast<const XT *>(p->d_send),
-                                                     static_cast<XT *>(p->d_recv));
-    const uint32_t nb1 = blocks_for(p->H), nb2 = blocks_for(p->Gon);
-    if (nb1 + nb2 > 0)
-        k_scatter2<XT><<<nb1 + nb2, kBlock, 0, s>>>(
-            (int32_t)p->H, p->d_ssrc, p->d_sdst, static_cast<const XT *>(p->d_recv),
-            (int32_t)p->Gon, p->d_lsrc, p->d_ldst, v, static_cast<XT *>(p->d_ghost), nb1);
+template <typename VT, typename XT, int CAP, int W>
+void launch_local_w(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
+    const bool std_mode = p->hp.mode == NAPSPMV_STANDARD;
+    XT *xdst = static_cast<XT *>(std_mode ? p->d_ghost : p->d_send);
+    const int32_t *idx = std_mode ? p->d_gather : p->d_pack;
+    napspmv::k_local<VT, XT, CAP, W><<<(uint32_t)p->n_tasks, napspmv::kBlock, 0, s>>>(
+        p->d_tasks, reinterpret_cast<const int2 *>(p->d_items), idx, xdst, p->d_onblk,
+        p->d_onptr, reinterpret_cast<const int2 *>(p->d_win), p->d_rp_on, p->d_col_on,
+        static_cast<const VT *>(p->d_val_on), v, w);
 }
 
-template <typename VT, typename XT, int S>
-void launch_spmv_s(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
-    constexpr int rows = napspmv::kBlock / S;
-    const int64_t n = p->hp.n;
-    const uint32_t nb = (uint32_t)((n + rows - 1) / rows);
-    napspmv::k_spmv<VT, XT, S><<<nb, napspmv::kBlock, 0, s>>>(
-        (int32_t)n, p->d_rowptr, p->d_col, static_cast<const VT *>(p->d_val), v,
-        static_cast<const XT *>(p->d_ghost), w);
+template <typename VT, typename XT, int CAP>
+void launch_local(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
+    switch (p->cur_window) {
+        case 1024: launch_local_w<VT, XT, CAP, 1024>(p, v, w, s); break;
+        case 2048: launch_local_w<VT, XT, CAP, 2048>(p, v, w, s); break;
+        case 4096: launch_local_w<VT, XT, CAP, 4096>(p, v, w, s); break;
+        default: launch_local_w<VT, XT, CAP, 0>(p, v, w, s); break;
+    }
+}
+
+template <typename VT, typename XT, int CAP>
+void launch_remote(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
+    using namespace napspmv;
+    if (p->hp.mode == NAPSPMV_NAP) {
+        // the inter-node hop (alias unless copied), then the scatter of the
+        // received values to every user on the node, with the fully local
+        // on-node values
+        if (p->E > 0 && p->d_recv != p->d_send)
+            k_copy<XT><<<blocks_for(p->E), kBlock, 0, s>>>((int32_t)p->E,
+                                                         static_cast<const XT *>(p->d_send),
+                                                         static_cast<XT *>(p->d_recv));
+        const uint32_t nb1 = blocks_for(p->H), nb2 = blocks_for(p->Gon);
+        if (nb1 + nb2 > 0)
+            k_scatter2<XT><<<nb1 + nb2, kBlock, 0, s>>>(
+                (int32_t)p->H, p->d_ssrc, p->d_sdst, static_cast<const XT *>(p->d_recv),
+                (int32_t)p->Gon, p->d_lsrc, p->d_ldst, v, static_cast<XT *>(p->d_ghost), nb1);
+    }
+    if (p->hp.nnz_off > 0)
+        k_remote<VT, XT, CAP><<<(uint32_t)p->n_off_blocks, kBlock, 0, s>>>(
+            p->d_offblk, p->d_offptr, p->d_rp_off, p->d_col_off,
+            static_cast<const VT *>(p->d_val_off), static_cast<const XT *>(p->d_ghost), w);
 }
 
 template <typename VT, typename XT>
-void launch_spmv(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
-    switch (p->lanes ? p->lanes : p->auto_lanes) {
-        case 1: launch_spmv_s<VT, XT, 1>(p, v, w, s); break;
-        case 2: launch_spmv_s<VT, XT, 2>(p, v, w, s); break;
-        case 4: launch_spmv_s<VT, XT, 4>(p, v, w, s); break;
-        case 8: launch_spmv_s<VT, XT, 8>(p, v, w, s); break;
-        case 16: launch_spmv_s<VT, XT, 16>(p, v, w, s); break;
-        case 32: launch_spmv_s<VT, XT, 32>(p, v, w, s); break;
-        default: launch_spmv_s<VT, XT, 64>(p, v, w, s); break;
+void launch_stage(napspmv_plan_s *p, int stage, const XT *v, XT *w, hipStream_t s) {
+    switch (p->cur_block_nnz) {
+        case 1024:
+            stage == NAPSPMV_STAGE_LOCAL ? launch_local<VT, XT, 1024>(p, v, w, s)
+                                         : launch_remote<VT, XT, 1024>(p, v, w, s);
+            break;
+        case 4096:
+            stage == NAPSPMV_STAGE_LOCAL ? launch_local<VT, XT, 4096>(p, v, w, s)
+                                         : launch_remote<VT, XT, 4096>(p, v, w, s);
+            break;
+        default:
+            stage == NAPSPMV_STAGE_LOCAL ? launch_local<VT, XT, 2048>(p, v, w, s)
+                                         : launch_remote<VT, XT, 2048>(p, v, w, s);
+            break;
     }
 }
 
 void run_stage(napspmv_plan_s *p, int stage, const void *v, void *w, hipStream_t s) {
-    if (stage == NAPSPMV_STAGE_EXCHANGE) {
-        if (p->hp.dtype == NAPSPMV_F64)
-            launch_exchange<double>(p, static_cast<const double *>(v), s);
-        else
-            launch_exchange<float>(p, static_cast<const float *>(v), s);
-    } else {
-        switch (p->hp.dtype) {
-            case NAPSPMV_F64:
-                launch_spmv<double, double>(p, static_cast<const double *>(v), static_cast<double *>(w), s);
-                break;
-            case NAPSPMV_F32:
-                launch_spmv<float, float>(p, static_cast<const float *>(v), static_cast<float *>(w), s);
-                break;
-            default:
-                launch_spmv<uint16_t, float>(p, static_cast<const float *>(v), static_cast<float *>(w), s);
-                break;
-        }
+    switch (p->hp.dtype) {
+        case NAPSPMV_F64:
+            launch_stage<double, double>(p, stage, static_cast<const double *>(v),
+                                         static_cast<double *>(w), s);
+            break;
+        case NAPSPMV_F32:
+            launch_stage<float, float>(p, stage, static_cast<const float *>(v),
+                                       static_cast<float *>(w), s);
+            break;
+        default:
+            launch_stage<uint16_t, float>(p, stage, static_cast<const float *>(v),
+                                          static_cast<float *>(w), s);
+            break;
     }
     HIP_OK(hipGetLastError());
 }
@@ -267,6 +364,19 @@ void fill_stats(const napspmv_plan_s *p, napspmv_stats_t *s) {
     s->upload_seconds = p->upload_s;
 }
 
+template <typename F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(NAPSPMV_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(NAPSPMV_EINVAL, e.what());
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -279,7 +389,7 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
     if (flags & ~(NAPSPMV_HOST_ONLY | NAPSPMV_EXCHANGE_COPY))
         return fail(NAPSPMV_EINVAL, "unknown flag bits");
     napspmv_plan_s *p = nullptr;
-    try {
+    const int rc = guarded([&]() {
         p = new napspmv_plan_s();
         p->flags = flags;
         const auto t0 = std::chrono::steady_clock::now();
@@ -290,7 +400,7 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         p->E = (int64_t)p->hp.pack_idx.size();
         p->H = (int64_t)p->hp.scat_src.size();
         p->Gon = (int64_t)p->hp.l2_src.size();
-        p->auto_lanes = pick_lanes(n > 0 ? (double)p->hp.nnz / (double)n : 0.0);
+        p->auto_bands = pick_bands(n, vec_bytes(dtype));
         if (!(flags & NAPSPMV_HOST_ONLY)) {
             to_device(p);
             napspmv::release_device_arrays(p->hp);
@@ -300,43 +410,32 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         *plan_out = p;
         g_last_error.clear();
         return NAPSPMV_OK;
-    } catch (const Error &e) {
-        delete p;
-        return fail(e.code, e.what());
-    } catch (const std::bad_alloc &) {
-        delete p;
-        return fail(NAPSPMV_ENOMEM, "host allocation failed");
-    } catch (const std::exception &e) {
-        delete p;
-        return fail(NAPSPMV_EINVAL, e.what());
-    }
+    });
+    if (rc != NAPSPMV_OK) delete p;
+    return rc;
 }
 
 int napspmv_apply_stage(napspmv_plan_t plan, int stage, const void *v, void *w, void *stream) {
     int rc = check_apply(plan, v, w);
     if (rc) return rc;
-    if (stage != NAPSPMV_STAGE_EXCHANGE && stage != NAPSPMV_STAGE_SPMV)
+    if (stage != NAPSPMV_STAGE_LOCAL && stage != NAPSPMV_STAGE_REMOTE)
         return fail(NAPSPMV_EINVAL, "unknown stage");
-    try {
+    return guarded([&]() {
         DeviceGuard g(plan->device);
         run_stage(plan, stage, v, w, static_cast<hipStream_t>(stream));
         return NAPSPMV_OK;
-    } catch (const Error &e) {
-        return fail(e.code, e.what());
-    }
+    });
 }
 
 int napspmv_apply(napspmv_plan_t plan, const void *v, void *w, void *stream) {
     int rc = check_apply(plan, v, w);
     if (rc) return rc;
-    try {
+    return guarded([&]() {
         DeviceGuard g(plan->device);
-        run_stage(plan, NAPSPMV_STAGE_EXCHANGE, v, w, static_cast<hipStream_t>(stream));
-        run_stage(plan, NAPSPMV_STAGE_SPMV, v, w, static_cast<hipStream_t>(stream));
+        run_stage(plan, NAPSPMV_STAGE_LOCAL, v, w, static_cast<hipStream_t>(stream));
+        run_stage(plan, NAPSPMV_STAGE_REMOTE, v, w, static_cast<hipStream_t>(stream));
         return NAPSPMV_OK;
-    } catch (const Error &e) {
-        return fail(e.code, e.what());
-    }
+    });
 }
 
 int napspmv_plan_stats(napspmv_plan_t plan, napspmv_stats_t *out) {
@@ -369,29 +468,55 @@ int napspmv_plan_ghosts(napspmv_plan_t plan, int64_t *ghost_ptr, int32_t *ghost_
 int napspmv_plan_read_ghost_values(napspmv_plan_t plan, void *out, void *stream) {
     if (!plan || !out) return fail(NAPSPMV_EINVAL, "plan or out is NULL");
     if (!plan->on_device) return fail(NAPSPMV_EINVAL, "plan was built with NAPSPMV_HOST_ONLY");
-    try {
+    return guarded([&]() {
         DeviceGuard g(plan->device);
         HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
         if (plan->G > 0)
             HIP_OK(hipMemcpy(out, plan->d_ghost, (size_t)(plan->G * vec_bytes(plan->hp.dtype)),
                              hipMemcpyDeviceToHost));
         return NAPSPMV_OK;
-    } catch (const Error &e) {
-        return fail(e.code, e.what());
+    });
+}
+
+int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value) {
+    if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
+    switch (param) {
+        case NAPSPMV_PARAM_BLOCK_NNZ:
+            if (value != -1 && value != 1024 && value != 2048 && value != 4096)
+                return fail(NAPSPMV_EINVAL, "block entries must be -1, 1024, 2048 or 4096");
+            plan->block_nnz = value;
+            break;
+        case NAPSPMV_PARAM_GATHER_BANDS:
+            if (value != -1 && (value < 1 || value > 4096))
+                return fail(NAPSPMV_EINVAL, "bands must be -1 or in [1, 4096]");
+            plan->bands = value;
+            break;
+        case NAPSPMV_PARAM_VWINDOW:
+            if (value != -1 && value != 0 && value != 1024 && value != 2048 && value != 4096)
+                return fail(NAPSPMV_EINVAL, "window must be -1, 0, 1024, 2048 or 4096");
+            plan->window = value;
+            break;
+        default:
+            return fail(NAPSPMV_EINVAL, "unknown parameter");
     }
+    if (!plan->on_device) return NAPSPMV_OK;
+    return guarded([&]() {
+        DeviceGuard g(plan->device);
+        HIP_OK(hipDeviceSynchronize());
+        refresh_schedules(plan);
+        HIP_OK(hipDeviceSynchronize());
+        return NAPSPMV_OK;
+    });
 }
 
-int napspmv_plan_set_lanes(napspmv_plan_t plan, int lanes) {
+int napspmv_plan_get_param(napspmv_plan_t plan, int param) {
     if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
-    if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))))
-        return fail(NAPSPMV_EINVAL, "lanes per row must be 0 or a power of two up to 64");
-    plan->lanes = lanes;
-    return NAPSPMV_OK;
-}
-
-int napspmv_plan_get_lanes(napspmv_plan_t plan) {
-    if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
-    return plan->lanes ? plan->lanes : plan->auto_lanes;
+    switch (param) {
+        case NAPSPMV_PARAM_BLOCK_NNZ: return plan->block_nnz >= 0 ? plan->block_nnz : plan->auto_block_nnz;
+        case NAPSPMV_PARAM_GATHER_BANDS: return plan->bands >= 0 ? plan->bands : plan->auto_bands;
+        case NAPSPMV_PARAM_VWINDOW: return plan->window >= 0 ? plan->window : plan->auto_window;
+        default: return fail(NAPSPMV_EINVAL, "unknown parameter");
+    }
 }
 
 int napspmv_plan_destroy(napspmv_plan_t plan) {

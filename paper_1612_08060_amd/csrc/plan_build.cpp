@@ -35,7 +35,9 @@
 namespace napspmv {
 namespace {
 
-constexpr int64_t kInt32Max = 0x7fffffff;
+// Sizes stay below 2^31 - 2^16 so that every 32-bit index a kernel forms
+// (an index plus at most one block's worth of work) is representable.
+constexpr int64_t kInt32Max = 0x7fffffff - 0x10000;
 
 struct Owner {
     const std::vector<int64_t> &starts;
@@ -109,14 +111,14 @@ void validate(const int64_t *rowptr, const int32_t *col, const void *val, int dt
     if (n_p < 1 || ppn < 1) throw Error(NAPSPMV_EINVAL, "need n_p >= 1 and ppn >= 1");
     if (n_p % ppn != 0) throw Error(NAPSPMV_EINVAL, "ppn must divide n_p");
     if (n < n_p) throw Error(NAPSPMV_EINVAL, "need n >= n_p (one row per process at least)");
-    if (n > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "n must be below 2^31");
+    if (n > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "n must be below 2^31 - 2^16");
     if (rowptr[0] != 0) throw Error(NAPSPMV_EINVAL, "rowptr[0] must be 0");
     bool mono = true;
 #pragma omp parallel for reduction(&& : mono)
     for (int64_t i = 0; i < n; ++i) mono = mono && rowptr[i + 1] >= rowptr[i];
     if (!mono) throw Error(NAPSPMV_EINVAL, "rowptr must be nondecreasing");
     const int64_t nnz = rowptr[n];
-    if (nnz > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "nnz must be below 2^31");
+    if (nnz > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "nnz must be below 2^31 - 2^16");
     if (nnz > 0 && (!col || !val)) throw Error(NAPSPMV_EINVAL, "col or val is NULL");
     bool inrange = true;
 #pragma omp parallel for reduction(&& : inrange)
@@ -134,9 +136,10 @@ void validate(const int64_t *rowptr, const int32_t *col, const void *val, int dt
 }  // namespace
 
 void release_device_arrays(HostPlan &hp) {
-    std::vector<int32_t>().swap(hp.rowptr);
-    std::vector<int32_t>().swap(hp.col);
-    std::vector<uint8_t>().swap(hp.val);
+    std::vector<int32_t>().swap(hp.col_on);
+    std::vector<int32_t>().swap(hp.col_off);
+    std::vector<uint8_t>().swap(hp.val_on);
+    std::vector<uint8_t>().swap(hp.val_off);
     std::vector<int32_t>().swap(hp.gather_idx);
     std::vector<int32_t>().swap(hp.pack_idx);
     std::vector<int32_t>().swap(hp.scat_src);
@@ -187,48 +190,68 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
     hp.ghost_ptr.assign(n_p + 1, 0);
     for (int64_t t = 0; t < n_p; ++t) hp.ghost_ptr[t + 1] = hp.ghost_ptr[t] + (int64_t)gh[t].size();
     const int64_t G = hp.ghost_ptr[n_p];
-    if (G > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "ghost count must be below 2^31");
+    if (G > kInt32Max) throw Error(NAPSPMV_EUNSUPPORTED, "ghost count must be below 2^31 - 2^16");
     hp.ghost_col.resize(G);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < n_p; ++t)
         std::copy(gh[t].begin(), gh[t].end(), hp.ghost_col.begin() + hp.ghost_ptr[t]);
 
-    // Split CSR, on-process entries first in each row, off-process after.
+    // Split CSR: the on-process and off-process entries of every row, each in
+    // stored order; off-process columns become ghost positions.
     const int64_t vs = hp.value_size;
-    hp.rowptr.resize(n + 1);
-    hp.col.resize(hp.nnz);
-    hp.val.resize((size_t)(hp.nnz * vs));
     const uint8_t *vbytes = static_cast<const uint8_t *>(val);
-    int64_t on_total = 0;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : on_total)
+    hp.rowptr_on.assign(n + 1, 0);
+    hp.rowptr_off.assign(n + 1, 0);
+    hp.on_lo.assign(n, 0x7fffffff);
+    hp.on_hi.assign(n, -1);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < n_p; ++t) {
+        const int64_t lo = hp.starts[t], hi = hp.starts[t + 1];
+        for (int64_t i = lo; i < hi; ++i) {
+            int32_t on = 0;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                if (col[k] >= lo && col[k] < hi) {
+                    ++on;
+                    hp.on_lo[i] = std::min(hp.on_lo[i], col[k]);
+                    hp.on_hi[i] = std::max(hp.on_hi[i], col[k]);
+                }
+            }
+            hp.rowptr_on[i + 1] = on;
+            hp.rowptr_off[i + 1] = (int32_t)(rowptr[i + 1] - rowptr[i]) - on;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        hp.rowptr_on[i + 1] += hp.rowptr_on[i];
+        hp.rowptr_off[i + 1] += hp.rowptr_off[i];
+    }
+    hp.nnz_on = hp.rowptr_on[n];
+    hp.nnz_off = hp.rowptr_off[n];
+    hp.col_on.resize(hp.nnz_on);
+    hp.col_off.resize(hp.nnz_off);
+    hp.val_on.resize((size_t)(hp.nnz_on * vs));
+    hp.val_off.resize((size_t)(hp.nnz_off * vs));
+#pragma omp parallel for schedule(dynamic, 4)
     for (int64_t t = 0; t < n_p; ++t) {
         const int64_t lo = hp.starts[t], hi = hp.starts[t + 1];
         const std::vector<int32_t> &g = gh[t];
         const int64_t gbase = hp.ghost_ptr[t];
         for (int64_t i = lo; i < hi; ++i) {
-            hp.rowptr[i] = (int32_t)rowptr[i];
-            int64_t o = rowptr[i];
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-                    const int32_t j = col[k];
-                    const bool on = j >= lo && j < hi;
-                    if (on != (pass == 0)) continue;
-                    if (on) {
-                        hp.col[o] = j;
-                        ++on_total;
-                    } else {
-                        const int64_t pos = std::lower_bound(g.begin(), g.end(), j) - g.begin();
-                        hp.col[o] = (int32_t)(0x80000000u | (uint32_t)(gbase + pos));
-                    }
-                    std::memcpy(&hp.val[(size_t)(o * vs)], vbytes + k * vs, (size_t)vs);
-                    ++o;
+            int64_t a = hp.rowptr_on[i], b = hp.rowptr_off[i];
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int32_t j = col[k];
+                if (j >= lo && j < hi) {
+                    hp.col_on[a] = j;
+                    std::memcpy(&hp.val_on[(size_t)(a * vs)], vbytes + k * vs, (size_t)vs);
+                    ++a;
+                } else {
+                    const int64_t pos = std::lower_bound(g.begin(), g.end(), j) - g.begin();
+                    hp.col_off[b] = (int32_t)(gbase + pos);
+                    std::memcpy(&hp.val_off[(size_t)(b * vs)], vbytes + k * vs, (size_t)vs);
+                    ++b;
                 }
             }
         }
     }
-    hp.rowptr[n] = (int32_t)hp.nnz;
-    hp.nnz_on = on_total;
-    hp.nnz_off = hp.nnz - on_total;
 
     // Runs of gh(t) by owner: the standard messages D(r, t).
     std::vector<std::vector<MsgRef>> runs(n_p);

@@ -41,13 +41,17 @@ struct HostPlan {
     std::vector<int32_t> ghost_col;    // G, each process's list ascending
     int64_t nnz_on = 0, nnz_off = 0;
 
-    // Split CSR as the device reads it.  Each row holds its on-process
-    // entries (stored order), then its off-process entries (stored order).
-    // col >= 0 is a column of v; col < 0 encodes ghost position
-    // (col & 0x7fffffff) in the concatenated ghost buffer.
-    std::vector<int32_t> rowptr;       // n + 1
-    std::vector<int32_t> col;          // nnz
-    std::vector<uint8_t> val;          // nnz * value_size
+    // Split CSR as the device reads it (section 2, the on_process and
+    // off_process blocks): two CSR matrices over the same rows, each keeping
+    // the stored order of its entries.  col_on holds columns of v; col_off
+    // holds positions in the concatenated ghost buffer.
+    std::vector<int32_t> rowptr_on, col_on;      // n + 1, nnz_on
+    std::vector<uint8_t> val_on;                 // nnz_on * value_size
+    std::vector<int32_t> rowptr_off, col_off;    // n + 1, nnz_off
+    std::vector<uint8_t> val_off;                // nnz_off * value_size
+    // Smallest and largest on-process column of each row (lo > hi if none):
+    // the window of v a row block reads directly.
+    std::vector<int32_t> on_lo, on_hi;
 
     Phase phase[4];                    // INTER, L0, L1, L2
     PhaseStats stats[4];
@@ -64,7 +68,8 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
                 const int64_t *row_starts);
 
-// Frees the host copies of the split matrix and device lists (after upload).
+// Frees the host copies of the split matrix and device lists after upload
+// (row pointers and row windows stay: launch schedules are rebuilt from them).
 void release_device_arrays(HostPlan &hp);
 
 }  // namespace napspmv

@@ -1,0 +1,108 @@
+// Launch schedules of the apply kernels.  See schedule.hpp.
+#include "schedule.hpp"
+
+#include <algorithm>
+#include <cstdint>
+
+namespace napspmv {
+
+void row_blocks(const int32_t *rowptr, int64_t n, int cap, int max_rows,
+                std::vector<int32_t> &rowblk, std::vector<int32_t> &blkptr) {
+    rowblk.clear();
+    blkptr.clear();
+    int64_t r = 0;
+    while (r < n) {
+        rowblk.push_back((int32_t)r);
+        blkptr.push_back(rowptr[r]);
+        const int64_t start = r;
+        if (rowptr[r + 1] - rowptr[r] > cap) {
+            ++r;                                   // a long row alone
+            continue;
+        }
+        while (r < n && r - start < max_rows && rowptr[r + 1] - rowptr[start] <= cap) ++r;
+    }
+    rowblk.push_back((int32_t)n);
+    blkptr.push_back(rowptr[n]);
+}
+
+void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int32_t> &on_lo,
+                       const std::vector<int32_t> &on_hi, int64_t n, int window,
+                       std::vector<int32_t> &win) {
+    const int64_t nb = (int64_t)rowblk.size() - 1;
+    win.assign(2 * nb, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t lo = INT64_MAX, hi = -1;
+        for (int64_t r = rowblk[b]; r < rowblk[b + 1]; ++r) {
+            if (on_lo[r] <= on_hi[r]) {
+                lo = std::min<int64_t>(lo, on_lo[r]);
+                hi = std::max<int64_t>(hi, on_hi[r]);
+            }
+        }
+        int64_t s = 0, len = 0;
+        if (hi >= lo) {
+            if (hi - lo + 1 <= window) {
+                s = lo;
+                len = hi - lo + 1;
+            } else {
+                s = std::min(std::max<int64_t>(((int64_t)rowblk[b] + rowblk[b + 1]) / 2 - window / 2, lo),
+                             hi - window + 1);
+                len = window;
+            }
+        }
+        s = std::max<int64_t>(0, std::min<int64_t>(s, n - len));
+        win[2 * b] = (int32_t)s;
+        win[2 * b + 1] = (int32_t)len;
+    }
+}
+
+void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks) {
+    tasks.clear();
+    tasks.reserve((size_t)(n_items + n_blocks));
+    int64_t i = 0, b = 0;
+    while (i < n_items || b < n_blocks) {
+        // take an item while items are behind their share of the sequence
+        if (b >= n_blocks || (i < n_items && i * n_blocks <= b * n_items))
+            tasks.push_back(~(int32_t)i++);
+        else
+            tasks.push_back((int32_t)b++);
+    }
+}
+
+void gather_items(const std::vector<int64_t> &ghost_ptr, const std::vector<int32_t> &ghost_col,
+                  int64_t n, int bands, int max_len, std::vector<int32_t> &items) {
+    items.clear();
+    const int64_t n_p = (int64_t)ghost_ptr.size() - 1;
+    if (bands < 1) bands = 1;
+    // cut[t * (bands + 1) + b]: first position of gh(t) in band b
+    std::vector<int64_t> cut((size_t)(n_p * (bands + 1)));
+    for (int64_t t = 0; t < n_p; ++t) {
+        const int32_t *g0 = ghost_col.data() + ghost_ptr[t];
+        const int32_t *g1 = ghost_col.data() + ghost_ptr[t + 1];
+        for (int b = 0; b <= bands; ++b) {
+            const int64_t lo = (n * b) / bands;
+            cut[t * (bands + 1) + b] =
+                b == bands ? ghost_ptr[t + 1] : ghost_ptr[t] + (std::lower_bound(g0, g1, lo) - g0);
+        }
+    }
+    for (int b = 0; b < bands; ++b)
+        for (int64_t t = 0; t < n_p; ++t) {
+            int64_t a = cut[t * (bands + 1) + b];
+            const int64_t e = cut[t * (bands + 1) + b + 1];
+            while (a < e) {
+                const int64_t len = std::min<int64_t>(max_len, e - a);
+                items.push_back((int32_t)a);
+                items.push_back((int32_t)len);
+                a += len;
+            }
+        }
+}
+
+void flat_items(int64_t total, int max_len, std::vector<int32_t> &items) {
+    items.clear();
+    for (int64_t a = 0; a < total; a += max_len) {
+        items.push_back((int32_t)a);
+        items.push_back((int32_t)std::min<int64_t>(max_len, total - a));
+    }
+}
+
+}  // namespace napspmv

@@ -1,0 +1,40 @@
+// Launch schedules of the apply kernels, computed on the host from a plan.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace napspmv {
+
+// Row blocks of the stream product: maximal runs of consecutive rows whose
+// entries fit in `cap` (at most `max_rows` rows); a row longer than `cap`
+// gets a block of its own.  rowblk[b], blkptr[b] = first row and first entry
+// of block b; both have nblocks + 1 entries.
+void row_blocks(const int32_t *rowptr, int64_t n, int cap, int max_rows,
+                std::vector<int32_t> &rowblk, std::vector<int32_t> &blkptr);
+
+// The window of v (first column, length <= `window`) each row block stages
+// in LDS, as interleaved pairs: the block's whole on-process column range if
+// it fits, otherwise `window` columns centred on the block's rows inside that
+// range.  Windows stay inside [0, n).
+void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int32_t> &on_lo,
+                       const std::vector<int32_t> &on_hi, int64_t n, int window,
+                       std::vector<int32_t> &win);
+
+// Launch order of the first apply launch: exchange items (encoded ~i) and
+// local row blocks (encoded b >= 0) interleaved in proportion, each list
+// kept in its own order, so that any contiguous stretch of the launch (an
+// XCD's share) holds a proportional slice of both.
+void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks);
+
+// Work items (start, len) over the ghost buffer for the standard gather:
+// each process's ascending ghost list cut at `bands` equal column bands of v
+// and into pieces of at most `max_len`, ordered by (band, process).
+// Returned as interleaved pairs.
+void gather_items(const std::vector<int64_t> &ghost_ptr, const std::vector<int32_t> &ghost_col,
+                  int64_t n, int bands, int max_len, std::vector<int32_t> &items);
+
+// Work items covering [0, total) in order, pieces of at most `max_len`.
+void flat_items(int64_t total, int max_len, std::vector<int32_t> &items);
+
+}  // namespace napspmv

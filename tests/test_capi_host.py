@@ -184,16 +184,20 @@ def test_host_only_plan_refuses_apply():
     assert so.napspmv_plan_destroy(None) == 0
 
 
-def test_lanes_setting():
+def test_tuning_parameters():
     a = kkt_like(1 << 10, 2)
     p = lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, host_only=True)
-    assert p.lanes == 16                       # about two entries per lane at ~31 per row
-    p.lanes = 4
-    assert p.lanes == 4
-    with pytest.raises(lib.NapspmvError):
-        p.lanes = 3
-    p.lanes = 0
-    assert p.lanes == 16
+    assert p.get_param("block_nnz") == 4096 and p.get_param("window") == 1024
+    assert p.get_param("bands") >= 1
+    p.set_param("block_nnz", 1024)
+    p.set_param("window", 0)
+    p.set_param("bands", 7)
+    assert (p.get_param("block_nnz"), p.get_param("window"), p.get_param("bands")) == (1024, 0, 7)
+    for name, bad in (("block_nnz", 3000), ("window", 512), ("bands", 0)):
+        with pytest.raises(lib.NapspmvError):
+            p.set_param(name, bad)
+    p.set_param("block_nnz", -1)
+    assert p.get_param("block_nnz") == 4096
 
 
 def test_duplicates_and_stored_zeros_are_structure():

@@ -54,3 +54,41 @@ def test_rows_match_full_product_bitwise():
 def test_empty_matrix_rows():
     a = CSR(4, np.array([0, 0, 0, 0, 0], np.int64), np.zeros(0, np.int32), np.zeros(0))
     assert np.array_equal(spmv.spmv(a, np.ones(4)), np.zeros(4))
+
+
+def test_split_order_pins():
+    """The split-order product (on-process block, then off-process block, as
+    standard_spmv sums it) equals the dense product within rounding, is exact
+    on integer inputs, reduces to the plain product for one process, and its
+    C and Python evaluations agree bit for bit."""
+    from oracle.spmv import spmv_split, spmv_split_rows
+    for seed in range(4):
+        a = random_pattern(53, 0.12, seed, empty_rows=2, duplicates=4)
+        v_int = (np.arange(53) % 5 - 2).astype(np.float64)
+        for n_p in (1, 2, 5, 53):
+            assert np.array_equal(spmv_split(a, v_int, n_p), brute.matvec(a, v_int))
+        a = CSR(a.n, a.rowptr, a.col, np.random.default_rng(seed).standard_normal(a.nnz))
+        v = vec_normal(53, seed)
+        assert np.array_equal(spmv_split(a, v, 1), spmv.spmv(a, v))
+        for n_p in (3, 7):
+            w = spmv_split(a, v, n_p, threads=2)
+            ref = brute.matvec(a, v)
+            assert np.linalg.norm(w - ref) <= 1e-14 * np.linalg.norm(ref)
+            assert np.array_equal(spmv_split_rows(a, v, n_p, range(53)), w)
+    starts = np.array([0, 4, 5, 30, 53], np.int64)
+    w = spmv_split(a, v, 4, row_starts=starts)
+    assert np.array_equal(spmv_split_rows(a, v, 4, range(53), row_starts=starts), w)
+
+
+def test_split_order_differs_from_stored_order():
+    """Planted check: a row whose off-process entries come before its
+    on-process entry is summed differently by the two routines."""
+    from oracle.spmv import spmv_split
+    big = 2.0 ** 53
+    # 4 rows on 2 processes; row 0 (process 0 owns columns 0, 1) stores
+    # (col 2: 1), (col 3: 2^53), (col 0: -2^53)
+    a = CSR(4, np.array([0, 3, 4, 5, 6], np.int64), np.array([2, 3, 0, 1, 2, 3], np.int32),
+            np.array([1.0, big, -big, 1.0, 1.0, 1.0]))
+    v = np.ones(4)
+    assert spmv.spmv(a, v)[0] == 0.0          # (1 + 2^53) - 2^53: the 1 is lost
+    assert spmv_split(a, v, 2)[0] == 1.0      # (-2^53 + 1) + 2^53: exact
