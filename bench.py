@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--bands", type=int, default=-1)
     ap.add_argument("--extras", type=int, default=1, help="also time NAP mode and reduced precision")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="end with three plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the whole hot path lives on one device); "
@@ -270,6 +272,12 @@ def main():
     if args.cpu_seconds > 0:
         log("timing the CPU oracle ...")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    if args.calib_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
     print(json.dumps(result), flush=True)
 
 
