@@ -96,6 +96,7 @@ extern "C" {
 #define NAPSPMV_STAGE_REMOTE 1
 
 typedef struct napspmv_plan_s *napspmv_plan_t;
+typedef struct napspmv_batch_s *napspmv_batch_t;
 
 /* Per-phase message statistics (section 5 reports the per-process maxima).
  * Element counts are vector values; bytes moved = elems * value_bytes. */
@@ -166,9 +167,69 @@ NAPSPMV_API int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, c
 NAPSPMV_API int napspmv_apply(napspmv_plan_t plan, const void *v, void *w, void *stream);
 
 /* One stage of napspmv_apply (NAPSPMV_STAGE_*), for per-stage timing.
- * STAGE_SPMV reads the ghost buffer the last STAGE_EXCHANGE wrote. */
+ * STAGE_REMOTE reads the ghost buffer and partial w the last STAGE_LOCAL
+ * wrote. */
 NAPSPMV_API int napspmv_apply_stage(napspmv_plan_t plan, int stage, const void *v, void *w,
                         void *stream);
+
+/* Bytes of a caller-owned workspace for this plan: the ghost buffer and, for
+ * NAP plans, the inter-node send (and receive) buffers. */
+NAPSPMV_API int64_t napspmv_plan_workspace_bytes(napspmv_plan_t plan);
+
+/* napspmv_apply with a caller-owned workspace `ws` (device memory of
+ * napspmv_plan_workspace_bytes bytes, 256-byte aligned; NULL = the plan's
+ * own).  Applies of one plan with different workspaces may be in flight at
+ * the same time (on different streams); the workspace must not be shared by
+ * two applies in flight.  Allocates nothing. */
+NAPSPMV_API int napspmv_apply_ws(napspmv_plan_t plan, void *ws, const void *v, void *w,
+                                 void *stream);
+
+/*
+ * Batched applies: `count` independent products w[i] = A_i v[i] (plans
+ * plans[i], different matrices or the same one with different workspaces)
+ * in one launch sequence -- one first launch over every product's exchange
+ * and on-process work, one NAP scatter launch if any plan is NAP, one second
+ * launch over every off-process product.  All plans must share the value
+ * type, BLOCK_NNZ and VWINDOW, be on the batch's device and receive NAP
+ * messages in place.  ws may be NULL (every plan's own workspace) or hold
+ * per-product workspaces (NULL entries = the plan's own).  The batch object
+ * owns a device descriptor table (and a pinned host copy) for up to
+ * max_count products; a call waits until the previous call's launches have
+ * read the table, so use one batch object per stream.  napspmv_batch_apply
+ * allocates nothing.
+ */
+NAPSPMV_API int napspmv_batch_create(int max_count, napspmv_batch_t *out);
+NAPSPMV_API int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *plans,
+                                    void *const *ws, const void *const *v, void *const *w,
+                                    void *stream);
+NAPSPMV_API int napspmv_batch_destroy(napspmv_batch_t batch);
+
+/* Per-partition applies (standard plans): the rows of one process only --
+ * its own ghost gather and its split product -- as one pair of launches,
+ * the way each process of standard_spmv (section 2.1) computes its rows.
+ * prepare builds the per-partition launch schedules (allocates, synchronizes);
+ * apply_partition allocates nothing. */
+NAPSPMV_API int napspmv_plan_prepare_partitions(napspmv_plan_t plan);
+NAPSPMV_API int napspmv_apply_partition(napspmv_plan_t plan, int64_t part, const void *v, void *w,
+                                        void *stream);
+
+/* A HIP graph (hipGraphExec_t, returned as void*) that replays
+ * napspmv_apply(plan, v, w) on the stream it is launched on.  The graph
+ * holds the plan's pointers: destroy it before the plan, and re-create it
+ * after changing a tuning parameter. */
+NAPSPMV_API int napspmv_graph_create(napspmv_plan_t plan, const void *v, void *w, void **graph_out);
+NAPSPMV_API int napspmv_graph_launch(void *graph, void *stream);
+NAPSPMV_API int napspmv_graph_destroy(void *graph);
+
+/* Autotuner: times every (BLOCK_NNZ, VWINDOW, GATHER_BANDS) candidate on
+ * this plan with `reps` applies each (HIP events on `stream`; w is
+ * overwritten) and keeps the fastest.  With cache_path (may be NULL), a
+ * result already cached for the same device and workload shape is used
+ * without timing, and a new result is appended.  *best_ms (may be NULL)
+ * receives the best time per apply, or -1 when the cache answered.  No
+ * candidate changes any result bit.  Synchronizes; may allocate. */
+NAPSPMV_API int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *stream,
+                                      int reps, const char *cache_path, double *best_ms);
 
 /* Copy the plan's statistics into *out. */
 NAPSPMV_API int napspmv_plan_stats(napspmv_plan_t plan, napspmv_stats_t *out);
@@ -187,9 +248,11 @@ NAPSPMV_API int napspmv_plan_export(napspmv_plan_t plan, int phase, int64_t *n_m
  * list ascending.  Either array may be NULL. */
 NAPSPMV_API int napspmv_plan_ghosts(napspmv_plan_t plan, int64_t *ghost_ptr, int32_t *ghost_col);
 
-/* Diagnostic: copy the device ghost buffer (G elements of the vector type)
- * into host memory `out`; synchronizes `stream` first. */
-NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, void *out, void *stream);
+/* Diagnostic: copy the ghost buffer of workspace `ws` (NULL = the plan's own;
+ * G elements of the vector type) into host memory `out`; synchronizes
+ * `stream` first. */
+NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *ws, void *out,
+                                               void *stream);
 
 /* Tuning parameters of the apply kernels (NAPSPMV_PARAM_*); -1 restores the
  * automatic value.  No parameter changes any result bit.  Setting one on a

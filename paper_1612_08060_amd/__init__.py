@@ -14,7 +14,8 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "NapspmvError", "load_library", "LIB_PATH", "MODES", "DTYPES", "PHASES",
+__all__ = ["Plan", "Graph", "Batch", "NapspmvError", "load_library", "LIB_PATH", "MODES",
+           "DTYPES", "PHASES",
            "STAGE_LOCAL", "STAGE_REMOTE", "set_device_budget", "device_bytes_in_use"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnapspmv.so")
@@ -59,7 +60,18 @@ _SIGS = {
     "napspmv_plan_stats": (I32, [P, P]),
     "napspmv_plan_export": (I32, [P, I32, P, P, P, P, P, P]),
     "napspmv_plan_ghosts": (I32, [P, P, P]),
-    "napspmv_plan_read_ghost_values": (I32, [P, P, P]),
+    "napspmv_plan_read_ghost_values": (I32, [P, P, P, P]),
+    "napspmv_plan_workspace_bytes": (I64, [P]),
+    "napspmv_apply_ws": (I32, [P, P, P, P, P]),
+    "napspmv_batch_create": (I32, [I32, P]),
+    "napspmv_batch_apply": (I32, [P, I32, P, P, P, P, P]),
+    "napspmv_batch_destroy": (I32, [P]),
+    "napspmv_plan_prepare_partitions": (I32, [P]),
+    "napspmv_apply_partition": (I32, [P, I64, P, P, P]),
+    "napspmv_graph_create": (I32, [P, P, P, P]),
+    "napspmv_graph_launch": (I32, [P, P]),
+    "napspmv_graph_destroy": (I32, [P]),
+    "napspmv_plan_autotune": (I32, [P, P, P, P, I32, ctypes.c_char_p, P]),
     "napspmv_plan_set_param": (I32, [P, I32, I32]),
     "napspmv_plan_get_param": (I32, [P, I32]),
     "napspmv_plan_destroy": (I32, [P]),
@@ -214,13 +226,58 @@ class Plan:
                                                   self._vec_check(w, "w"),
                                                   _stream_handle(stream)))
 
-    def read_ghosts(self, stream=None) -> np.ndarray:
-        """The device ghost buffer after the last exchange (synchronizes)."""
+    def read_ghosts(self, stream=None, ws=None) -> np.ndarray:
+        """The ghost buffer after the last exchange (synchronizes)."""
         g = int(self.stats["ghosts"])
         out = np.empty(g, np.float64 if self.dtype == "f64" else np.float32)
-        _check(load_library().napspmv_plan_read_ghost_values(self._h, out.ctypes.data,
-                                                             _stream_handle(stream)))
+        _check(load_library().napspmv_plan_read_ghost_values(
+            self._h, None if ws is None else ctypes.c_void_p(ws.data_ptr()), out.ctypes.data,
+            _stream_handle(stream)))
         return out
+
+    @property
+    def workspace_bytes(self) -> int:
+        r = load_library().napspmv_plan_workspace_bytes(self._h)
+        if r < 0:
+            _check(r)
+        return int(r)
+
+    def new_workspace(self):
+        """A caller-owned workspace tensor (uint8, 256-byte aligned) for apply(ws=...)."""
+        import torch
+        nbytes = max(self.workspace_bytes, 1)
+        t = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-t.data_ptr()) % 256
+        return t[off:off + nbytes]
+
+    def apply_ws(self, ws, v, w, stream=None):
+        """w = A v using a caller-owned workspace (see new_workspace)."""
+        _check(load_library().napspmv_apply_ws(
+            self._h, ctypes.c_void_p(ws.data_ptr()), self._vec_check(v, "v"),
+            self._vec_check(w, "w"), _stream_handle(stream)))
+        return w
+
+    def prepare_partitions(self):
+        _check(load_library().napspmv_plan_prepare_partitions(self._h))
+
+    def apply_partition(self, part: int, v, w, stream=None):
+        """The rows of one process only (standard plans; prepare_partitions first)."""
+        _check(load_library().napspmv_apply_partition(self._h, int(part), self._vec_check(v, "v"),
+                                                      self._vec_check(w, "w"),
+                                                      _stream_handle(stream)))
+
+    def graph(self, v, w):
+        """A replayable HIP graph of apply(v, w) (see Graph)."""
+        return Graph(self, v, w)
+
+    def autotune(self, v, w, stream=None, reps: int = 5, cache_path=None) -> float:
+        """Pick the fastest tuning for this plan (see napspmv_plan_autotune)."""
+        best = ctypes.c_double()
+        _check(load_library().napspmv_plan_autotune(
+            self._h, self._vec_check(v, "v"), self._vec_check(w, "w"), _stream_handle(stream),
+            int(reps), None if cache_path is None else str(cache_path).encode(),
+            ctypes.byref(best)))
+        return best.value
 
     def close(self):
         if getattr(self, "_h", None) is not None:
@@ -238,3 +295,63 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Graph:
+    """A HIP graph replaying one apply of a plan on fixed vectors."""
+
+    def __init__(self, plan: Plan, v, w):
+        self.plan = plan
+        self._v, self._w = v, w            # keep the vectors alive
+        h = ctypes.c_void_p()
+        _check(load_library().napspmv_graph_create(plan._h, plan._vec_check(v, "v"),
+                                                   plan._vec_check(w, "w"), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load_library().napspmv_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().napspmv_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched applies over many plans in one launch sequence
+    (napspmv_batch_apply); one Batch per stream."""
+
+    def __init__(self, max_count: int):
+        h = ctypes.c_void_p()
+        _check(load_library().napspmv_batch_create(int(max_count), ctypes.byref(h)))
+        self._h = h
+        self.max_count = int(max_count)
+
+    def apply(self, plans, vs, ws_out, workspaces=None, stream=None):
+        n = len(plans)
+        P_ = ctypes.c_void_p * n
+        hp = P_(*[p._h.value for p in plans])
+        hv = P_(*[p._vec_check(v, "v").value for p, v in zip(plans, vs)])
+        hw = P_(*[p._vec_check(w, "w").value for p, w in zip(plans, ws_out)])
+        hws = None
+        if workspaces is not None:
+            hws = P_(*[None if x is None else x.data_ptr() for x in workspaces])
+        _check(load_library().napspmv_batch_apply(self._h, n, hp, hws, hv, hw,
+                                                  _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().napspmv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

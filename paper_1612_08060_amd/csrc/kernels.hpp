@@ -207,42 +207,137 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
     }
 }
 
-// First launch: tasks[b] (after the XCD remap) is either an exchange item
-// (~i: xdst[k] = v[idx[k]] over items[i]) or a row block of the on-process
-// product (b >= 0: rows rowblk[b].., entries blkptr[b].., window win[b]).
-// The two kinds are interleaved in the task list, so every CU runs both at
-// once.
+// Everything one product needs, by launch.  A plain launch passes one view by
+// value; a batched launch reads views from a device table.
+template <typename VT, typename XT>
+struct LocalView {
+    const int32_t *tasks;      // task list: ~i exchange item, b >= 0 on-process block
+    int32_t n_tasks;
+    const int2 *items;         // exchange items (start, len)
+    const int32_t *idx;        // exchange source indices (columns of v)
+    XT *xdst;                  // exchange destination (ghost buffer or NAP send buffer)
+    const int32_t *rowblk, *blkptr;
+    const int2 *win;           // v windows of the on-process blocks (or null)
+    const int32_t *rowptr, *col;
+    const VT *val;
+    const XT *v;
+    XT *w;
+};
+
+template <typename VT, typename XT>
+struct RemoteView {
+    int32_t n_blocks;
+    const int32_t *rowblk, *blkptr, *rowptr, *col;
+    const VT *val;
+    const XT *ghost;
+    XT *w;
+};
+
+template <typename XT>
+struct ScatterView {
+    int32_t n1;                // received values -> ghost slots
+    const int32_t *s1, *d1;
+    const XT *s1v;
+    int32_t n2;                // fully local values -> ghost slots
+    const int32_t *s2, *d2;
+    const XT *s2v;
+    XT *ghost;
+};
+
 template <typename VT, typename XT, int CAP, int W>
-__global__ __launch_bounds__(kBlock) void k_local(
-    const int32_t *__restrict__ tasks, const int2 *__restrict__ items,
-    const int32_t *__restrict__ idx, XT *__restrict__ xdst,
-    const int32_t *__restrict__ rowblk, const int32_t *__restrict__ blkptr,
-    const int2 *__restrict__ win, const int32_t *__restrict__ rowptr,
-    const int32_t *__restrict__ col, const VT *__restrict__ val, const XT *__restrict__ v,
-    XT *__restrict__ w) {
-    __shared__ XT prod[CAP];
-    __shared__ XT wbuf[W > 0 ? W : 1];
-    const int32_t task = tasks[xcd_block(blockIdx.x, gridDim.x)];
+__device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t, XT *prod,
+                                           XT *wbuf) {
+    const int32_t task = L.tasks[t];
     if (task < 0) {
-        gather_item(items[~task], idx, v, xdst);
+        gather_item(L.items[~task], L.idx, L.v, L.xdst);
         return;
     }
-    const int2 wn = W > 0 ? win[task] : make_int2(0, 0);
-    product_block<VT, XT, CAP, W, false>(rowblk[task], rowblk[task + 1], blkptr[task],
-                                         blkptr[task + 1], wn, rowptr, col, val, v, w, prod, wbuf);
+    const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
+    product_block<VT, XT, CAP, W, false>(L.rowblk[task], L.rowblk[task + 1], L.blkptr[task],
+                                         L.blkptr[task + 1], wn, L.rowptr, L.col, L.val, L.v,
+                                         L.w, prod, wbuf);
+}
+
+template <typename VT, typename XT, int CAP>
+__device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
+    product_block<VT, XT, CAP, 0, true>(R.rowblk[b], R.rowblk[b + 1], R.blkptr[b],
+                                        R.blkptr[b + 1], make_int2(0, 0), R.rowptr, R.col, R.val,
+                                        R.ghost, R.w, prod, nullptr);
+}
+
+// Index of the entry of prefix[0..count] (ascending, prefix[0] = 0) whose
+// range [prefix[i], prefix[i+1]) holds b.
+__device__ __forceinline__ int32_t find_range(const int32_t *__restrict__ prefix, int32_t count,
+                                              int32_t b) {
+    int32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// First launch: task t (after the XCD remap) is either an exchange item or a
+// row block of the on-process product.  The two kinds are interleaved in the
+// task list, so every CU runs both at once.
+template <typename VT, typename XT, int CAP, int W>
+__global__ __launch_bounds__(kBlock) void k_local(LocalView<VT, XT> L) {
+    __shared__ XT prod[CAP];
+    __shared__ XT wbuf[W > 0 ? W : 1];
+    local_task<VT, XT, CAP, W>(L, (int32_t)xcd_block(blockIdx.x, gridDim.x), prod, wbuf);
 }
 
 // Second launch: the off-process product, added into the partial w.
 template <typename VT, typename XT, int CAP>
-__global__ __launch_bounds__(kBlock) void k_remote(
-    const int32_t *__restrict__ rowblk, const int32_t *__restrict__ blkptr,
-    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-    const VT *__restrict__ val, const XT *__restrict__ ghost, XT *__restrict__ w) {
+__global__ __launch_bounds__(kBlock) void k_remote(RemoteView<VT, XT> R) {
     __shared__ XT prod[CAP];
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    product_block<VT, XT, CAP, 0, true>(rowblk[b], rowblk[b + 1], blkptr[b], blkptr[b + 1],
-                                        make_int2(0, 0), rowptr, col, val, ghost, w, prod,
-                                        nullptr);
+    remote_block<VT, XT, CAP>(R, (int32_t)xcd_block(blockIdx.x, gridDim.x), prod);
+}
+
+// Batched first launch over `count` products: views[i] owns the launch's
+// blocks [prefix[i], prefix[i+1]).
+template <typename VT, typename XT, int CAP, int W>
+__global__ __launch_bounds__(kBlock) void k_local_batch(const LocalView<VT, XT> *__restrict__ views,
+                                                        const int32_t *__restrict__ prefix,
+                                                        int32_t count) {
+    __shared__ XT prod[CAP];
+    __shared__ XT wbuf[W > 0 ? W : 1];
+    const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
+    const int32_t i = find_range(prefix, count, b);
+    local_task<VT, XT, CAP, W>(views[i], b - prefix[i], prod, wbuf);
+}
+
+template <typename VT, typename XT, int CAP>
+__global__ __launch_bounds__(kBlock) void k_remote_batch(const RemoteView<VT, XT> *__restrict__ views,
+                                                         const int32_t *__restrict__ prefix,
+                                                         int32_t count) {
+    __shared__ XT prod[CAP];
+    const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
+    const int32_t i = find_range(prefix, count, b);
+    remote_block<VT, XT, CAP>(views[i], b - prefix[i], prod);
+}
+
+// Batched NAP scatter: views[i] owns blocks [prefix[i], prefix[i+1]); each
+// view's first ceil(n1/256) blocks copy received values, the rest fully
+// local values.
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void k_scatter_batch(const ScatterView<XT> *__restrict__ views,
+                                                          const int32_t *__restrict__ prefix,
+                                                          int32_t count) {
+    const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
+    const int32_t i = find_range(prefix, count, b);
+    const ScatterView<XT> &S = views[i];
+    const uint32_t lb = (uint32_t)(b - prefix[i]);
+    const uint32_t nb1 = ((uint32_t)S.n1 + kBlock - 1) / kBlock;
+    if (lb < nb1) {
+        const uint32_t k = lb * kBlock + threadIdx.x;
+        if (k < (uint32_t)S.n1)
+            S.ghost[__builtin_nontemporal_load(S.d1 + k)] = S.s1v[__builtin_nontemporal_load(S.s1 + k)];
+    } else {
+        const uint32_t k = (lb - nb1) * kBlock + threadIdx.x;
+        if (k < (uint32_t)S.n2)
+            S.ghost[__builtin_nontemporal_load(S.d2 + k)] = S.s2v[__builtin_nontemporal_load(S.s2 + k)];
+    }
 }
 
 }  // namespace napspmv

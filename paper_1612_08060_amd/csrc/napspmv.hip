@@ -1,5 +1,6 @@
 // The C ABI of include/napspmv.h: plan creation (host builder + device
-// upload), the apply path (exchange kernels + split product), tuning and
+// upload), the apply path (exchange kernels + split product), caller-owned
+// workspaces, batched and per-partition applies, graph capture, tuning and
 // diagnostics.  Nothing here throws across the interface.
 #include <hip/hip_runtime.h>
 
@@ -7,8 +8,12 @@
 #include <atomic>
 #include <chrono>
 #include <cstring>
+#include <fstream>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 #include "napspmv.h"
@@ -19,9 +24,22 @@ using napspmv::Error;
 using napspmv::HostPlan;
 
 namespace {
-constexpr int kMaxItem = 4096;          // gather work item length
+constexpr int kMaxItem = 4096;                      // exchange work item length
 constexpr int kMaxRowsPerBlock = napspmv::kMaxRows;  // rows of a product block
+constexpr int64_t kAlign = 256;
+
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 }  // namespace
+
+// Launch schedules of one set of row blocks and exchange items.
+struct Schedules {
+    int32_t *onblk = nullptr, *onptr = nullptr, *win = nullptr;
+    int32_t *offblk = nullptr, *offptr = nullptr, *items = nullptr, *tasks = nullptr;
+    int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, bytes = 0;
+    // per-partition schedules only: each process's range of tasks and of
+    // off-process blocks
+    std::vector<int64_t> task_ptr, off_ptr;
+};
 
 struct napspmv_plan_s {
     HostPlan hp;
@@ -33,20 +51,26 @@ struct napspmv_plan_s {
     int auto_block_nnz = 4096, auto_bands = 1, auto_window = 1024;
     int cur_block_nnz = 0, cur_bands = 0, cur_window = -1;   // schedules on the device
     int64_t G = 0, E = 0, H = 0, Gon = 0;
-    int64_t n_on_blocks = 0, n_off_blocks = 0, n_items = 0, n_tasks = 0;
     int32_t *d_rp_on = nullptr, *d_col_on = nullptr, *d_rp_off = nullptr, *d_col_off = nullptr;
     void *d_val_on = nullptr, *d_val_off = nullptr;
-    void *d_ghost = nullptr;
     int32_t *d_gather = nullptr, *d_pack = nullptr;
-    void *d_send = nullptr, *d_recv = nullptr;
     int32_t *d_ssrc = nullptr, *d_sdst = nullptr, *d_lsrc = nullptr, *d_ldst = nullptr;
-    // schedules: on-process row blocks + windows, off-process row blocks,
-    // exchange items, the merged task list of the first launch
-    int32_t *d_onblk = nullptr, *d_onptr = nullptr, *d_win = nullptr;
-    int32_t *d_offblk = nullptr, *d_offptr = nullptr, *d_items = nullptr, *d_tasks = nullptr;
-    int64_t bytes_sched = 0;
+    void *d_ws = nullptr;            // the plan's own workspace (ghost, send, receive)
+    Schedules sched;                 // all partitions in one launch pair
+    Schedules part;                  // per-partition schedules (built on request)
+    bool part_ready = false;
     int64_t device_bytes = 0;
     double build_s = 0, upload_s = 0;
+};
+
+struct napspmv_batch_s {
+    int capacity = 0;
+    int device = 0;
+    void *d_desc = nullptr;          // device descriptor table
+    void *h_desc = nullptr;          // pinned host staging of the table
+    size_t desc_bytes = 0;
+    hipEvent_t done = nullptr;       // recorded after the last batch's launches
+    bool pending = false;
 };
 
 namespace {
@@ -81,12 +105,54 @@ struct DeviceGuard {
     }
 };
 
+template <typename F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(NAPSPMV_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(NAPSPMV_EINVAL, e.what());
+    }
+}
+
 int64_t vec_bytes(int dtype) { return dtype == NAPSPMV_F64 ? 8 : 4; }
 
 // Column bands of the standard gather: about 2 MiB of v per band.
 int pick_bands(int64_t n, int64_t vb) {
     const int64_t b = (n * vb + (2 << 20) - 1) / (2 << 20);
     return (int)std::max<int64_t>(1, std::min<int64_t>(64, b));
+}
+
+// Workspace layout: ghost buffer, then the NAP send buffer, then the NAP
+// receive buffer (explicit hop only), each 256-byte aligned.
+struct WsLayout {
+    int64_t ghost = 0, send = 0, recv = 0, total = 0;
+};
+
+WsLayout ws_layout(const napspmv_plan_s *p) {
+    const int64_t vb = vec_bytes(p->hp.dtype);
+    const bool nap = p->hp.mode == NAPSPMV_NAP;
+    const bool copy = nap && (p->flags & NAPSPMV_EXCHANGE_COPY);
+    WsLayout l;
+    l.send = align_up(p->G * vb);
+    l.total = l.send + (nap ? align_up(p->E * vb) : 0);
+    l.recv = copy ? l.total : l.send;
+    if (copy) l.total += align_up(p->E * vb);
+    return l;
+}
+
+struct Ws {
+    void *ghost, *send, *recv;
+};
+
+Ws ws_ptrs(const napspmv_plan_s *p, void *base) {
+    if (!base) return Ws{nullptr, nullptr, nullptr};
+    const WsLayout l = ws_layout(p);
+    char *b = static_cast<char *>(base);
+    return Ws{b + l.ghost, b + l.send, b + l.recv};
 }
 
 template <typename T>
@@ -98,12 +164,6 @@ void upload(T *&dst, const std::vector<T> &src, int64_t &total) {
     HIP_OK(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
 }
 
-void alloc(void *&dst, int64_t bytes, int64_t &total) {
-    if (bytes <= 0) return;
-    HIP_OK(hipMalloc(&dst, (size_t)bytes));
-    total += bytes;
-}
-
 void free_ptr(void *p) {
     if (p) (void)hipFree(p);
 }
@@ -113,52 +173,120 @@ void charge(napspmv_plan_s *p, int64_t bytes) {
     g_in_use += bytes;
 }
 
-void free_schedules(napspmv_plan_s *p) {
-    void *ptrs[] = {p->d_onblk, p->d_onptr, p->d_win, p->d_offblk, p->d_offptr, p->d_items,
-                    p->d_tasks};
+void free_schedules(napspmv_plan_s *p, Schedules &s) {
+    void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks};
     for (void *q : ptrs) free_ptr(q);
-    p->d_onblk = p->d_onptr = p->d_win = p->d_offblk = p->d_offptr = nullptr;
-    p->d_items = p->d_tasks = nullptr;
-    charge(p, -p->bytes_sched);
-    p->bytes_sched = 0;
+    charge(p, -s.bytes);
+    s = Schedules();
 }
 
 void free_device(napspmv_plan_s *p) {
-    free_schedules(p);
+    free_schedules(p, p->sched);
+    free_schedules(p, p->part);
+    p->part_ready = false;
     void *ptrs[] = {p->d_rp_on, p->d_col_on, p->d_rp_off, p->d_col_off, p->d_val_on,
-                    p->d_val_off, p->d_ghost, p->d_gather, p->d_pack, p->d_send,
-                    p->d_recv == p->d_send ? nullptr : p->d_recv,
-                    p->d_ssrc, p->d_sdst, p->d_lsrc, p->d_ldst};
+                    p->d_val_off, p->d_gather, p->d_pack, p->d_ssrc, p->d_sdst, p->d_lsrc,
+                    p->d_ldst, p->d_ws};
     for (void *q : ptrs) free_ptr(q);
     p->d_rp_on = p->d_col_on = p->d_rp_off = p->d_col_off = nullptr;
-    p->d_val_on = p->d_val_off = p->d_ghost = p->d_send = p->d_recv = nullptr;
+    p->d_val_on = p->d_val_off = p->d_ws = nullptr;
     p->d_gather = p->d_pack = p->d_ssrc = p->d_sdst = p->d_lsrc = p->d_ldst = nullptr;
     g_in_use -= p->device_bytes;
     p->device_bytes = 0;
     p->on_device = false;
 }
 
-int64_t planned_device_bytes(const HostPlan &hp, uint32_t flags) {
-    const int64_t vb = vec_bytes(hp.dtype);
+int64_t planned_device_bytes(const napspmv_plan_s *p) {
+    const HostPlan &hp = p->hp;
     int64_t b = (int64_t)(hp.rowptr_on.size() + hp.col_on.size() + hp.rowptr_off.size() +
                           hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
-    b += (int64_t)hp.ghost_col.size() * vb;
     b += (int64_t)(hp.gather_idx.size() + hp.pack_idx.size() + hp.scat_src.size() +
                    hp.scat_dst.size() + hp.l2_src.size() + hp.l2_dst.size()) * 4;
-    if (hp.mode == NAPSPMV_NAP)
-        b += (int64_t)hp.pack_idx.size() * vb * ((flags & NAPSPMV_EXCHANGE_COPY) ? 2 : 1);
-    return b;
+    return b + ws_layout(p).total;
 }
 
-// (Re)build every launch schedule for the current tuning: on-process row
+void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t> &onblk,
+                      const std::vector<int32_t> &onptr, const std::vector<int32_t> &wins,
+                      const std::vector<int32_t> &offblk, const std::vector<int32_t> &offptr,
+                      const std::vector<int32_t> &items, const std::vector<int32_t> &tasks) {
+    free_schedules(p, s);
+    int64_t total = 0;
+    try {
+        upload(s.onblk, onblk, total);
+        upload(s.onptr, onptr, total);
+        upload(s.win, wins, total);
+        upload(s.offblk, offblk, total);
+        upload(s.offptr, offptr, total);
+        upload(s.items, items, total);
+        upload(s.tasks, tasks, total);
+    } catch (...) {
+        s.bytes = total;
+        charge(p, total);
+        throw;
+    }
+    s.bytes = total;
+    charge(p, total);
+    s.n_on = (int64_t)onblk.size() - 1;
+    s.n_off = (int64_t)offblk.size() - 1;
+    s.n_items = (int64_t)items.size() / 2;
+    s.n_tasks = (int64_t)tasks.size();
+}
+
+int cur_cap(const napspmv_plan_s *p) { return p->block_nnz >= 0 ? p->block_nnz : p->auto_block_nnz; }
+int cur_win(const napspmv_plan_s *p) { return p->window >= 0 ? p->window : p->auto_window; }
+int cur_bands(const napspmv_plan_s *p) { return p->bands >= 0 ? p->bands : p->auto_bands; }
+
+// Per-partition schedules (standard mode): each process's row blocks and its
+// own ghost gather items, contiguous per process, so one process's product
+// is one pair of launches.
+void build_partitions(napspmv_plan_s *p) {
+    const HostPlan &hp = p->hp;
+    const int cap = cur_cap(p), win = cur_win(p);
+    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks;
+    std::vector<int64_t> task_ptr(hp.n_p + 1, 0), off_ptr(hp.n_p + 1, 0);
+    for (int64_t t = 0; t < hp.n_p; ++t) {
+        const int64_t r0 = hp.starts[t], r1 = hp.starts[t + 1];
+        std::vector<int32_t> ob, op, fb, fp, it, ts, wn;
+        napspmv::row_blocks(hp.rowptr_on.data() + r0, r1 - r0, cap, kMaxRowsPerBlock, ob, op);
+        napspmv::row_blocks(hp.rowptr_off.data() + r0, r1 - r0, cap, kMaxRowsPerBlock, fb, fp);
+        for (auto &x : ob) x += (int32_t)r0;
+        for (auto &x : fb) x += (int32_t)r0;
+        if (win > 0) napspmv::row_block_windows(ob, hp.on_lo, hp.on_hi, hp.n, win, wn);
+        napspmv::flat_items(hp.ghost_ptr[t + 1] - hp.ghost_ptr[t], kMaxItem, it);
+        for (size_t k = 0; k < it.size(); k += 2) it[k] += (int32_t)hp.ghost_ptr[t];
+        const int32_t blk_base = (int32_t)onblk.size();
+        const int32_t item_base = (int32_t)(items.size() / 2);
+        napspmv::merge_tasks((int64_t)it.size() / 2, (int64_t)ob.size() - 1, ts);
+        for (auto &x : ts) x = x < 0 ? ~(~x + item_base) : x + blk_base;
+        // concatenate; a process's closing boundary is the next one's first
+        onblk.insert(onblk.end(), ob.begin(), ob.end() - 1);
+        onptr.insert(onptr.end(), op.begin(), op.end() - 1);
+        wins.insert(wins.end(), wn.begin(), wn.end());
+        off_ptr[t] = (int64_t)offblk.size();
+        offblk.insert(offblk.end(), fb.begin(), fb.end() - 1);
+        offptr.insert(offptr.end(), fp.begin(), fp.end() - 1);
+        off_ptr[t + 1] = (int64_t)offblk.size();
+        items.insert(items.end(), it.begin(), it.end());
+        tasks.insert(tasks.end(), ts.begin(), ts.end());
+        task_ptr[t + 1] = (int64_t)tasks.size();
+    }
+    onblk.push_back((int32_t)hp.n);
+    onptr.push_back(hp.rowptr_on[hp.n]);
+    offblk.push_back((int32_t)hp.n);
+    offptr.push_back(hp.rowptr_off[hp.n]);
+    upload_schedules(p, p->part, onblk, onptr, wins, offblk, offptr, items, tasks);
+    p->part.task_ptr = task_ptr;
+    p->part.off_ptr = off_ptr;
+    p->part_ready = true;
+}
+
+// (Re)build the launch schedules for the current tuning: on-process row
 // blocks with their v windows, off-process row blocks, the exchange items
 // (standard: ghost gather by column band; NAP: pack in order) and the task
-// list of the first launch.
+// list of the first launch.  Per-partition schedules follow.
 void refresh_schedules(napspmv_plan_s *p) {
-    const int cap = p->block_nnz >= 0 ? p->block_nnz : p->auto_block_nnz;
-    const int win = p->window >= 0 ? p->window : p->auto_window;
-    const int bands = p->bands >= 0 ? p->bands : p->auto_bands;
-    if (p->d_onblk && cap == p->cur_block_nnz && win == p->cur_window && bands == p->cur_bands)
+    const int cap = cur_cap(p), win = cur_win(p), bands = cur_bands(p);
+    if (p->sched.onblk && cap == p->cur_block_nnz && win == p->cur_window && bands == p->cur_bands)
         return;
     const HostPlan &hp = p->hp;
     std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks;
@@ -170,37 +298,17 @@ void refresh_schedules(napspmv_plan_s *p) {
     else
         napspmv::flat_items(p->E, kMaxItem, items);
     napspmv::merge_tasks((int64_t)items.size() / 2, (int64_t)onblk.size() - 1, tasks);
-    free_schedules(p);
-    int64_t total = 0;
-    try {
-        upload(p->d_onblk, onblk, total);
-        upload(p->d_onptr, onptr, total);
-        upload(p->d_win, wins, total);
-        upload(p->d_offblk, offblk, total);
-        upload(p->d_offptr, offptr, total);
-        upload(p->d_items, items, total);
-        upload(p->d_tasks, tasks, total);
-    } catch (...) {
-        p->bytes_sched = total;
-        charge(p, total);
-        throw;
-    }
-    p->bytes_sched = total;
-    charge(p, total);
-    p->n_on_blocks = (int64_t)onblk.size() - 1;
-    p->n_off_blocks = (int64_t)offblk.size() - 1;
-    p->n_items = (int64_t)items.size() / 2;
-    p->n_tasks = (int64_t)tasks.size();
+    upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks);
     p->cur_block_nnz = cap;
     p->cur_window = win;
     p->cur_bands = bands;
+    if (p->part_ready) build_partitions(p);
 }
 
 void to_device(napspmv_plan_s *p) {
     HostPlan &hp = p->hp;
     HIP_OK(hipGetDevice(&p->device));
-
-    const int64_t need = planned_device_bytes(hp, p->flags);
+    const int64_t need = planned_device_bytes(p);
     const int64_t budget = g_budget.load();
     if (budget > 0 && g_in_use.load() + need > budget)
         throw Error(NAPSPMV_ENOMEM, "device budget exceeded: plan needs " + std::to_string(need) +
@@ -208,7 +316,6 @@ void to_device(napspmv_plan_s *p) {
                                         " in use of " + std::to_string(budget));
     int64_t total = 0;
     try {
-        const int64_t vb = vec_bytes(hp.dtype);
         upload(p->d_rp_on, hp.rowptr_on, total);
         upload(p->d_col_on, hp.col_on, total);
         upload(p->d_rp_off, hp.rowptr_off, total);
@@ -221,19 +328,16 @@ void to_device(napspmv_plan_s *p) {
         };
         upload_bytes(p->d_val_on, hp.val_on);
         upload_bytes(p->d_val_off, hp.val_off);
-        alloc(p->d_ghost, p->G * vb, total);
         upload(p->d_gather, hp.gather_idx, total);
         upload(p->d_pack, hp.pack_idx, total);
         upload(p->d_ssrc, hp.scat_src, total);
         upload(p->d_sdst, hp.scat_dst, total);
         upload(p->d_lsrc, hp.l2_src, total);
         upload(p->d_ldst, hp.l2_dst, total);
-        if (hp.mode == NAPSPMV_NAP) {
-            alloc(p->d_send, p->E * vb, total);
-            if (p->flags & NAPSPMV_EXCHANGE_COPY)
-                alloc(p->d_recv, p->E * vb, total);
-            else
-                p->d_recv = p->d_send;          // receive in place: the exchange is an alias
+        const int64_t wsb = ws_layout(p).total;
+        if (wsb > 0) {
+            HIP_OK(hipMalloc(&p->d_ws, (size_t)wsb));
+            total += wsb;
         }
         charge(p, total);
         total = 0;
@@ -249,87 +353,144 @@ void to_device(napspmv_plan_s *p) {
 
 inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + napspmv::kBlock - 1) / napspmv::kBlock); }
 
-template <typename VT, typename XT, int CAP, int W>
-void launch_local_w(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
+// ---- views -------------------------------------------------------------------
+
+template <typename VT, typename XT>
+napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &s, const Ws &ws,
+                                      const XT *v, XT *w, int64_t task0, int64_t n_tasks) {
     const bool std_mode = p->hp.mode == NAPSPMV_STANDARD;
-    XT *xdst = static_cast<XT *>(std_mode ? p->d_ghost : p->d_send);
-    const int32_t *idx = std_mode ? p->d_gather : p->d_pack;
-    napspmv::k_local<VT, XT, CAP, W><<<(uint32_t)p->n_tasks, napspmv::kBlock, 0, s>>>(
-        p->d_tasks, reinterpret_cast<const int2 *>(p->d_items), idx, xdst, p->d_onblk,
-        p->d_onptr, reinterpret_cast<const int2 *>(p->d_win), p->d_rp_on, p->d_col_on,
-        static_cast<const VT *>(p->d_val_on), v, w);
-}
-
-template <typename VT, typename XT, int CAP>
-void launch_local(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
-    switch (p->cur_window) {
-        case 1024: launch_local_w<VT, XT, CAP, 1024>(p, v, w, s); break;
-        case 2048: launch_local_w<VT, XT, CAP, 2048>(p, v, w, s); break;
-        case 4096: launch_local_w<VT, XT, CAP, 4096>(p, v, w, s); break;
-        default: launch_local_w<VT, XT, CAP, 0>(p, v, w, s); break;
-    }
-}
-
-template <typename VT, typename XT, int CAP>
-void launch_remote(napspmv_plan_s *p, const XT *v, XT *w, hipStream_t s) {
-    using namespace napspmv;
-    if (p->hp.mode == NAPSPMV_NAP) {
-        // the inter-node hop (alias unless copied), then the scatter of the
-        // received values to every user on the node, with the fully local
-        // on-node values
-        if (p->E > 0 && p->d_recv != p->d_send)
-            k_copy<XT><<<blocks_for(p->E), kBlock, 0, s>>>((int32_t)p->E,
-                                                         static_cast<const XT *>(p->d_send),
-                                                         static_cast<XT *>(p->d_recv));
-        const uint32_t nb1 = blocks_for(p->H), nb2 = blocks_for(p->Gon);
-        if (nb1 + nb2 > 0)
-            k_scatter2<XT><<<nb1 + nb2, kBlock, 0, s>>>(
-                (int32_t)p->H, p->d_ssrc, p->d_sdst, static_cast<const XT *>(p->d_recv),
-                (int32_t)p->Gon, p->d_lsrc, p->d_ldst, v, static_cast<XT *>(p->d_ghost), nb1);
-    }
-    if (p->hp.nnz_off > 0)
-        k_remote<VT, XT, CAP><<<(uint32_t)p->n_off_blocks, kBlock, 0, s>>>(
-            p->d_offblk, p->d_offptr, p->d_rp_off, p->d_col_off,
-            static_cast<const VT *>(p->d_val_off), static_cast<const XT *>(p->d_ghost), w);
+    napspmv::LocalView<VT, XT> L;
+    L.tasks = s.tasks + task0;
+    L.n_tasks = (int32_t)n_tasks;
+    L.items = reinterpret_cast<const int2 *>(s.items);
+    L.idx = std_mode ? p->d_gather : p->d_pack;
+    L.xdst = static_cast<XT *>(std_mode ? ws.ghost : ws.send);
+    L.rowblk = s.onblk;
+    L.blkptr = s.onptr;
+    L.win = reinterpret_cast<const int2 *>(s.win);
+    L.rowptr = p->d_rp_on;
+    L.col = p->d_col_on;
+    L.val = static_cast<const VT *>(p->d_val_on);
+    L.v = v;
+    L.w = w;
+    return L;
 }
 
 template <typename VT, typename XT>
-void launch_stage(napspmv_plan_s *p, int stage, const XT *v, XT *w, hipStream_t s) {
-    switch (p->cur_block_nnz) {
-        case 1024:
-            stage == NAPSPMV_STAGE_LOCAL ? launch_local<VT, XT, 1024>(p, v, w, s)
-                                         : launch_remote<VT, XT, 1024>(p, v, w, s);
-            break;
-        case 4096:
-            stage == NAPSPMV_STAGE_LOCAL ? launch_local<VT, XT, 4096>(p, v, w, s)
-                                         : launch_remote<VT, XT, 4096>(p, v, w, s);
-            break;
-        default:
-            stage == NAPSPMV_STAGE_LOCAL ? launch_local<VT, XT, 2048>(p, v, w, s)
-                                         : launch_remote<VT, XT, 2048>(p, v, w, s);
-            break;
+napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules &s, const Ws &ws,
+                                        XT *w, int64_t blk0, int64_t n_blk) {
+    napspmv::RemoteView<VT, XT> R;
+    R.n_blocks = (int32_t)n_blk;
+    R.rowblk = s.offblk + blk0;
+    R.blkptr = s.offptr + blk0;
+    R.rowptr = p->d_rp_off;
+    R.col = p->d_col_off;
+    R.val = static_cast<const VT *>(p->d_val_off);
+    R.ghost = static_cast<const XT *>(ws.ghost);
+    R.w = w;
+    return R;
+}
+
+template <typename XT>
+napspmv::ScatterView<XT> scatter_view(const napspmv_plan_s *p, const Ws &ws, const XT *v) {
+    napspmv::ScatterView<XT> S;
+    S.n1 = (int32_t)p->H;
+    S.s1 = p->d_ssrc;
+    S.d1 = p->d_sdst;
+    S.s1v = static_cast<const XT *>(ws.recv);
+    S.n2 = (int32_t)p->Gon;
+    S.s2 = p->d_lsrc;
+    S.d2 = p->d_ldst;
+    S.s2v = v;
+    S.ghost = static_cast<XT *>(ws.ghost);
+    return S;
+}
+
+// ---- single-plan launches ------------------------------------------------------
+
+template <typename VT, typename XT, int CAP, int W>
+void launch_local_w(const napspmv::LocalView<VT, XT> &L, hipStream_t s) {
+    if (L.n_tasks > 0)
+        napspmv::k_local<VT, XT, CAP, W><<<(uint32_t)L.n_tasks, napspmv::kBlock, 0, s>>>(L);
+}
+
+template <typename VT, typename XT, int CAP>
+void launch_local(int win, const napspmv::LocalView<VT, XT> &L, hipStream_t s) {
+    switch (win) {
+        case 1024: launch_local_w<VT, XT, CAP, 1024>(L, s); break;
+        case 2048: launch_local_w<VT, XT, CAP, 2048>(L, s); break;
+        case 4096: launch_local_w<VT, XT, CAP, 4096>(L, s); break;
+        default: launch_local_w<VT, XT, CAP, 0>(L, s); break;
     }
 }
 
-void run_stage(napspmv_plan_s *p, int stage, const void *v, void *w, hipStream_t s) {
+template <typename XT>
+void launch_hop_scatter(const napspmv_plan_s *p, const Ws &ws, const XT *v, hipStream_t s) {
+    using namespace napspmv;
+    if (p->E > 0 && ws.recv != ws.send)
+        k_copy<XT><<<blocks_for(p->E), kBlock, 0, s>>>((int32_t)p->E, static_cast<const XT *>(ws.send),
+                                                     static_cast<XT *>(ws.recv));
+    const uint32_t nb1 = blocks_for(p->H), nb2 = blocks_for(p->Gon);
+    if (nb1 + nb2 > 0)
+        k_scatter2<XT><<<nb1 + nb2, kBlock, 0, s>>>(
+            (int32_t)p->H, p->d_ssrc, p->d_sdst, static_cast<const XT *>(ws.recv),
+            (int32_t)p->Gon, p->d_lsrc, p->d_ldst, v, static_cast<XT *>(ws.ghost), nb1);
+}
+
+template <typename VT, typename XT, int CAP>
+void launch_cap(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, int stage,
+                const XT *v, XT *w, hipStream_t s, int64_t task0, int64_t n_tasks, int64_t blk0,
+                int64_t n_blk) {
+    if (stage == NAPSPMV_STAGE_LOCAL) {
+        launch_local<VT, XT, CAP>(p->cur_window, local_view<VT, XT>(p, sc, ws, v, w, task0, n_tasks), s);
+        return;
+    }
+    if (p->hp.mode == NAPSPMV_NAP) launch_hop_scatter<XT>(p, ws, v, s);
+    if (p->hp.nnz_off > 0 && n_blk > 0)
+        napspmv::k_remote<VT, XT, CAP><<<(uint32_t)n_blk, napspmv::kBlock, 0, s>>>(
+            remote_view<VT, XT>(p, sc, ws, w, blk0, n_blk));
+}
+
+template <typename VT, typename XT>
+void launch_stage(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, int stage,
+                  const XT *v, XT *w, hipStream_t s, int64_t task0, int64_t n_tasks, int64_t blk0,
+                  int64_t n_blk) {
+    switch (p->cur_block_nnz) {
+        case 1024: launch_cap<VT, XT, 1024>(p, sc, ws, stage, v, w, s, task0, n_tasks, blk0, n_blk); break;
+        case 2048: launch_cap<VT, XT, 2048>(p, sc, ws, stage, v, w, s, task0, n_tasks, blk0, n_blk); break;
+        default: launch_cap<VT, XT, 4096>(p, sc, ws, stage, v, w, s, task0, n_tasks, blk0, n_blk); break;
+    }
+}
+
+// One stage over the task range [task0, task0 + n_tasks) and the
+// off-process block range [blk0, blk0 + n_blk) of schedules `sc`.
+void run_stage(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, int stage,
+               const void *v, void *w, hipStream_t s, int64_t task0, int64_t n_tasks, int64_t blk0,
+               int64_t n_blk) {
     switch (p->hp.dtype) {
         case NAPSPMV_F64:
-            launch_stage<double, double>(p, stage, static_cast<const double *>(v),
-                                         static_cast<double *>(w), s);
+            launch_stage<double, double>(p, sc, ws, stage, static_cast<const double *>(v),
+                                         static_cast<double *>(w), s, task0, n_tasks, blk0, n_blk);
             break;
         case NAPSPMV_F32:
-            launch_stage<float, float>(p, stage, static_cast<const float *>(v),
-                                       static_cast<float *>(w), s);
+            launch_stage<float, float>(p, sc, ws, stage, static_cast<const float *>(v),
+                                       static_cast<float *>(w), s, task0, n_tasks, blk0, n_blk);
             break;
         default:
-            launch_stage<uint16_t, float>(p, stage, static_cast<const float *>(v),
-                                          static_cast<float *>(w), s);
+            launch_stage<uint16_t, float>(p, sc, ws, stage, static_cast<const float *>(v),
+                                          static_cast<float *>(w), s, task0, n_tasks, blk0, n_blk);
             break;
     }
     HIP_OK(hipGetLastError());
 }
 
-int check_apply(napspmv_plan_t plan, const void *v, void *w) {
+void run_apply(const napspmv_plan_s *p, const Ws &ws, const void *v, void *w, hipStream_t s) {
+    const Schedules &sc = p->sched;
+    run_stage(p, sc, ws, NAPSPMV_STAGE_LOCAL, v, w, s, 0, sc.n_tasks, 0, sc.n_off);
+    run_stage(p, sc, ws, NAPSPMV_STAGE_REMOTE, v, w, s, 0, sc.n_tasks, 0, sc.n_off);
+}
+
+int check_vectors(napspmv_plan_t plan, const void *v, void *w) {
     if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
     if (!plan->on_device) return fail(NAPSPMV_EINVAL, "plan was built with NAPSPMV_HOST_ONLY");
     if (!v || !w) return fail(NAPSPMV_EINVAL, "v or w is NULL");
@@ -337,6 +498,12 @@ int check_apply(napspmv_plan_t plan, const void *v, void *w) {
     const char *a = static_cast<const char *>(v);
     const char *b = static_cast<const char *>(w);
     if (a < b + bytes && b < a + bytes) return fail(NAPSPMV_EINVAL, "v and w overlap");
+    return NAPSPMV_OK;
+}
+
+int check_ws(const void *ws) {
+    if (ws && (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+        return fail(NAPSPMV_EINVAL, "workspace must be 256-byte aligned");
     return NAPSPMV_OK;
 }
 
@@ -364,17 +531,154 @@ void fill_stats(const napspmv_plan_s *p, napspmv_stats_t *s) {
     s->upload_seconds = p->upload_s;
 }
 
-template <typename F>
-int guarded(F &&f) {
-    try {
-        return f();
-    } catch (const Error &e) {
-        return fail(e.code, e.what());
-    } catch (const std::bad_alloc &) {
-        return fail(NAPSPMV_ENOMEM, "host allocation failed");
-    } catch (const std::exception &e) {
-        return fail(NAPSPMV_EINVAL, e.what());
+// ---- batched launches -----------------------------------------------------------
+
+// Descriptor table of a batch: the block prefix arrays of the three
+// launches, then one view per product for each launch, each part 256-byte
+// aligned.
+struct BatchTable {
+    size_t pre_local = 0, pre_scatter = 0, pre_remote = 0, local = 0, scatter = 0, remote = 0, total = 0;
+};
+
+template <typename VT, typename XT>
+BatchTable batch_table(int count) {
+    BatchTable t;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (size_t)align_up((int64_t)(off + bytes));
+        return at;
+    };
+    t.pre_local = take(sizeof(int32_t) * (count + 1));
+    t.pre_scatter = take(sizeof(int32_t) * (count + 1));
+    t.pre_remote = take(sizeof(int32_t) * (count + 1));
+    t.local = take(sizeof(napspmv::LocalView<VT, XT>) * count);
+    t.scatter = take(sizeof(napspmv::ScatterView<XT>) * count);
+    t.remote = take(sizeof(napspmv::RemoteView<VT, XT>) * count);
+    t.total = off;
+    return t;
+}
+
+size_t batch_bytes(int count) {
+    return std::max(batch_table<double, double>(count).total,
+                    std::max(batch_table<float, float>(count).total,
+                             batch_table<uint16_t, float>(count).total));
+}
+
+template <typename VT, typename XT, int CAP, int W>
+void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, void *const *ws,
+                  const void *const *v, void *const *w, hipStream_t s) {
+    using namespace napspmv;
+    const BatchTable t = batch_table<VT, XT>(count);
+    char *h = static_cast<char *>(B->h_desc);
+    char *d = static_cast<char *>(B->d_desc);
+    int32_t *pl = reinterpret_cast<int32_t *>(h + t.pre_local);
+    int32_t *ps = reinterpret_cast<int32_t *>(h + t.pre_scatter);
+    int32_t *pr = reinterpret_cast<int32_t *>(h + t.pre_remote);
+    auto *lv = reinterpret_cast<LocalView<VT, XT> *>(h + t.local);
+    auto *sv = reinterpret_cast<ScatterView<XT> *>(h + t.scatter);
+    auto *rv = reinterpret_cast<RemoteView<VT, XT> *>(h + t.remote);
+    pl[0] = ps[0] = pr[0] = 0;
+    bool any_nap = false;
+    for (int i = 0; i < count; ++i) {
+        const napspmv_plan_s *p = plans[i];
+        const Ws wp = ws_ptrs(p, ws && ws[i] ? ws[i] : p->d_ws);
+        lv[i] = local_view<VT, XT>(p, p->sched, wp, static_cast<const XT *>(v[i]),
+                                   static_cast<XT *>(w[i]), 0, p->sched.n_tasks);
+        sv[i] = scatter_view<XT>(p, wp, static_cast<const XT *>(v[i]));
+        rv[i] = remote_view<VT, XT>(p, p->sched, wp, static_cast<XT *>(w[i]), 0,
+                                    p->hp.nnz_off > 0 ? p->sched.n_off : 0);
+        const bool nap = p->hp.mode == NAPSPMV_NAP;
+        any_nap = any_nap || nap;
+        pl[i + 1] = pl[i] + lv[i].n_tasks;
+        ps[i + 1] = ps[i] + (nap ? (int32_t)(blocks_for(p->H) + blocks_for(p->Gon)) : 0);
+        pr[i + 1] = pr[i] + rv[i].n_blocks;
     }
+    HIP_OK(hipMemcpyAsync(d, h, t.total, hipMemcpyHostToDevice, s));
+    if (pl[count] > 0)
+        k_local_batch<VT, XT, CAP, W><<<(uint32_t)pl[count], kBlock, 0, s>>>(
+            reinterpret_cast<const LocalView<VT, XT> *>(d + t.local),
+            reinterpret_cast<const int32_t *>(d + t.pre_local), count);
+    if (any_nap && ps[count] > 0)
+        k_scatter_batch<XT><<<(uint32_t)ps[count], kBlock, 0, s>>>(
+            reinterpret_cast<const ScatterView<XT> *>(d + t.scatter),
+            reinterpret_cast<const int32_t *>(d + t.pre_scatter), count);
+    if (pr[count] > 0)
+        k_remote_batch<VT, XT, CAP><<<(uint32_t)pr[count], kBlock, 0, s>>>(
+            reinterpret_cast<const RemoteView<VT, XT> *>(d + t.remote),
+            reinterpret_cast<const int32_t *>(d + t.pre_remote), count);
+    HIP_OK(hipGetLastError());
+}
+
+template <typename VT, typename XT, int CAP>
+void batch_launch_cap(int win, napspmv_batch_s *B, int count, const napspmv_plan_t *plans,
+                      void *const *ws, const void *const *v, void *const *w, hipStream_t s) {
+    switch (win) {
+        case 1024: batch_launch<VT, XT, CAP, 1024>(B, count, plans, ws, v, w, s); break;
+        case 2048: batch_launch<VT, XT, CAP, 2048>(B, count, plans, ws, v, w, s); break;
+        case 4096: batch_launch<VT, XT, CAP, 4096>(B, count, plans, ws, v, w, s); break;
+        default: batch_launch<VT, XT, CAP, 0>(B, count, plans, ws, v, w, s); break;
+    }
+}
+
+template <typename VT, typename XT>
+void batch_launch_t(int cap, int win, napspmv_batch_s *B, int count, const napspmv_plan_t *plans,
+                    void *const *ws, const void *const *v, void *const *w, hipStream_t s) {
+    switch (cap) {
+        case 1024: batch_launch_cap<VT, XT, 1024>(win, B, count, plans, ws, v, w, s); break;
+        case 2048: batch_launch_cap<VT, XT, 2048>(win, B, count, plans, ws, v, w, s); break;
+        default: batch_launch_cap<VT, XT, 4096>(win, B, count, plans, ws, v, w, s); break;
+    }
+}
+
+// ---- autotuner --------------------------------------------------------------------
+
+std::mutex g_tune_mutex;
+
+// Cache key: the device and the workload's shape (not its values).
+std::string tune_key(const napspmv_plan_s *p) {
+    hipDeviceProp_t prop;
+    std::string dev = "gpu";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) dev = prop.gcnArchName;
+    std::ostringstream k;
+    k << dev << ";n=" << p->hp.n << ";nnz=" << p->hp.nnz << ";np=" << p->hp.n_p << ";ppn="
+      << p->hp.ppn << ";mode=" << p->hp.mode << ";dtype=" << p->hp.dtype << ";G=" << p->G
+      << ";on=" << p->hp.nnz_on;
+    std::string s = k.str();
+    std::replace(s.begin(), s.end(), ' ', '_');
+    return s;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int out[3]) {
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string k;
+        int a, b, c;
+        if (in >> k >> a >> b >> c && k == key) {
+            out[0] = a;
+            out[1] = b;
+            out[2] = c;
+            found = true;       // the last entry of a key wins
+        }
+    }
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const int v[3], double ms) {
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    std::ofstream f(path, std::ios::app);
+    f << key << ' ' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << ms << '\n';
+}
+
+bool valid_cfg(const int c[3]) {
+    return (c[0] == 1024 || c[0] == 2048 || c[0] == 4096) &&
+           (c[1] == 0 || c[1] == 1024 || c[1] == 2048 || c[1] == 4096) && c[2] >= 1 && c[2] <= 4096;
 }
 
 }  // namespace
@@ -416,24 +720,265 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
 }
 
 int napspmv_apply_stage(napspmv_plan_t plan, int stage, const void *v, void *w, void *stream) {
-    int rc = check_apply(plan, v, w);
+    int rc = check_vectors(plan, v, w);
     if (rc) return rc;
     if (stage != NAPSPMV_STAGE_LOCAL && stage != NAPSPMV_STAGE_REMOTE)
         return fail(NAPSPMV_EINVAL, "unknown stage");
     return guarded([&]() {
         DeviceGuard g(plan->device);
-        run_stage(plan, stage, v, w, static_cast<hipStream_t>(stream));
+        const Schedules &sc = plan->sched;
+        run_stage(plan, sc, ws_ptrs(plan, plan->d_ws), stage, v, w,
+                  static_cast<hipStream_t>(stream), 0, sc.n_tasks, 0, sc.n_off);
+        return NAPSPMV_OK;
+    });
+}
+
+int napspmv_apply_ws(napspmv_plan_t plan, void *ws, const void *v, void *w, void *stream) {
+    int rc = check_vectors(plan, v, w);
+    if (rc) return rc;
+    if ((rc = check_ws(ws))) return rc;
+    return guarded([&]() {
+        DeviceGuard g(plan->device);
+        run_apply(plan, ws_ptrs(plan, ws ? ws : plan->d_ws), v, w, static_cast<hipStream_t>(stream));
         return NAPSPMV_OK;
     });
 }
 
 int napspmv_apply(napspmv_plan_t plan, const void *v, void *w, void *stream) {
-    int rc = check_apply(plan, v, w);
+    return napspmv_apply_ws(plan, nullptr, v, w, stream);
+}
+
+int64_t napspmv_plan_workspace_bytes(napspmv_plan_t plan) {
+    if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
+    return ws_layout(plan).total;
+}
+
+int napspmv_plan_prepare_partitions(napspmv_plan_t plan) {
+    if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
+    if (!plan->on_device) return fail(NAPSPMV_EINVAL, "plan was built with NAPSPMV_HOST_ONLY");
+    if (plan->hp.mode != NAPSPMV_STANDARD)
+        return fail(NAPSPMV_EUNSUPPORTED, "per-partition applies need a standard-mode plan");
+    return guarded([&]() {
+        DeviceGuard g(plan->device);
+        if (!plan->part_ready) build_partitions(plan);
+        HIP_OK(hipDeviceSynchronize());
+        return NAPSPMV_OK;
+    });
+}
+
+int napspmv_apply_partition(napspmv_plan_t plan, int64_t part, const void *v, void *w,
+                            void *stream) {
+    int rc = check_vectors(plan, v, w);
+    if (rc) return rc;
+    if (!plan->part_ready) return fail(NAPSPMV_EINVAL, "call napspmv_plan_prepare_partitions first");
+    if (part < 0 || part >= plan->hp.n_p) return fail(NAPSPMV_EINVAL, "partition out of range");
+    return guarded([&]() {
+        DeviceGuard g(plan->device);
+        const Schedules &sc = plan->part;
+        const Ws wp = ws_ptrs(plan, plan->d_ws);
+        const int64_t t0 = sc.task_ptr[part], t1 = sc.task_ptr[part + 1];
+        const int64_t b0 = sc.off_ptr[part], b1 = sc.off_ptr[part + 1];
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        run_stage(plan, sc, wp, NAPSPMV_STAGE_LOCAL, v, w, s, t0, t1 - t0, b0, b1 - b0);
+        run_stage(plan, sc, wp, NAPSPMV_STAGE_REMOTE, v, w, s, t0, t1 - t0, b0, b1 - b0);
+        return NAPSPMV_OK;
+    });
+}
+
+int napspmv_batch_create(int max_count, napspmv_batch_t *out) {
+    if (!out) return fail(NAPSPMV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_count < 1 || max_count > (1 << 20)) return fail(NAPSPMV_EINVAL, "max_count out of range");
+    napspmv_batch_s *b = nullptr;
+    const int rc = guarded([&]() {
+        b = new napspmv_batch_s();
+        b->capacity = max_count;
+        HIP_OK(hipGetDevice(&b->device));
+        b->desc_bytes = batch_bytes(max_count);
+        HIP_OK(hipMalloc(&b->d_desc, b->desc_bytes));
+        HIP_OK(hipHostMalloc(&b->h_desc, b->desc_bytes, hipHostMallocDefault));
+        HIP_OK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+        *out = b;
+        return NAPSPMV_OK;
+    });
+    if (rc != NAPSPMV_OK && b) {
+        if (b->d_desc) (void)hipFree(b->d_desc);
+        if (b->h_desc) (void)hipHostFree(b->h_desc);
+        delete b;
+    }
+    return rc;
+}
+
+int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *plans,
+                        void *const *ws, const void *const *v, void *const *w, void *stream) {
+    if (!batch || !plans || !v || !w) return fail(NAPSPMV_EINVAL, "NULL argument");
+    if (count < 1 || count > batch->capacity) return fail(NAPSPMV_EINVAL, "count out of range");
+    const napspmv_plan_s *p0 = plans[0];
+    for (int i = 0; i < count; ++i) {
+        int rc = check_vectors(plans[i], v[i], w[i]);
+        if (rc) return rc;
+        if ((rc = check_ws(ws ? ws[i] : nullptr))) return rc;
+        const napspmv_plan_s *p = plans[i];
+        if (p->device != batch->device) return fail(NAPSPMV_EINVAL, "plans on different devices");
+        if (p->hp.dtype != p0->hp.dtype || p->cur_block_nnz != p0->cur_block_nnz ||
+            p->cur_window != p0->cur_window)
+            return fail(NAPSPMV_EINVAL, "a batch needs one value type, BLOCK_NNZ and VWINDOW");
+        if (p->hp.mode == NAPSPMV_NAP && (p->flags & NAPSPMV_EXCHANGE_COPY))
+            return fail(NAPSPMV_EUNSUPPORTED, "batched applies receive NAP messages in place");
+    }
+    return guarded([&]() {
+        DeviceGuard g(batch->device);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // the descriptor table is reused: the previous batch must be done with it
+        if (batch->pending) HIP_OK(hipEventSynchronize(batch->done));
+        switch (p0->hp.dtype) {
+            case NAPSPMV_F64:
+                batch_launch_t<double, double>(p0->cur_block_nnz, p0->cur_window, batch, count,
+                                               plans, ws, v, w, s);
+                break;
+            case NAPSPMV_F32:
+                batch_launch_t<float, float>(p0->cur_block_nnz, p0->cur_window, batch, count,
+                                             plans, ws, v, w, s);
+                break;
+            default:
+                batch_launch_t<uint16_t, float>(p0->cur_block_nnz, p0->cur_window, batch, count,
+                                                plans, ws, v, w, s);
+                break;
+        }
+        HIP_OK(hipEventRecord(batch->done, s));
+        batch->pending = true;
+        return NAPSPMV_OK;
+    });
+}
+
+int napspmv_batch_destroy(napspmv_batch_t batch) {
+    if (!batch) return NAPSPMV_OK;
+    try {
+        DeviceGuard g(batch->device);
+        if (batch->pending) (void)hipEventSynchronize(batch->done);
+        if (batch->done) (void)hipEventDestroy(batch->done);
+        if (batch->d_desc) (void)hipFree(batch->d_desc);
+        if (batch->h_desc) (void)hipHostFree(batch->h_desc);
+    } catch (const Error &) {
+    }
+    delete batch;
+    return NAPSPMV_OK;
+}
+
+int napspmv_graph_create(napspmv_plan_t plan, const void *v, void *w, void **graph_out) {
+    if (!graph_out) return fail(NAPSPMV_EINVAL, "graph_out is NULL");
+    *graph_out = nullptr;
+    int rc = check_vectors(plan, v, w);
     if (rc) return rc;
     return guarded([&]() {
         DeviceGuard g(plan->device);
-        run_stage(plan, NAPSPMV_STAGE_LOCAL, v, w, static_cast<hipStream_t>(stream));
-        run_stage(plan, NAPSPMV_STAGE_REMOTE, v, w, static_cast<hipStream_t>(stream));
+        hipStream_t s = nullptr;
+        HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        try {
+            HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                run_apply(plan, ws_ptrs(plan, plan->d_ws), v, w, s);
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &graph);
+                throw;
+            }
+            HIP_OK(hipStreamEndCapture(s, &graph));
+            HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        } catch (...) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipStreamDestroy(s);
+            throw;
+        }
+        (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(s);
+        *graph_out = exec;
+        return NAPSPMV_OK;
+    });
+}
+
+int napspmv_graph_launch(void *graph, void *stream) {
+    if (!graph) return fail(NAPSPMV_EINVAL, "graph is NULL");
+    return guarded([&]() {
+        HIP_OK(hipGraphLaunch(static_cast<hipGraphExec_t>(graph), static_cast<hipStream_t>(stream)));
+        return NAPSPMV_OK;
+    });
+}
+
+int napspmv_graph_destroy(void *graph) {
+    if (graph) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph));
+    return NAPSPMV_OK;
+}
+
+int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *stream, int reps,
+                          const char *cache_path, double *best_ms) {
+    int rc = check_vectors(plan, v, w);
+    if (rc) return rc;
+    if (reps < 1) reps = 5;
+    return guarded([&]() {
+        DeviceGuard g(plan->device);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const std::string key = tune_key(plan);
+        int cfg[3];
+        if (cache_lookup(cache_path, key, cfg) && valid_cfg(cfg)) {
+            plan->block_nnz = cfg[0];
+            plan->window = cfg[1];
+            plan->bands = cfg[2];
+            refresh_schedules(plan);
+            HIP_OK(hipDeviceSynchronize());
+            if (best_ms) *best_ms = -1.0;
+            return NAPSPMV_OK;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        const int ab = plan->auto_bands;
+        std::vector<int> band_opts = {ab};
+        if (plan->hp.mode == NAPSPMV_STANDARD) {
+            if (ab > 1) band_opts.push_back(std::max(1, ab / 2));
+            band_opts.push_back(std::min(4096, ab * 2));
+        }
+        double best = 1e30;
+        int best_cfg[3] = {cur_cap(plan), cur_win(plan), cur_bands(plan)};
+        try {
+            for (int cap : {1024, 2048, 4096})
+                for (int win : {0, 1024, 2048, 4096})
+                    for (int bands : band_opts) {
+                        plan->block_nnz = cap;
+                        plan->window = win;
+                        plan->bands = bands;
+                        refresh_schedules(plan);
+                        const Ws wp = ws_ptrs(plan, plan->d_ws);
+                        run_apply(plan, wp, v, w, s);            // warm-up
+                        HIP_OK(hipEventRecord(e0, s));
+                        for (int r = 0; r < reps; ++r) run_apply(plan, wp, v, w, s);
+                        HIP_OK(hipEventRecord(e1, s));
+                        HIP_OK(hipEventSynchronize(e1));
+                        float ms = 0;
+                        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                        const double per = ms / reps;
+                        if (per < best) {
+                            best = per;
+                            best_cfg[0] = cap;
+                            best_cfg[1] = win;
+                            best_cfg[2] = bands;
+                        }
+                    }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        plan->block_nnz = best_cfg[0];
+        plan->window = best_cfg[1];
+        plan->bands = best_cfg[2];
+        refresh_schedules(plan);
+        HIP_OK(hipDeviceSynchronize());
+        cache_store(cache_path, key, best_cfg, best);
+        if (best_ms) *best_ms = best;
         return NAPSPMV_OK;
     });
 }
@@ -465,14 +1010,15 @@ int napspmv_plan_ghosts(napspmv_plan_t plan, int64_t *ghost_ptr, int32_t *ghost_
     return NAPSPMV_OK;
 }
 
-int napspmv_plan_read_ghost_values(napspmv_plan_t plan, void *out, void *stream) {
+int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *ws, void *out, void *stream) {
     if (!plan || !out) return fail(NAPSPMV_EINVAL, "plan or out is NULL");
     if (!plan->on_device) return fail(NAPSPMV_EINVAL, "plan was built with NAPSPMV_HOST_ONLY");
     return guarded([&]() {
         DeviceGuard g(plan->device);
         HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+        const Ws wp = ws_ptrs(plan, ws ? const_cast<void *>(ws) : plan->d_ws);
         if (plan->G > 0)
-            HIP_OK(hipMemcpy(out, plan->d_ghost, (size_t)(plan->G * vec_bytes(plan->hp.dtype)),
+            HIP_OK(hipMemcpy(out, wp.ghost, (size_t)(plan->G * vec_bytes(plan->hp.dtype)),
                              hipMemcpyDeviceToHost));
         return NAPSPMV_OK;
     });
@@ -512,9 +1058,9 @@ int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value) {
 int napspmv_plan_get_param(napspmv_plan_t plan, int param) {
     if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
     switch (param) {
-        case NAPSPMV_PARAM_BLOCK_NNZ: return plan->block_nnz >= 0 ? plan->block_nnz : plan->auto_block_nnz;
-        case NAPSPMV_PARAM_GATHER_BANDS: return plan->bands >= 0 ? plan->bands : plan->auto_bands;
-        case NAPSPMV_PARAM_VWINDOW: return plan->window >= 0 ? plan->window : plan->auto_window;
+        case NAPSPMV_PARAM_BLOCK_NNZ: return cur_cap(plan);
+        case NAPSPMV_PARAM_GATHER_BANDS: return cur_bands(plan);
+        case NAPSPMV_PARAM_VWINDOW: return cur_win(plan);
         default: return fail(NAPSPMV_EINVAL, "unknown parameter");
     }
 }
