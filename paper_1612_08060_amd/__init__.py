@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "Graph", "Batch", "NapspmvError", "load_library", "LIB_PATH", "MODES",
+__all__ = ["Plan", "Graph", "Batch", "Server", "NapspmvError", "load_library", "LIB_PATH", "MODES",
            "DTYPES", "PHASES",
            "STAGE_LOCAL", "STAGE_REMOTE", "set_device_budget", "device_bytes_in_use"]
 
@@ -72,6 +72,16 @@ _SIGS = {
     "napspmv_graph_launch": (I32, [P, P]),
     "napspmv_graph_destroy": (I32, [P]),
     "napspmv_plan_autotune": (I32, [P, P, P, P, I32, ctypes.c_char_p, P]),
+    "napspmv_server_create": (I32, [I32, I32, I64, P]),
+    "napspmv_server_add_plan": (I32, [P, P, P]),
+    "napspmv_server_submit": (I32, [P, I32, P, P, P]),
+    "napspmv_server_poll": (I64, [P]),
+    "napspmv_server_wait": (I32, [P, I64]),
+    "napspmv_server_request_info": (I32, [P, I64, P, P, P]),
+    "napspmv_server_replay": (I32, [P, I64, P, P, P, P, P, P]),
+    "napspmv_server_workspace_bytes": (I64, [P]),
+    "napspmv_server_last_error": (ctypes.c_char_p, []),
+    "napspmv_server_destroy": (I32, [P]),
     "napspmv_plan_set_param": (I32, [P, I32, I32]),
     "napspmv_plan_get_param": (I32, [P, I32]),
     "napspmv_plan_destroy": (I32, [P]),
@@ -348,6 +358,79 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None:
             load_library().napspmv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scheck(rc: int):
+    if rc < 0:
+        raise NapspmvError(int(rc), load_library().napspmv_server_last_error().decode())
+
+
+class Server:
+    """The serving engine (napspmv_server_*): resident plans, slots on their
+    own streams, workspace budget, continuous batching."""
+
+    def __init__(self, slots: int = 4, max_batch: int = 16, workspace_budget: int = 0):
+        h = ctypes.c_void_p()
+        _scheck(load_library().napspmv_server_create(int(slots), int(max_batch),
+                                                     int(workspace_budget), ctypes.byref(h)))
+        self._h = h
+        self.plans = []
+
+    def add(self, plan: Plan) -> int:
+        i = ctypes.c_int()
+        _scheck(load_library().napspmv_server_add_plan(self._h, plan._h, ctypes.byref(i)))
+        self.plans.append(plan)
+        return i.value
+
+    def submit(self, pid: int, v, w) -> int:
+        p = self.plans[pid]
+        t = ctypes.c_int64()
+        _scheck(load_library().napspmv_server_submit(self._h, int(pid), p._vec_check(v, "v"),
+                                                     p._vec_check(w, "w"), ctypes.byref(t)))
+        return t.value
+
+    def poll(self) -> int:
+        r = load_library().napspmv_server_poll(self._h)
+        _scheck(r)
+        return int(r)
+
+    def wait(self, ticket: int):
+        _scheck(load_library().napspmv_server_wait(self._h, int(ticket)))
+
+    def info(self, ticket: int):
+        s, d, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        _scheck(load_library().napspmv_server_request_info(self._h, int(ticket), ctypes.byref(s),
+                                                           ctypes.byref(d), ctypes.byref(b)))
+        return s.value, d.value, b.value
+
+    def replay(self, ids, arrival_ns, vs, ws_out):
+        """Replay an arrival trace natively; returns (latency_ns, batch_sizes)."""
+        n = len(ids)
+        ids_a = np.ascontiguousarray(ids, dtype=np.int32)
+        arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+        P_ = ctypes.c_void_p * n
+        hv = P_(*[self.plans[i]._vec_check(v, "v").value for i, v in zip(ids, vs)])
+        hw = P_(*[self.plans[i]._vec_check(w, "w").value for i, w in zip(ids, ws_out)])
+        lat = np.empty(n, np.int64)
+        bs = np.empty(n, np.int32)
+        _scheck(load_library().napspmv_server_replay(self._h, n, ids_a.ctypes.data, arr.ctypes.data,
+                                                     hv, hw, lat.ctypes.data, bs.ctypes.data))
+        return lat, bs
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(load_library().napspmv_server_workspace_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().napspmv_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

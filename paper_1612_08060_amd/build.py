@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libnapspmv.so")
-SOURCES = ["plan_build.cpp", "schedule.cpp", "napspmv.hip"]
+SOURCES = ["plan_build.cpp", "schedule.cpp", "napspmv.hip", "server.hip"]
 ARCH = "gfx950"
 
 

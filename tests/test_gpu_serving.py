@@ -1,0 +1,107 @@
+"""The serving engine (napspmv_server_*) on an MI355X: many resident plans of
+mixed value types and modes, requests admitted into slots as slots and
+workspace memory free up, batched per kernel group.  Every request's result
+must be bitwise the result of the same apply done alone."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1612_08060_amd as nap
+from workloads import (bf16_bits, kkt_like, laplacian_2d, laplacian_3d, poisson_arrivals,
+                       random_pattern, stencil_27, to_f32, vec_uniform)
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _mats():
+    specs = [(kkt_like(6000, 3), 16, 4, "standard", "f64"),
+             (laplacian_2d(90, 40), 8, 4, "nap", "f64"),
+             (laplacian_3d(24, 20, 10), 16, 16, "standard", "f32"),
+             (stencil_27(20000), 32, 16, "nap", "f32"),
+             (kkt_like(9000, 4), 48, 16, "nap", "bf16"),
+             (random_pattern(400, 0.02, 6, empty_rows=4), 4, 2, "standard", "bf16"),
+             (laplacian_2d(64, 64), 16, 4, "standard", "f64"),
+             (kkt_like(30000, 5), 64, 16, "standard", "f32")]
+    out = []
+    for a, n_p, ppn, mode, dt in specs:
+        val = {"f64": a.val, "f32": to_f32(a.val), "bf16": bf16_bits(a.val)}[dt]
+        out.append((a, nap.Plan(a.rowptr, a.col, val, a.n, n_p, ppn, mode=mode, dtype=dt), dt))
+    return out
+
+
+def _vec(x, dt):
+    return torch.from_numpy(np.ascontiguousarray(x if dt == "f64" else to_f32(x))).to(DEV)
+
+
+def _requests(mats, n, seed):
+    rng = np.random.default_rng(seed)
+    ids = rng.integers(0, len(mats), size=n)
+    vs = [_vec(vec_uniform(mats[i][0].n, 100 + k), mats[i][2]) for k, i in enumerate(ids)]
+    return ids, vs
+
+
+def _solo(mats, ids, vs):
+    out = []
+    for i, v in zip(ids, vs):
+        w = torch.empty_like(v)
+        mats[i][1].apply(v, w)
+        out.append(w)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("slots,max_batch,budget", [(2, 8, 0), (4, 3, 0), (1, 1, 0),
+                                                    (3, 6, 2 << 20)])
+def test_submit_poll_matches_solo(slots, max_batch, budget):
+    mats = _mats()
+    ids, vs = _requests(mats, 60, seed=slots * 10 + max_batch)
+    ref = _solo(mats, ids, vs)
+    srv = nap.Server(slots=slots, max_batch=max_batch, workspace_budget=budget)
+    pids = [srv.add(p) for _, p, _ in mats]
+    outs = [torch.full_like(v, float("nan")) for v in vs]
+    tickets = [srv.submit(pids[i], v, w) for i, v, w in zip(ids, vs, outs)]
+    srv.wait(tickets[-1])
+    for t in tickets:
+        srv.wait(t)
+    torch.cuda.synchronize()
+    sizes = []
+    for k, t in enumerate(tickets):
+        sub, done, bs = srv.info(t)
+        assert done >= sub and 1 <= bs <= max_batch
+        sizes.append(bs)
+        assert torch.equal(outs[k], ref[k]), k
+    if max_batch > 1:
+        assert max(sizes) > 1                 # requests were batched
+    if budget:
+        assert srv.workspace_bytes <= budget
+    srv.close()
+    for _, p, _ in mats:
+        p.close()
+
+
+def test_replay_trace_matches_solo():
+    mats = _mats()
+    srv = nap.Server(slots=4, max_batch=8)
+    pids = [srv.add(p) for _, p, _ in mats]
+    ids, arrival = poisson_arrivals(200, 20000.0, len(mats), seed=9)
+    vs = [_vec(vec_uniform(mats[i][0].n, 500 + k), mats[i][2]) for k, i in enumerate(ids)]
+    ref = _solo(mats, ids, vs)
+    outs = [torch.full_like(v, float("nan")) for v in vs]
+    lat, bs = srv.replay([pids[i] for i in ids], arrival, vs, outs)
+    torch.cuda.synchronize()
+    assert np.all(lat > 0) and np.all(bs >= 1)
+    for k in range(len(ids)):
+        assert torch.equal(outs[k], ref[k]), k
+    srv.close()
+    for _, p, _ in mats:
+        p.close()
+
+
+def test_server_rejects_bad_arguments():
+    with pytest.raises(nap.NapspmvError):
+        nap.Server(slots=0)
+    srv = nap.Server(slots=1, max_batch=1)
+    with pytest.raises(nap.NapspmvError):
+        srv.wait(5)
+    srv.close()

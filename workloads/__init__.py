@@ -24,7 +24,8 @@ import numpy as np
 __all__ = [
     "CSR", "Workload", "laplacian_2d", "laplacian_3d", "stencil_27", "kkt_like",
     "random_pattern", "vec_uniform", "vec_normal", "to_f32", "bf16_bits",
-    "bf16_to_f32", "lognormal_blocks", "config", "digest", "CONFIG_NAMES",
+    "bf16_to_f32", "lognormal_blocks", "config", "digest", "CONFIG_NAMES", "serving_mix",
+    "poisson_arrivals",
 ]
 
 
@@ -226,6 +227,49 @@ class Workload:
     row_starts: np.ndarray | None = None   # explicit block boundaries, or None
     dtypes: tuple = ("f64",)
     meta: dict = field(default_factory=dict)
+
+
+def serving_mix(count: int = 64, seed: int = 5, n_lo: float = 1e4, n_hi: float = 2e6):
+    """Resident matrices of a serving workload.  Matrix k uses generator
+    k mod 4 (2D 5-point, 3D 7-point, KKT-like, 3D 27-point) at a size drawn
+    log-uniform in [n_lo, n_hi] (snapped to the generator's grid), value type
+    floor(k/4) mod 3 (float64, float32, bfloat16), ppn 16 and
+    n_p = 16 * max(1, round(N / 32768)).  Returns a list of Workload."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(count):
+        target = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        kind = k % 4
+        if kind == 0:
+            e = max(16, int(round(target ** 0.5)))
+            a = laplacian_2d(e, e)
+            name = f"laplace2d_{e}"
+        elif kind == 1:
+            e = max(8, int(round(target ** (1 / 3))))
+            a = laplacian_3d(e, e, e)
+            name = f"laplace3d_{e}"
+        elif kind == 2:
+            n = max(4096, int(target))
+            a = kkt_like(n, 1000 + k, band=min(512, n // 8))
+            name = f"kkt_like_{n}"
+        else:
+            n = max(4096, int(target))
+            a = stencil_27(n)
+            name = f"stencil27_{n}"
+        dtype = ("f64", "f32", "bf16")[(k // 4) % 3]
+        n_p = 16 * max(1, int(round(a.n / 32768)))
+        out.append(Workload(name, a, n_p, 16, vec_uniform(a.n, 2000 + k), dtypes=(dtype,)))
+    return out
+
+
+def poisson_arrivals(n: int, rate_per_s: float, n_mats: int, seed: int):
+    """Request trace: (matrix ids uniform over n_mats, arrival times in ns of
+    a Poisson process of the given rate)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate_per_s, size=n)
+    t = np.cumsum(gaps) * 1e9
+    ids = rng.integers(0, n_mats, size=n)
+    return ids.astype(np.int32), (t - t[0]).astype(np.int64)
 
 
 CONFIG_NAMES = {
