@@ -119,6 +119,146 @@ def time_apply(plan, v, w, steps, warmup, torch, nap):
     return (t1 - t0) * 1e3 / steps, sum(local) / steps, sum(remote) / steps
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time_ms(torch, fn, reps):
+    """Average ms of fn() over reps calls, HIP events on the current stream."""
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(torch, nap, dev, reps=20):
+    """256 uneven row blocks of a 27-point stencil, float32 values: the whole
+    product as one graph-captured launch pair (autotuned), against one launch
+    pair per block (eager, and captured in one graph)."""
+    import numpy as np
+    from workloads import config, to_f32
+    wl = config(4)
+    a = wl.csr
+    p = nap.Plan(a.rowptr, a.col, to_f32(a.val), a.n, wl.n_p, wl.ppn, mode="standard",
+                 dtype="f32", row_starts=wl.row_starts)
+    v = torch.from_numpy(to_f32(wl.v)).to(dev)
+    w = torch.empty_like(v)
+    default_ms = _time_ms(torch, lambda: p.apply(v, w), reps)
+    tune_ms = p.autotune(v, w, reps=3)
+    tuning = {k: p.get_param(k) for k in ("block_nnz", "window", "bands")}
+    g = p.graph(v, w)
+    batched_ms = _time_ms(torch, g.launch, reps)
+    torch.cuda.synchronize()
+    w_batched = w.clone()
+    p.prepare_partitions()
+    w2 = torch.empty_like(v)
+
+    def parts():
+        for t in range(wl.n_p):
+            p.apply_partition(t, v, w2)
+    parts_eager_ms = _time_ms(torch, parts, max(3, reps // 4))
+    cg = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    with torch.cuda.stream(cs):
+        parts()
+        cs.synchronize()
+        with torch.cuda.graph(cg, stream=cs):
+            parts()
+    torch.cuda.synchronize()
+    parts_graph_ms = _time_ms(torch, cg.replay, reps)
+    same = bool(torch.equal(w_batched, w2))
+    st = p.stats
+    nbytes = spmv_bytes(st, 4, 4) + exchange_bytes(st, 4)
+    g.close()
+    p.close()
+    sizes = np.diff(wl.row_starts)
+    return {"workload": wl.name, "n": a.n, "nnz": a.nnz, "blocks": wl.n_p,
+            "block_rows_min_median_max": [int(sizes.min()), int(np.median(sizes)), int(sizes.max())],
+            "dtype": "f32", "bytes_per_apply": nbytes,
+            "batched_graph_ms": round(batched_ms, 5),
+            "batched_gbs": round(nbytes / (batched_ms * 1e-3) / 1e9, 1),
+            "default_tuning_ms": round(default_ms, 5), "autotuned": tuning,
+            "autotune_best_ms": round(tune_ms, 5),
+            "per_block_launches_eager_ms": round(parts_eager_ms, 4),
+            "per_block_launches_graph_ms": round(parts_graph_ms, 4),
+            "speedup_vs_per_block_eager": round(parts_eager_ms / batched_ms, 2),
+            "speedup_vs_per_block_graph": round(parts_graph_ms / batched_ms, 2),
+            "per_block_equals_batched_bitwise": same}
+
+
+def bench_serving(torch, nap, dev, n_req=3000, warm=300, rhos=(0.5, 0.8, 0.95)):
+    """Poisson-arrival requests on 64 resident matrices of mixed size, type
+    and value precision, served with continuous batching (4 slots, batches
+    up to 16, 16 GiB workspace budget), against each request served alone in
+    arrival order on the plain float64 path."""
+    import numpy as np
+    from workloads import bf16_bits, poisson_arrivals, serving_mix, to_f32
+    mix = serving_mix()
+    vals = {"f64": lambda x: x, "f32": to_f32, "bf16": bf16_bits}
+    served, plain, vin, vin64, nbytes = [], [], [], [], []
+    for wl in mix:
+        a, dt = wl.csr, wl.dtypes[0]
+        served.append(nap.Plan(a.rowptr, a.col, vals[dt](a.val), a.n, wl.n_p, wl.ppn,
+                               mode="standard", dtype=dt))
+        plain.append(nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="standard"))
+        vin.append(torch.from_numpy(wl.v if dt == "f64" else to_f32(wl.v)).to(dev))
+        vin64.append(torch.from_numpy(wl.v).to(dev))
+        st = served[-1].stats
+        sa = {"f64": 8, "f32": 4, "bf16": 2}[dt]
+        sv = 8 if dt == "f64" else 4
+        nbytes.append(spmv_bytes(st, sa, sv) + exchange_bytes(st, sv))
+    # serial float64 capacity: mean service time over a uniform matrix choice
+    w64 = [torch.empty_like(x) for x in vin64]
+    service = [_time_ms(torch, lambda k=k: plain[k].apply(vin64[k], w64[k]), 5)
+               for k in range(len(mix))]
+    capacity = 1000.0 / float(np.mean(service))          # requests per second
+    out = {"matrices": len(mix), "rows_min_max": [min(w.csr.n for w in mix), max(w.csr.n for w in mix)],
+           "nnz_total": int(sum(w.csr.nnz for w in mix)), "requests": n_req, "discarded": warm,
+           "serial_f64_mean_service_ms": round(float(np.mean(service)), 4),
+           "serial_f64_capacity_rps": round(capacity, 1), "runs": []}
+    for rho in rhos:
+        ids, arr = poisson_arrivals(n_req, rho * capacity, len(mix), seed=5)
+        row = {"rho": rho, "rate_rps": round(rho * capacity, 1)}
+        for label, plans, vecs, slots, batch in (("serial_f64", plain, vin64, 1, 1),
+                                                 ("served", served, vin, 4, 16)):
+            srv = nap.Server(slots=slots, max_batch=batch, workspace_budget=16 << 30)
+            pids = [srv.add(pl) for pl in plans]
+            outs = [torch.empty_like(vecs[i]) for i in ids]
+            lat, bs = srv.replay([pids[i] for i in ids], arr, [vecs[i] for i in ids], outs)
+            torch.cuda.synchronize()
+            keep = slice(warm, None)
+            l_us = lat[keep] / 1e3
+            span_s = (arr[-1] + lat[-1] - arr[warm]) / 1e9
+            total_b = float(sum(nbytes[i] for i in ids[keep]))
+            row[label] = {"p50_us": round(float(np.percentile(l_us, 50)), 1),
+                          "p99_us": round(float(np.percentile(l_us, 99)), 1),
+                          "mean_batch": round(float(bs[keep].mean()), 2),
+                          "gbs": round(total_b / span_s / 1e9, 1)}
+            if label == "served":
+                errs = {}
+                for k in range(warm, min(n_req, warm + 200)):
+                    i = int(ids[k])
+                    dt = mix[i].dtypes[0]
+                    ref = torch.empty_like(vin64[i])
+                    plain[i].apply(vin64[i], ref)
+                    r = ref.cpu().numpy()
+                    e = float(np.linalg.norm(outs[k].cpu().numpy().astype(np.float64) - r)
+                              / max(np.linalg.norm(r), 1e-300))
+                    errs[dt] = max(errs.get(dt, 0.0), e)
+                row[label]["max_rel_err_vs_f64"] = errs
+            srv.close()
+        out["runs"].append(row)
+    for pl in served + plain:
+        pl.close()
+    return out
+
+
 def cpu_baseline(wl, budget_s):
     """The oracle's float64 CSR SpMV (plain C, OpenMP) on the host cores."""
     import numpy as np
@@ -152,6 +292,8 @@ def main():
     ap.add_argument("--window", type=int, default=-1)
     ap.add_argument("--bands", type=int, default=-1)
     ap.add_argument("--extras", type=int, default=1, help="also time NAP mode and reduced precision")
+    ap.add_argument("--batched", type=int, default=1, help="also run the batched 256-block workload")
+    ap.add_argument("--serving", type=int, default=1, help="also run the serving workload")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="end with three plain 1 GiB device copies (counter calibration)")
@@ -269,6 +411,12 @@ def main():
             pr.close()
         result["extras"] = ext
 
+    if args.batched:
+        log("batched 256-block workload ...")
+        result["batched"] = bench_batched(torch, nap, dev)
+    if args.serving:
+        log("serving workload ...")
+        result["serving"] = bench_serving(torch, nap, dev)
     if args.cpu_seconds > 0:
         log("timing the CPU oracle ...")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

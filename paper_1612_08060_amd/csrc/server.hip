@@ -195,8 +195,10 @@ void admit(napspmv_server_s *s) {
             R.state = 1;
             R.batch = n;
         }
-        const int rc = napspmv_batch_apply(sl.batch, n, plans.data(), wss.data(), vs.data(),
-                                           ws_out.data(), sl.stream);
+        // a lone request takes the plain apply path (no descriptor table)
+        const int rc = n == 1 ? napspmv_apply_ws(plans[0], wss[0], vs[0], ws_out[0], sl.stream)
+                              : napspmv_batch_apply(sl.batch, n, plans.data(), wss.data(),
+                                                    vs.data(), ws_out.data(), sl.stream);
         if (rc != NAPSPMV_OK) throw Error(rc, std::string("batch apply: ") + napspmv_last_error());
         HIP_SOK(hipEventRecord(sl.done, sl.stream));
         sl.reqs = take;
