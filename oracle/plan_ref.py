@@ -40,6 +40,27 @@ Readings taken where the paper is silent, garbled or at odds with itself:
 * The off_node -> on_node step forwards values received in the inter-node
   step (algorithm NAPSpMV passes ``v|R`` there; the received buffer is
   meant), and the receiving process uses its own received values directly.
+
+Variants (none is the default; each leaves every ghost value and w unchanged):
+
+* ``owner_map``: the other mapping section 4.1 names but does not explore:
+  partner node m of n is sent by the process of n that owns the most indices
+  of E(n, m) (ties: the lowest local number).  U is unchanged.
+* ``split``: the rule section 4.1 states for a node with fewer partners than
+  processes per node, where one partner is spread over several local
+  processes so that every process takes part (the worked example's table
+  does not do this, hence not the default).  Read as: the i-th of k < ppn
+  partners (T order) is sent by local processes i, i + k, i + 2k, ... < ppn,
+  E(n, m) cut into that many contiguous pieces of near-equal length in index
+  order, piece c sent by the c-th of them; on the receiving side the i'-th
+  of k' < ppn senders (U order) is received by local processes ppn-1-i',
+  ppn-1-i'-k', ..., and piece c goes to the (c mod count)-th of those.  A
+  node with at least ppn partners (senders) keeps the mapping's choice.
+* ``dedup``: not in the paper; the fully local step does not carry an index
+  that the on_node -> off_node step already carries between the same two
+  processes (the receiving process uses that copy for its own product too).
+  This is not what Table example_L2 prints either (it keeps (1,1) -> (0,1):
+  {3}, which that step also carries).
 """
 from __future__ import annotations
 
@@ -48,6 +69,7 @@ from collections import defaultdict
 import numpy as np
 
 PHASES = ("INTER", "L0", "L1", "L2")
+VARIANTS = frozenset({"owner_map", "dedup", "split"})
 
 
 class Layout:
@@ -146,9 +168,9 @@ def node_sets(csr, lay: Layout):
     return N, {k: sorted(v) for k, v in E.items()}
 
 
-def mapping(lay: Layout, N: dict, E: dict):
+def mapping(lay: Layout, N: dict, E: dict, owner_map: bool = False):
     """T((p, n)) and U((p, n)) of section 4.1 under the mapping rule stated
-    there (see the module docstring for the reading).
+    there (see the module docstring for the reading and the variant).
 
     Returns (T, U, t_rank, u_rank): T and U map rank -> sorted node list;
     t_rank[(n, m)] is the rank on n sending to node m, u_rank[(n, m)] the rank
@@ -162,7 +184,12 @@ def mapping(lay: Layout, N: dict, E: dict):
     t_rank, u_rank = {}, {}
     for n in range(lay.n_nodes):
         for k, m in enumerate(order(n, N[n])):
-            r = lay.rank(k % lay.ppn, n)
+            if owner_map:
+                held = [sum(1 for j in E[(n, m)] if lay.owner(j) == lay.rank(p, n))
+                        for p in range(lay.ppn)]
+                r = lay.rank(held.index(max(held)), n)
+            else:
+                r = lay.rank(k % lay.ppn, n)
             T[r].append(m)
             t_rank[(n, m)] = r
         senders = [m for m in range(lay.n_nodes) if n in N[m]]
@@ -175,21 +202,62 @@ def mapping(lay: Layout, N: dict, E: dict):
     return T, U, t_rank, u_rank
 
 
-def nap_plan(csr, lay: Layout) -> dict:
-    """Every set of section 4: N, E, T, U, G, I and the three local steps."""
+def split_messages(lay: Layout, N: dict, E: dict, t_rank: dict, u_rank: dict):
+    """The ``split`` variant: {(sender, receiver): piece of E(n, m)}, each
+    piece sent in its own message.  Only a node with fewer partners (or
+    senders) than processes splits; elsewhere the sender and receiver are
+    those of the mapping (``t_rank``, ``u_rank``)."""
+    def order(n, partners):
+        return sorted(partners, key=lambda m: (-len(E.get((n, m), ())), m))
+
+    senders_of, receivers_of = {}, {}
+    for n in range(lay.n_nodes):
+        part = order(n, N[n])
+        k = len(part)
+        for i, m in enumerate(part):
+            senders_of[(n, m)] = ([lay.rank(p, n) for p in range(i, lay.ppn, k)]
+                                  if k < lay.ppn else [t_rank[(n, m)]])
+        snd = order(n, [m for m in range(lay.n_nodes) if n in N[m]])
+        k2 = len(snd)
+        for i, m in enumerate(snd):
+            receivers_of[(m, n)] = ([lay.rank(p, n) for p in range(lay.ppn - 1 - i, -1, -k2)]
+                                    if k2 < lay.ppn else [u_rank[(m, n)]])
+    msgs = {}
+    for (n, m), idx in E.items():
+        s_list, r_list = senders_of[(n, m)], receivers_of[(n, m)]
+        c = len(s_list)
+        L = len(idx)
+        for piece in range(c):
+            part = idx[piece * L // c:(piece + 1) * L // c]
+            if part:
+                msgs[(s_list[piece], r_list[piece % len(r_list)])] = set(part)
+    return msgs
+
+
+def nap_plan(csr, lay: Layout, variant=()) -> dict:
+    """Every set of section 4: N, E, T, U, G, I and the three local steps,
+    under the default readings or the named variants."""
+    variant = set(variant)
+    if variant - VARIANTS:
+        raise ValueError(f"unknown variant(s) {sorted(variant - VARIANTS)}")
     N, E = node_sets(csr, lay)
-    T, U, t_rank, u_rank = mapping(lay, N, E)
+    T, U, t_rank, u_rank = mapping(lay, N, E, owner_map="owner_map" in variant)
 
     # G((p, n)) = {(q, m) | m in T((p, n)), n in U((q, m))};  I = E(n, m).
     G = defaultdict(set)
     I = {}
-    for s in range(lay.n_p):
-        n = lay.node(s)
-        for m in T[s]:
-            for q in (lay.rank(x, m) for x in range(lay.ppn)):
-                if n in U[q]:
-                    G[s].add(q)
-                    I[(s, q)] = set(E[(n, m)])
+    if "split" in variant:
+        I = split_messages(lay, N, E, t_rank, u_rank)
+        for (s, q) in I:
+            G[s].add(q)
+    else:
+        for s in range(lay.n_p):
+            n = lay.node(s)
+            for m in T[s]:
+                for q in (lay.rank(x, m) for x in range(lay.ppn)):
+                    if n in U[q]:
+                        G[s].add(q)
+                        I[(s, q)] = set(E[(n, m)])
 
     # on_node -> off_node: owners hand their values to the inter-node sender.
     J0 = defaultdict(set)
@@ -217,9 +285,12 @@ def nap_plan(csr, lay: Layout) -> dict:
         t, r = lay.owner(i), lay.owner(j)
         if r != t and lay.node(r) == lay.node(t):
             J2[(r, t)].add(j)
+    if "dedup" in variant:
+        for key in list(J2):
+            J2[key] -= J0.get(key, set())
 
     return {
-        "mode": "nap",
+        "mode": "nap", "variant": sorted(variant),
         "N": N, "E": E, "T": T, "U": U,
         "t_rank": t_rank, "u_rank": u_rank,
         "G": {s: sorted(G[s]) for s in range(lay.n_p)},
@@ -229,11 +300,11 @@ def nap_plan(csr, lay: Layout) -> dict:
     }
 
 
-def plan(csr, lay: Layout, mode: str) -> dict:
+def plan(csr, lay: Layout, mode: str, variant=()) -> dict:
     if mode == "standard":
         return standard_plan(csr, lay)
     if mode == "nap":
-        return nap_plan(csr, lay)
+        return nap_plan(csr, lay, variant)
     raise ValueError(mode)
 
 

@@ -17,6 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 PHASES = ("INTER", "L0", "L1", "L2")
+VARIANTS = frozenset({"owner_map", "dedup", "split"})
 
 
 def row_starts(n: int, n_p: int, given=None) -> np.ndarray:
@@ -93,9 +94,13 @@ def _rank_within(group: np.ndarray) -> np.ndarray:
     return k - np.maximum.accumulate(start)
 
 
-def nap_plan(csr, n_p: int, ppn: int, given_starts=None) -> dict:
+def nap_plan(csr, n_p: int, ppn: int, given_starts=None, variant=()) -> dict:
     """E(n, m), the T/U mapping, the inter-node messages I and the three
-    local steps of section 4, under the readings of ``plan_ref``."""
+    local steps of section 4, under the readings and variants of
+    ``plan_ref`` (module docstring there)."""
+    variant = set(variant)
+    if variant - VARIANTS:
+        raise ValueError(f"unknown variant(s) {sorted(variant - VARIANTS)}")
     starts = row_starts(csr.n, n_p, given_starts)
     n_nodes = n_p // ppn
     t, j = ghost_pairs(csr, starts)
@@ -107,15 +112,21 @@ def nap_plan(csr, n_p: int, ppn: int, given_starts=None) -> dict:
     nn = np.int64(n_nodes)
     key = np.unique((src_node[offn] * nn + dst_node[offn]) * csr.n + j[offn])
     e_pair, e_j = key // csr.n, key % csr.n
-    e_n, e_m = e_pair // nn, e_pair % nn
     pairs, sizes = np.unique(e_pair, return_counts=True)
     p_n, p_m = pairs // nn, pairs % nn
 
     # T: partners of n by (|E(n, m)| desc, m asc) -> local k mod ppn.
     o = np.lexsort((p_m, -sizes, p_n))
-    k = _rank_within(p_n[o])
-    t_loc = np.empty(pairs.size, dtype=np.int64)
-    t_loc[o] = k % ppn
+    kT = np.empty(pairs.size, dtype=np.int64)
+    kT[o] = _rank_within(p_n[o])
+    t_loc = kT % ppn
+    if "owner_map" in variant:
+        # the local process owning the most indices of E(n, m) (lowest on ties)
+        pair_of_e = np.searchsorted(pairs, e_pair)
+        own_loc = owner(starts, e_j) % ppn
+        counts = np.zeros((pairs.size, ppn), dtype=np.int64)
+        np.add.at(counts, (pair_of_e, own_loc), 1)
+        t_loc = counts.argmax(axis=1)
     # U: senders m of node n by (|E(n, m)| desc, m asc) -> local ppn-1-(k mod ppn).
     vol = {}
     for a, b, s in zip(p_n.tolist(), p_m.tolist(), sizes.tolist()):
@@ -123,14 +134,35 @@ def nap_plan(csr, n_p: int, ppn: int, given_starts=None) -> dict:
     back = np.array([vol.get((b, a), 0) for a, b in zip(p_n.tolist(), p_m.tolist())],
                     dtype=np.int64)
     o = np.lexsort((p_n, -back, p_m))
-    k = _rank_within(p_m[o])
-    u_loc = np.empty(pairs.size, dtype=np.int64)
-    u_loc[o] = ppn - 1 - (k % ppn)
+    kU = np.empty(pairs.size, dtype=np.int64)
+    kU[o] = _rank_within(p_m[o])
+    u_loc = ppn - 1 - (kU % ppn)
 
-    send_rank = p_n * ppn + t_loc
-    recv_rank = p_m * ppn + u_loc
     pair_of = np.searchsorted(pairs, e_pair)
-    i_src, i_dst = send_rank[pair_of], recv_rank[pair_of]
+    if "split" in variant:
+        # pieces of E(n, m) over several senders/receivers when a node has
+        # fewer partners (senders) than processes per node
+        n_part = np.bincount(p_n, minlength=n_nodes)[p_n]          # k of the sender node
+        n_send = np.bincount(p_m, minlength=n_nodes)[p_m]          # k' of the receiver node
+        c_snd = np.where(n_part < ppn, (ppn - kT + n_part - 1) // n_part, 1)
+        c_rcv = np.where(n_send < ppn, (ppn - kU + n_send - 1) // n_send, 1)
+        e_start = np.searchsorted(e_pair, pairs)                    # first entry of each pair
+        pos = np.arange(e_j.size) - e_start[pair_of]                # rank inside E(n, m)
+        L = sizes[pair_of]
+        c = c_snd[pair_of]
+        piece = (pos * c) // L
+        # piece containing pos: the largest k with k*L//c <= pos
+        piece = np.where(((piece + 1) * L) // c <= pos, piece + 1, piece)
+        s_loc = np.where(n_part[pair_of] < ppn, kT[pair_of] + piece * n_part[pair_of], t_loc[pair_of])
+        r_idx = piece % c_rcv[pair_of]
+        r_loc = np.where(n_send[pair_of] < ppn, ppn - 1 - kU[pair_of] - r_idx * n_send[pair_of],
+                         u_loc[pair_of])
+        i_src = p_n[pair_of] * ppn + s_loc
+        i_dst = p_m[pair_of] * ppn + r_loc
+    else:
+        send_rank = p_n * ppn + t_loc
+        recv_rank = p_m * ppn + u_loc
+        i_src, i_dst = send_rank[pair_of], recv_rank[pair_of]
 
     # on_node -> off_node: owner -> inter-node sender, deduplicated per pair.
     own = owner(starts, e_j)
@@ -138,32 +170,38 @@ def nap_plan(csr, n_p: int, ppn: int, given_starts=None) -> dict:
     l0 = np.unique((own[need] * n_p + i_src[need]) * csr.n + e_j[need])
     l0_src, l0_dst, l0_j = l0 // csr.n // n_p, (l0 // csr.n) % n_p, l0 % csr.n
 
-    # off_node -> on_node: receiver of E(n, m) -> each other user t on m.
-    gpair = src_node[offn] * nn + dst_node[offn]
-    q = recv_rank[np.searchsorted(pairs, gpair)]
+    # off_node -> on_node: receiver of j on the destination node -> each other user.
+    recv_key = np.unique((dst_node_of := p_m[pair_of]) * csr.n + e_j)
+    recv_sorted = i_dst[np.argsort(dst_node_of * csr.n + e_j, kind="stable")]
+    gq = np.searchsorted(recv_key, dst_node[offn] * csr.n + j[offn])
+    q = recv_sorted[gq]
     tt, jj = t[offn], j[offn]
     fwd = q != tt
 
     # on_node -> on_node: direct, the standard intra-node messages.
-    onn = (~offn)
+    onn = ~offn
+    l2_src, l2_dst, l2_j = r[onn], t[onn], j[onn]
+    if "dedup" in variant:
+        drop = np.isin((l2_src * n_p + l2_dst) * csr.n + l2_j,
+                       (l0_src * n_p + l0_dst) * csr.n + l0_j)
+        l2_src, l2_dst, l2_j = l2_src[~drop], l2_dst[~drop], l2_j[~drop]
     return {
-        "mode": "nap", "starts": starts, "ghost_t": t, "ghost_j": j,
-        "pairs": pairs, "pair_sizes": sizes, "send_rank": send_rank,
-        "recv_rank": recv_rank, "n_nodes": n_nodes,
+        "mode": "nap", "variant": sorted(variant), "starts": starts, "ghost_t": t,
+        "ghost_j": j, "pairs": pairs, "pair_sizes": sizes, "n_nodes": n_nodes,
         "phases": {
             "INTER": _segments(i_src, i_dst, e_j),
             "L0": _segments(l0_src, l0_dst, l0_j),
             "L1": _segments(q[fwd], tt[fwd], jj[fwd]),
-            "L2": _segments(r[onn], t[onn], j[onn]),
+            "L2": _segments(l2_src, l2_dst, l2_j),
         },
     }
 
 
-def plan(csr, n_p: int, ppn: int, mode: str, given_starts=None) -> dict:
+def plan(csr, n_p: int, ppn: int, mode: str, given_starts=None, variant=()) -> dict:
     if mode == "standard":
         return standard_plan(csr, n_p, ppn, given_starts)
     if mode == "nap":
-        return nap_plan(csr, n_p, ppn, given_starts)
+        return nap_plan(csr, n_p, ppn, given_starts, variant)
     raise ValueError(mode)
 
 

@@ -69,7 +69,11 @@ def simulate_standard(csr, lay: Layout, plan: dict, v):
 
 
 def simulate_nap(csr, lay: Layout, plan: dict, v):
-    """NAPSpMV on every rank.  Returns (ghost values per rank, w)."""
+    """NAPSpMV on every rank.  Returns (ghost values per rank, w).
+
+    Under the ``dedup`` variant a process also uses, for its own product,
+    the values it receives in the on_node -> off_node step."""
+    dedup = "dedup" in plan.get("variant", ())
     gh = ghosts(csr, lay)
     v_loc = _local_v(lay, v)
     ph = plan["phases"]
@@ -126,6 +130,11 @@ def simulate_nap(csr, lay: Layout, plan: dict, v):
             if j in slots:
                 counts[j] += 1
                 slots[j] = x
+        if dedup:
+            for j, x in b_lnl[t].items():    # on-node values received for packing
+                if j in slots and lay.node(lay.owner(j)) == lay.node(t):
+                    counts[j] += 1
+                    slots[j] = x
         _check(t, gh[t], counts, slots, v)
         ghost_vals.append(slots)
     w = _split_product(csr, lay, v_loc, ghost_vals, three_way=True)
