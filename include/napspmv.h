@@ -85,6 +85,23 @@ extern "C" {
 #define NAPSPMV_EXCHANGE_COPY 0x2u  /* NAP: copy the send buffer to a separate receive
                                        buffer (models the inter-node hop) instead of
                                        receiving in place */
+/* NAP plan variants (section 4.1; none is the default).  They change which
+ * process sends, receives or forwards what, hence the plan's messages and
+ * statistics; the ghost values and w are the same bit for bit.  EINVAL with
+ * NAPSPMV_STANDARD. */
+#define NAPSPMV_NAP_OWNER_MAP 0x4u  /* the inter-node sender of E(n, m) is the local
+                                       process of n owning most of its indices
+                                       (lowest local number on ties), instead of the
+                                       process the volume ranking assigns */
+#define NAPSPMV_NAP_SPLIT     0x8u  /* a node with k < ppn partners sends its i-th
+                                       partner's E(n, m) through locals i, i+k, ...,
+                                       cut into near-equal contiguous pieces; a node
+                                       with k' < ppn senders receives the i'-th through
+                                       locals ppn-1-i', ppn-1-i'-k', ... (piece c to the
+                                       (c mod count)-th) */
+#define NAPSPMV_NAP_DEDUP     0x10u /* the fully local (L2) step leaves out the indices
+                                       the on_node -> off_node (L0) step already carries
+                                       between the same two processes */
 
 /* Stages of an apply; napspmv_apply runs LOCAL then REMOTE.  LOCAL is one
  * launch: the exchange gather (standard: every ghost from its owner; NAP:

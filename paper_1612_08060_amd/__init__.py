@@ -24,6 +24,7 @@ DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 PHASES = ("INTER", "L0", "L1", "L2")
 STAGE_LOCAL, STAGE_REMOTE = 0, 1
 HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
+VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10}
 PARAMS = {"block_nnz": 0, "bands": 1, "window": 2}
 _VAL_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
@@ -135,13 +136,18 @@ class Plan:
     ``rowptr`` (int64, n+1), ``col`` (int32) and ``val`` (float64 for "f64",
     float32 for "f32", uint16 bfloat16 bits for "bf16") describe A in CSR.
     ``mode`` is "standard" or "nap".  ``host_only`` builds the plan on the
-    host without touching a GPU (stats and exports only).
+    host without touching a GPU (stats and exports only).  ``variant`` names
+    NAP plan variants ("owner_map", "split", "dedup"; section 4.1): they
+    change the messages, not the result.
     """
 
     def __init__(self, rowptr, col, val, n: int, n_p: int, ppn: int, mode: str = "standard",
                  dtype: str = "f64", row_starts=None, host_only: bool = False,
-                 exchange_copy: bool = False):
+                 exchange_copy: bool = False, variant=()):
         lib = load_library()
+        unknown = set(variant) - set(VARIANTS)
+        if unknown:
+            raise ValueError(f"unknown variant(s) {sorted(unknown)}; known: {sorted(VARIANTS)}")
         if mode not in MODES:
             raise ValueError(f"mode must be one of {list(MODES)}")
         if dtype not in DTYPES:
@@ -157,6 +163,9 @@ class Plan:
         self.n, self.n_p, self.ppn, self.mode, self.dtype = int(n), int(n_p), int(ppn), mode, dtype
         self.host_only = bool(host_only)
         flags = (HOST_ONLY if host_only else 0) | (EXCHANGE_COPY if exchange_copy else 0)
+        for name in variant:
+            flags |= VARIANTS[name]
+        self.variant = tuple(sorted(set(variant)))
         handle = ctypes.c_void_p()
         st = Stats()
         self._h = None

@@ -690,14 +690,16 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
                         uint32_t flags, napspmv_plan_t *plan_out, napspmv_stats_t *stats_out) {
     if (!plan_out) return fail(NAPSPMV_EINVAL, "plan_out is NULL");
     *plan_out = nullptr;
-    if (flags & ~(NAPSPMV_HOST_ONLY | NAPSPMV_EXCHANGE_COPY))
+    if (flags & ~(NAPSPMV_HOST_ONLY | NAPSPMV_EXCHANGE_COPY | NAPSPMV_NAP_OWNER_MAP |
+                  NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP))
         return fail(NAPSPMV_EINVAL, "unknown flag bits");
     napspmv_plan_s *p = nullptr;
     const int rc = guarded([&]() {
         p = new napspmv_plan_s();
         p->flags = flags;
         const auto t0 = std::chrono::steady_clock::now();
-        napspmv::build_plan(p->hp, rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts);
+        napspmv::build_plan(p->hp, rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts,
+                            flags & (NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP));
         const auto t1 = std::chrono::steady_clock::now();
         p->build_s = std::chrono::duration<double>(t1 - t0).count();
         p->G = p->hp.ghost_ptr.back();

@@ -16,6 +16,11 @@
 //    (what n sends to each of them, 0 if nothing), the k-th received by local
 //    process ppn - 1 - (k mod ppn).  No partner is split over processes.
 //  * I((p, n), (q, m)) = E(n, m) between the T-process and the U-process.
+//  * Variants (flags): the owner mapping (the T-process of a pair is the
+//    local process owning most of E(n, m)), the split of a partner over
+//    several processes when a node has fewer partners or senders than ppn
+//    (section 4.1), and the fully local step deduplicated against the
+//    on_node -> off_node step.
 //  * on_node -> off_node (L0): the indices of the inter-node messages sent by
 //    s that s does not own, unique per (owner, s).
 //  * off_node -> on_node (L1): every off-node ghost j of t arrives at the
@@ -38,6 +43,8 @@ namespace {
 // Sizes stay below 2^31 - 2^16 so that every 32-bit index a kernel forms
 // (an index plus at most one block's worth of work) is representable.
 constexpr int64_t kInt32Max = 0x7fffffff - 0x10000;
+
+constexpr uint32_t kVariantFlags = NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP;
 
 struct Owner {
     const std::vector<int64_t> &starts;
@@ -150,8 +157,11 @@ void release_device_arrays(HostPlan &hp) {
 
 void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
-                const int64_t *row_starts) {
+                const int64_t *row_starts, uint32_t variant) {
     validate(rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts);
+    if (variant & ~kVariantFlags) throw Error(NAPSPMV_EINVAL, "unknown plan variant flag");
+    if (variant && mode != NAPSPMV_NAP)
+        throw Error(NAPSPMV_EINVAL, "plan variant flags apply to NAP plans only");
     hp.n = n;
     hp.nnz = rowptr[n];
     hp.n_p = n_p;
@@ -301,9 +311,17 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
         // Node pairs (n -> m) with |E(n, m)|, grouped by destination m, n ascending.
         struct Pair {
             int32_t n, m;
-            int64_t start, len;     // range in Em[m]
+            int64_t start, len;        // range in Em[m]
+            int64_t kT = 0, kU = 0;    // rank among n's partners / among m's senders
+            int32_t send_local = 0, recv_local = 0;
+            int64_t piece_begin = 0, piece_end = 0;
+        };
+        // One inter-node message: a contiguous piece of E(n, m) (the whole set
+        // unless the split variant cuts it).
+        struct Piece {
             int32_t send_rank, recv_rank;
-            int64_t send_off;       // offset of the message in the send buffer
+            int64_t start, len;        // range in Em[m]
+            int64_t send_off = 0;      // offset in the send buffer
         };
         std::vector<Pair> pairs;
         std::vector<int64_t> pairs_of_m(nn + 1, 0);
@@ -315,13 +333,19 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
                 const int64_t end_row = hp.starts[(src_node + 1) * ppn];
                 size_t b = a + 1;
                 while (b < e.size() && e[b] < end_row) ++b;
-                pairs.push_back(Pair{(int32_t)src_node, (int32_t)m, (int64_t)a, (int64_t)(b - a),
-                                     -1, -1, 0});
+                Pair p;
+                p.n = (int32_t)src_node;
+                p.m = (int32_t)m;
+                p.start = (int64_t)a;
+                p.len = (int64_t)(b - a);
+                pairs.push_back(p);
                 a = b;
             }
             pairs_of_m[m + 1] = (int64_t)pairs.size();
         }
         const int64_t np_ = (int64_t)pairs.size();
+        std::vector<int64_t> partners(nn, 0);    // |N(n)|
+        for (const Pair &p : pairs) ++partners[p.n];
         // |E(a, b)| lookup through pairs sorted by (n, m).
         std::vector<int64_t> by_src(np_);
         std::iota(by_src.begin(), by_src.end(), 0);
@@ -346,7 +370,19 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
         for (int64_t k = 0, run = 0; k < np_; ++k) {
             run = (k > 0 && pairs[ord[k]].n == pairs[ord[k - 1]].n) ? run + 1 : 0;
             Pair &p = pairs[ord[k]];
-            p.send_rank = (int32_t)(p.n * ppn + run % ppn);
+            p.kT = run;
+            p.send_local = (int32_t)(run % ppn);
+        }
+        if (variant & NAPSPMV_NAP_OWNER_MAP) {
+            // The local process of n owning the most of E(n, m), lowest on ties.
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t x = 0; x < np_; ++x) {
+                Pair &p = pairs[x];
+                std::vector<int64_t> held(ppn, 0);
+                const int32_t *e = Em[p.m].data() + p.start;
+                for (int64_t a = 0; a < p.len; ++a) ++held[owner(e[a]) - (int64_t)p.n * ppn];
+                p.send_local = (int32_t)(std::max_element(held.begin(), held.end()) - held.begin());
+            }
         }
         // U: senders of m by (|E(m, n)| desc, n asc) -> local ppn-1-(k mod ppn).
         std::vector<int64_t> back(np_);
@@ -361,41 +397,78 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
         for (int64_t k = 0, run = 0; k < np_; ++k) {
             run = (k > 0 && pairs[ord[k]].m == pairs[ord[k - 1]].m) ? run + 1 : 0;
             Pair &p = pairs[ord[k]];
-            p.recv_rank = (int32_t)(p.m * ppn + ppn - 1 - run % ppn);
+            p.kU = run;
+            p.recv_local = (int32_t)(ppn - 1 - run % ppn);
         }
+        // Pieces.  Under the split variant a node with k < ppn partners sends
+        // the i-th through locals i, i + k, ... < ppn, E cut into that many
+        // near-equal contiguous pieces; a node with k' < ppn senders receives
+        // the i'-th through locals ppn-1-i', ppn-1-i'-k', ..., piece c going to
+        // the (c mod count)-th of them.
+        const bool split = (variant & NAPSPMV_NAP_SPLIT) != 0;
+        std::vector<Piece> pieces;
+        pieces.reserve((size_t)np_);
+        for (int64_t x = 0; x < np_; ++x) {
+            Pair &p = pairs[x];
+            const int64_t k_snd = partners[p.n];
+            const int64_t k_rcv = pairs_of_m[p.m + 1] - pairs_of_m[p.m];
+            const bool s_split = split && k_snd < ppn, r_split = split && k_rcv < ppn;
+            const int64_t cs = s_split ? (ppn - p.kT + k_snd - 1) / k_snd : 1;
+            const int64_t cr = r_split ? (ppn - p.kU + k_rcv - 1) / k_rcv : 1;
+            p.piece_begin = (int64_t)pieces.size();
+            for (int64_t c = 0; c < cs; ++c) {
+                const int64_t a = c * p.len / cs, b = (c + 1) * p.len / cs;
+                if (b == a) continue;
+                const int64_t sl = s_split ? p.kT + c * k_snd : p.send_local;
+                const int64_t rl = r_split ? ppn - 1 - p.kU - (c % cr) * k_rcv : p.recv_local;
+                Piece q;
+                q.send_rank = (int32_t)(p.n * ppn + sl);
+                q.recv_rank = (int32_t)(p.m * ppn + rl);
+                q.start = p.start + a;
+                q.len = b - a;
+                pieces.push_back(q);
+            }
+            p.piece_end = (int64_t)pieces.size();
+        }
+        const int64_t npc = (int64_t)pieces.size();
         // INTER messages in canonical order define the send buffer layout.
-        std::vector<int64_t> canon(np_);
+        std::vector<int64_t> pair_of_piece(npc);
+        for (int64_t x = 0; x < np_; ++x)
+            for (int64_t c = pairs[x].piece_begin; c < pairs[x].piece_end; ++c) pair_of_piece[c] = x;
+        std::vector<int64_t> canon(npc);
         std::iota(canon.begin(), canon.end(), 0);
         std::sort(canon.begin(), canon.end(), [&](int64_t x, int64_t y) {
-            const Pair &a = pairs[x], &b = pairs[y];
+            const Piece &a = pieces[x], &b = pieces[y];
             return a.send_rank != b.send_rank ? a.send_rank < b.send_rank
                                               : a.recv_rank < b.recv_rank;
         });
         {
-            std::vector<MsgRef> refs(np_);
+            std::vector<MsgRef> refs(npc);
             int64_t off = 0;
-            for (int64_t k = 0; k < np_; ++k) {
-                Pair &p = pairs[canon[k]];
-                p.send_off = off;
-                off += p.len;
-                refs[k] = MsgRef{p.send_rank, p.recv_rank, Em[p.m].data() + p.start, p.len};
+            for (int64_t k = 0; k < npc; ++k) {
+                Piece &q = pieces[canon[k]];
+                q.send_off = off;
+                off += q.len;
+                refs[k] = MsgRef{q.send_rank, q.recv_rank,
+                                 Em[pairs[pair_of_piece[canon[k]]].m].data() + q.start, q.len};
             }
             finalize_phase(refs, hp.phase[NAPSPMV_PHASE_INTER]);
             hp.pack_idx = hp.phase[NAPSPMV_PHASE_INTER].idx;
         }
         // L0: per inter-node sender s, the indices it sends but does not own.
+        std::vector<std::vector<int32_t>> l0(n_p);
         {
-            std::vector<std::vector<int64_t>> pairs_of_s(n_p);
-            for (int64_t x = 0; x < np_; ++x) pairs_of_s[pairs[x].send_rank].push_back(x);
-            std::vector<std::vector<int32_t>> l0(n_p);
+            std::vector<std::vector<int64_t>> pieces_of_s(n_p);
+            for (int64_t c = 0; c < npc; ++c) pieces_of_s[pieces[c].send_rank].push_back(c);
             std::vector<std::vector<MsgRef>> l0runs(n_p);
 #pragma omp parallel for schedule(dynamic, 4)
             for (int64_t s = 0; s < n_p; ++s) {
                 std::vector<int32_t> &d = l0[s];
-                for (int64_t x : pairs_of_s[s]) {
-                    const Pair &p = pairs[x];
-                    for (int64_t a = p.start; a < p.start + p.len; ++a) {
-                        const int32_t j = Em[p.m][a];
+                for (int64_t c : pieces_of_s[s]) {
+                    const Piece &q = pieces[c];
+                    const int32_t *e = Em[pairs[pair_of_piece[c]].m].data();
+                    for (int64_t a = q.start; a < q.start + q.len; ++a) {
+                        const int32_t j = e[a];
                         if (j < hp.starts[s] || j >= hp.starts[s + 1]) d.push_back(j);
                     }
                 }
@@ -439,11 +512,16 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
                     auto it = std::lower_bound(lo, hi, n_src,
                                                [](const Pair &p, int64_t v) { return p.n < v; });
                     const Pair &p = *it;
-                    const int32_t *e = Em[m].data() + p.start;
-                    const int64_t rank = std::lower_bound(e, e + p.len, j) - e;
-                    ssrc[t].push_back((int32_t)(p.send_off + rank));
+                    const int32_t *e = Em[m].data();
+                    const int64_t at = std::lower_bound(e + p.start, e + p.start + p.len, j) - e;
+                    // the piece holding position `at` (pieces of a pair ascend)
+                    auto pb = pieces.begin() + p.piece_begin, pe = pieces.begin() + p.piece_end;
+                    const Piece &q = *(std::upper_bound(pb, pe, at, [](int64_t v, const Piece &c) {
+                                           return v < c.start;
+                                       }) - 1);
+                    ssrc[t].push_back((int32_t)(q.send_off + (at - q.start)));
                     sdst[t].push_back(slot);
-                    if (p.recv_rank != t) fwd.emplace_back(p.recv_rank, j);
+                    if (q.recv_rank != t) fwd.emplace_back(q.recv_rank, j);
                 }
                 std::stable_sort(fwd.begin(), fwd.end(),
                                  [](const std::pair<int32_t, int32_t> &a,
@@ -475,6 +553,34 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
             flatten(sdst, hp.scat_dst);
             flatten(lsrc, hp.l2_src);
             flatten(ldst, hp.l2_dst);
+        }
+        if (variant & NAPSPMV_NAP_DEDUP) {
+            // The fully local step drops what the on_node -> off_node step
+            // already carries between the same two processes (l0[t] holds the
+            // indices t receives there).  The device still fills those ghost
+            // slots from v: on one device both copies are the same read.
+            std::vector<std::vector<int32_t>> keep(n_p);
+            std::vector<std::vector<MsgRef>> runs2(n_p);
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t t = 0; t < n_p; ++t) {
+                const std::vector<int32_t> &d = l0[t];
+                for (int32_t j : gh[t])
+                    if (node_of(owner(j)) == node_of(t) && !std::binary_search(d.begin(), d.end(), j))
+                        keep[t].push_back(j);
+                const std::vector<int32_t> &g = keep[t];
+                size_t a = 0;
+                while (a < g.size()) {
+                    const int64_t r = owner(g[a]);
+                    size_t b = a + 1;
+                    while (b < g.size() && g[b] < hp.starts[r + 1]) ++b;
+                    runs2[t].push_back(MsgRef{(int32_t)r, (int32_t)t, g.data() + a, (int64_t)(b - a)});
+                    a = b;
+                }
+            }
+            std::vector<MsgRef> refs;
+            for (int64_t t = 0; t < n_p; ++t) refs.insert(refs.end(), runs2[t].begin(), runs2[t].end());
+            hp.phase[NAPSPMV_PHASE_L2] = Phase();
+            finalize_phase(refs, hp.phase[NAPSPMV_PHASE_L2]);
         }
     }
     for (int ph = 0; ph < 4; ++ph) hp.stats[ph] = phase_stats(hp.phase[ph], n_p);

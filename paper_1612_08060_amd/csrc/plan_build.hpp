@@ -63,10 +63,11 @@ struct HostPlan {
     std::vector<int32_t> l2_src, l2_dst;          // NAP: ghost[l2_dst[k]] = v[l2_src[k]]
 };
 
-// Validates the inputs and builds the plan.  Throws Error or std::bad_alloc.
+// Validates the inputs and builds the plan.  `variant` holds NAPSPMV_NAP_*
+// flags (NAP mode only).  Throws Error or std::bad_alloc.
 void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
-                const int64_t *row_starts);
+                const int64_t *row_starts, uint32_t variant);
 
 // Frees the host copies of the split matrix and device lists after upload
 // (row pointers and row windows stay: launch schedules are rebuilt from them).

@@ -1,0 +1,84 @@
+"""NAP plan variants (NAPSPMV_NAP_OWNER_MAP / SPLIT / DEDUP) in the C-ABI
+host builder: every phase, every statistic and the ghost lists equal the
+oracle's bit for bit, on random patterns, paper-shaped matrices and the
+worked example."""
+import numpy as np
+import pytest
+
+import paper_1612_08060_amd as lib
+from oracle import plan_vec
+from tests.helpers import example_2_1
+from workloads import config, random_pattern
+
+VARIANTS = [("owner_map",), ("split",), ("dedup",), ("owner_map", "split"),
+            ("owner_map", "split", "dedup")]
+
+
+def _compare(a, n_p, ppn, variant, row_starts=None):
+    ref = plan_vec.plan(a, n_p, ppn, "nap", row_starts, variant)
+    with lib.Plan(a.rowptr, a.col, a.val, a.n, n_p, ppn, mode="nap", row_starts=row_starts,
+                  host_only=True, variant=variant) as p:
+        assert p.variant == tuple(sorted(variant))
+        st = p.stats
+        for ph in lib.PHASES:
+            got, exp = p.export(ph), ref["phases"][ph]
+            for g, e in zip(got, exp):
+                assert np.array_equal(g, e), (ph, variant)
+            assert st["phases"][ph] == plan_vec.phase_stats(exp, n_p), ph
+        gp, gc = p.ghosts()
+        assert np.array_equal(gc, ref["ghost_j"])
+    return st
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_example_2_1(variant):
+    g, a = example_2_1()
+    _compare(a, 6, 2, variant)
+
+
+@pytest.mark.parametrize("n_p,ppn", [(2, 2), (4, 2), (6, 3), (8, 4), (8, 2), (12, 4), (9, 3),
+                                     (16, 8), (16, 4), (24, 8)])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_random_patterns(n_p, ppn, variant):
+    for seed in range(3):
+        a = random_pattern(30 + 9 * n_p + 7 * seed, 0.03 + 0.05 * seed,
+                           seed=500 + 31 * n_p + ppn + seed, empty_rows=seed, duplicates=seed)
+        _compare(a, n_p, ppn, variant)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_explicit_row_starts(variant):
+    a = random_pattern(120, 0.05, seed=77)
+    starts = np.array([0, 3, 20, 21, 40, 64, 90, 100, 120], np.int64)
+    _compare(a, 8, 4, variant, starts)
+
+
+@pytest.mark.parametrize("k,scale", [(1, 0), (2, 4), (3, 4), (4, 2)])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_paper_shaped_configs(k, scale, variant):
+    wl = config(k, scale=scale)
+    _compare(wl.csr, wl.n_p, wl.ppn, variant, wl.row_starts)
+
+
+def test_variants_keep_inter_node_volume():
+    """E(n, m) does not depend on the variant: the inter-node element count
+    is the same, and the default plan's L1 volume too unless split moves
+    receivers."""
+    wl = config(2, scale=4)
+    base = _compare(wl.csr, wl.n_p, wl.ppn, ())
+    for variant in VARIANTS:
+        st = _compare(wl.csr, wl.n_p, wl.ppn, variant)
+        assert st["phases"]["INTER"]["elems"] == base["phases"]["INTER"]["elems"]
+        if "split" not in variant:
+            assert st["phases"]["L1"] == base["phases"]["L1"]
+
+
+def test_variant_flags_rejected_for_standard_and_unknown():
+    a = random_pattern(20, 0.2, seed=3)
+    with pytest.raises(lib.NapspmvError) as e:
+        lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, mode="standard", host_only=True,
+                 variant=("split",))
+    assert e.value.code == -1
+    with pytest.raises(ValueError):
+        lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, mode="nap", host_only=True,
+                 variant=("nope",))
