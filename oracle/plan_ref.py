@@ -61,6 +61,8 @@ Variants (none is the default; each leaves every ghost value and w unchanged):
   processes (the receiving process uses that copy for its own product too).
   This is not what Table example_L2 prints either (it keeps (1,1) -> (0,1):
   {3}, which that step also carries).
+* ``three_way``: no change to any set; the product is summed in three parts
+  as algorithm NAPSpMV writes it (``spmv.spmv_split3``).
 """
 from __future__ import annotations
 
@@ -69,7 +71,7 @@ from collections import defaultdict
 import numpy as np
 
 PHASES = ("INTER", "L0", "L1", "L2")
-VARIANTS = frozenset({"owner_map", "dedup", "split"})
+VARIANTS = frozenset({"owner_map", "dedup", "split", "three_way"})
 
 
 class Layout:

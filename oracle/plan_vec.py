@@ -17,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 PHASES = ("INTER", "L0", "L1", "L2")
-VARIANTS = frozenset({"owner_map", "dedup", "split"})
+VARIANTS = frozenset({"owner_map", "dedup", "split", "three_way"})
 
 
 def row_starts(n: int, n_p: int, given=None) -> np.ndarray:

@@ -7,6 +7,9 @@ spmv_split  the same product in the order algorithm standard_spmv of section
             2.1 forms it on each process: local_spmv(A_on_process, v), then
             local_spmv(A_off_process, b_recv) accumulated into w (C routine
             spmv_split_ref_f64).
+spmv_split3 the order algorithm NAPSpMV of section 4.3 forms it: the
+            on_process, on_node and off_node blocks in turn, each in stored
+            order, accumulated into w (C routine spmv_split3_ref_f64).
 *_rows      the same sums for sampled rows, in Python float64 arithmetic.
 """
 from __future__ import annotations
@@ -43,6 +46,10 @@ def _load():
         lib.spmv_split_ref_f64.restype = None
         lib.spmv_split_ref_f64.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 5
                                            + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int])
+        lib.spmv_split3_ref_f64.restype = None
+        lib.spmv_split3_ref_f64.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 5
+                                            + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                               ctypes.c_int])
         lib.spmv_ref_threads.restype = ctypes.c_int
         lib.spmv_ref_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -91,6 +98,46 @@ def spmv_split(csr, v, n_p: int, row_starts=None, threads: int = 0, out=None) ->
     lib.spmv_split_ref_f64(csr.n, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
                            x.ctypes.data, w.ctypes.data, int(n_p), st.ctypes.data, int(threads))
     return w
+
+
+def spmv_split3(csr, v, n_p: int, ppn: int, row_starts=None, threads: int = 0,
+                out=None) -> np.ndarray:
+    """w = A v summed as algorithm NAPSpMV does on every process: the
+    on_process block, then the on_node block, then the off_node block, each
+    in stored order (C routine spmv_split3_ref_f64)."""
+    if n_p % ppn:
+        raise ValueError("ppn must divide n_p")
+    lib = _load()
+    rp = np.ascontiguousarray(csr.rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(csr.col, dtype=np.int32)
+    val = np.ascontiguousarray(csr.val, dtype=np.float64)
+    x = np.ascontiguousarray(v, dtype=np.float64)
+    st = block_starts(csr.n, n_p, row_starts)
+    w = np.empty(csr.n, dtype=np.float64) if out is None else out
+    lib.spmv_split3_ref_f64(csr.n, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                            x.ctypes.data, w.ctypes.data, int(n_p), st.ctypes.data, int(ppn),
+                            int(threads))
+    return w
+
+
+def spmv_split3_rows(csr, v, n_p: int, ppn: int, rows, row_starts=None) -> np.ndarray:
+    """spmv_split3 for selected rows only, in Python float64 arithmetic."""
+    st = block_starts(csr.n, n_p, row_starts)
+    out = np.empty(len(rows))
+    for o, i in enumerate(rows):
+        r = int(np.searchsorted(st, i, side="right") - 1)
+        lo, hi = int(st[r]), int(st[r + 1])
+        node = r // ppn
+        nlo, nhi = int(st[node * ppn]), int(st[(node + 1) * ppn])
+        ks = range(int(csr.rowptr[i]), int(csr.rowptr[i + 1]))
+        own = [k for k in ks if lo <= int(csr.col[k]) < hi]
+        on_node = [k for k in ks if nlo <= int(csr.col[k]) < nhi and k not in own]
+        rest = [k for k in ks if k not in own and k not in on_node]
+        s = 0.0
+        for k in own + on_node + rest:
+            s = s + float(csr.val[k]) * float(v[int(csr.col[k])])
+        out[o] = s
+    return out
 
 
 def spmv_split_rows(csr, v, n_p: int, rows, row_starts=None) -> np.ndarray:

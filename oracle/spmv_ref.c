@@ -62,6 +62,44 @@ void spmv_split_ref_f64(int64_t n, const int64_t *rowptr, const int32_t *col,
     }
 }
 
+/*
+ * The same product as algorithm NAPSpMV of section 4.3 forms it on every
+ * process r of node n = r / ppn: local_spmv(A_on_process, v) into w, then
+ * local_spmv(A_on_node, b_{l->l}) accumulated into w, then
+ * local_spmv(A_off_node, b) accumulated into w.  Row i of block r adds,
+ * sequentially from 0: the products of its stored entries whose column lies
+ * in block r, in stored order; then those whose column lies in another
+ * block of node n (rows [starts[n ppn], starts[(n+1) ppn])), in stored
+ * order; then the rest, in stored order.  Every buffer holds copies of v.
+ */
+void spmv_split3_ref_f64(int64_t n, const int64_t *rowptr, const int32_t *col,
+                         const double *val, const double *v, double *w,
+                         int64_t n_p, const int64_t *starts, int64_t ppn, int threads)
+{
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n_p; ++r) {
+        const int64_t lo = starts[r], hi = starts[r + 1];
+        const int64_t node = r / ppn;
+        const int64_t nlo = starts[node * ppn], nhi = starts[(node + 1) * ppn];
+        for (int64_t i = lo; i < hi; ++i) {
+            double s = 0.0;
+            for (int part = 0; part < 3; ++part) {
+                for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                    const int32_t j = col[k];
+                    const int own = j >= lo && j < hi;
+                    const int on_node = !own && j >= nlo && j < nhi;
+                    const int which = own ? 0 : (on_node ? 1 : 2);
+                    if (which != part) continue;
+                    double prod = val[k] * v[j];
+                    s = s + prod;
+                }
+            }
+            w[i] = s;
+        }
+    }
+}
+
 /* Number of threads an OpenMP parallel region actually uses. */
 int spmv_ref_threads(int threads)
 {

@@ -92,3 +92,46 @@ def test_split_order_differs_from_stored_order():
     v = np.ones(4)
     assert spmv.spmv(a, v)[0] == 0.0          # (1 + 2^53) - 2^53: the 1 is lost
     assert spmv_split(a, v, 2)[0] == 1.0      # (-2^53 + 1) + 2^53: exact
+
+
+def test_three_way_order_pins():
+    """The three-way product (on_process, on_node, off_node blocks in turn, as
+    NAPSpMV sums it) is exact on integer inputs, equals the two-way product
+    when no block is on-node (one process per node) or none is off-node (one
+    node), is within rounding of the dense product otherwise, and its C and
+    Python evaluations agree bit for bit."""
+    from oracle.spmv import spmv_split, spmv_split3, spmv_split3_rows
+    for seed in range(4):
+        a = random_pattern(61, 0.12, seed + 10, empty_rows=2, duplicates=4)
+        v_int = (np.arange(61) % 7 - 3).astype(np.float64)
+        for n_p, ppn in ((1, 1), (4, 2), (6, 3), (61, 61)):
+            assert np.array_equal(spmv_split3(a, v_int, n_p, ppn), brute.matvec(a, v_int))
+        a = CSR(a.n, a.rowptr, a.col, np.random.default_rng(seed).standard_normal(a.nnz))
+        v = vec_normal(61, seed)
+        for n_p in (1, 3, 6):
+            assert np.array_equal(spmv_split3(a, v, n_p, 1), spmv_split(a, v, n_p))
+            assert np.array_equal(spmv_split3(a, v, n_p, n_p), spmv_split(a, v, n_p))
+        for n_p, ppn in ((6, 2), (12, 4)):
+            w = spmv_split3(a, v, n_p, ppn, threads=2)
+            ref = brute.matvec(a, v)
+            assert np.linalg.norm(w - ref) <= 1e-14 * np.linalg.norm(ref)
+            assert np.array_equal(spmv_split3_rows(a, v, n_p, ppn, range(61)), w)
+    starts = np.array([0, 4, 5, 30, 40, 53, 61], np.int64)
+    w = spmv_split3(a, v, 6, 3, row_starts=starts)
+    assert np.array_equal(spmv_split3_rows(a, v, 6, 3, range(61), row_starts=starts), w)
+
+
+def test_three_way_order_differs_from_two_way():
+    """Planted check: row 0 on process 0 of node 0 (processes 0, 1 on node 0;
+    2, 3 on node 1; one row each) stores (col 0: 2^53), (col 2: -2^53),
+    (col 1: 1).  Two-way: 2^53, then the off-process entries in stored order,
+    -2^53 then 1, gives 1.  Three-way: 2^53, then the on-node 1 (lost to
+    rounding), then the off-node -2^53, gives 0."""
+    from oracle.spmv import spmv_split, spmv_split3
+    big = 2.0 ** 53
+    a = CSR(4, np.array([0, 3, 4, 5, 6], np.int64), np.array([0, 2, 1, 1, 2, 3], np.int32),
+            np.array([big, -big, 1.0, 1.0, 1.0, 1.0]))
+    v = np.ones(4)
+    assert spmv_split(a, v, 4)[0] == 1.0
+    assert spmv_split3(a, v, 4, 2)[0] == 0.0
+    assert spmv_split3(a, v, 4, 1)[0] == 1.0      # no on-node block: two-way order
