@@ -393,6 +393,24 @@ def main():
         }
         pn.close()
         del w2
+        # algorithm NAPSpMV's three-part product, exchange beside the on_node product
+        p3 = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="nap", dtype="f64",
+                      row_starts=wl.row_starts, variant=("three_way",))
+        w3 = torch.empty_like(v)
+        ms_3, ex_3, sp_3 = time_apply(p3, v, w3, max(10, args.steps // 2), 2, torch, nap)
+        ext["nap_three_way_f64"] = {"ms": round(ms_3, 5), "gbs": round(bn / (ms_3 * 1e-3) / 1e9, 1),
+                                    "local_ms": round(ex_3, 5), "remote_ms": round(sp_3, 5)}
+        p3.close()
+        del w3
+        # message statistics of the mapping variants (host-only plans)
+        var = {}
+        for name in ("owner_map", "split", "dedup"):
+            with nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="nap",
+                          row_starts=wl.row_starts, host_only=True, variant=(name,)) as ph:
+                q = ph.stats["phases"]
+            var[name] = {k: {"msgs": q[k]["msgs"], "elems": q[k]["elems"],
+                             "max_msgs_sent": q[k]["max_msgs_sent"]} for k in ("INTER", "L0", "L1", "L2")}
+        result["nap_variant_messages"] = var
         # reduced-precision values, float32 accumulation; error against the
         # float64 apply above (itself checked against the oracle by the tests)
         ref = w.cpu().numpy()

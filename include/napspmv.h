@@ -102,6 +102,18 @@ extern "C" {
 #define NAPSPMV_NAP_DEDUP     0x10u /* the fully local (L2) step leaves out the indices
                                        the on_node -> off_node (L0) step already carries
                                        between the same two processes */
+/* NAP three-way product (algorithm NAPSpMV, section 4.3): the same messages,
+ * but the off-process block is split into its on_node and off_node parts and
+ * each row sums its on_process, then on_node, then off_node entries (each in
+ * stored order).  The on_node product runs on the caller's stream while the
+ * inter-node hop and the scatter run on a helper stream of the plan, joined
+ * by events before the off_node product.  Float64 w then equals that
+ * three-part order bit for bit (not the two-part order of the default).
+ * The helper stream and events belong to the plan: issue the applies of one
+ * such plan from one host thread at a time (their order on the GPU is then
+ * the call order).  Batches refuse such plans (EUNSUPPORTED); servers run
+ * them alone. */
+#define NAPSPMV_NAP_THREE_WAY 0x20u
 
 /* Stages of an apply; napspmv_apply runs LOCAL then REMOTE.  LOCAL is one
  * launch: the exchange gather (standard: every ghost from its owner; NAP:
@@ -138,6 +150,7 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the plan (0 for host-only) */
     double build_seconds;    /* host wall time of the plan build */
     double upload_seconds;   /* host wall time of the device upload */
+    uint32_t flags;          /* the NAPSPMV_* plan flags the plan was built with */
 } napspmv_stats_t;
 
 /*
@@ -255,7 +268,8 @@ NAPSPMV_API int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *
  * workspaces of other plans are released to make room), and each free slot
  * then runs up to `max_batch` queued requests of one kernel group (value
  * type, BLOCK_NNZ, VWINDOW; oldest request first) as one batched launch
- * sequence.  Requests that arrive while slots are busy are admitted as slots
+ * sequence (a NAP plan with NAPSPMV_EXCHANGE_COPY or NAPSPMV_NAP_THREE_WAY
+ * always runs alone, by napspmv_apply_ws).  Requests that arrive while slots are busy are admitted as slots
  * free up, so their work overlaps the work already on the device.
  * Single-threaded: one caller drives a server.  Every result is bitwise the
  * result of napspmv_apply on the same plan and vector.

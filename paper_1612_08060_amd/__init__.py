@@ -24,7 +24,7 @@ DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 PHASES = ("INTER", "L0", "L1", "L2")
 STAGE_LOCAL, STAGE_REMOTE = 0, 1
 HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
-VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10}
+VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20}
 PARAMS = {"block_nnz": 0, "bands": 1, "window": 2}
 _VAL_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
@@ -49,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("value_bytes", ctypes.c_int64), ("nnz_on", ctypes.c_int64),
                 ("nnz_off", ctypes.c_int64), ("ghosts", ctypes.c_int64),
                 ("phase", PhaseStats * 4), ("device_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double), ("upload_seconds", ctypes.c_double)]
+                ("build_seconds", ctypes.c_double), ("upload_seconds", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -138,7 +139,9 @@ class Plan:
     ``mode`` is "standard" or "nap".  ``host_only`` builds the plan on the
     host without touching a GPU (stats and exports only).  ``variant`` names
     NAP plan variants ("owner_map", "split", "dedup"; section 4.1): they
-    change the messages, not the result.
+    change the messages, not the result; "three_way" sums each row in the
+    three parts of algorithm NAPSpMV (on_process, on_node, off_node) with the
+    inter-node hop overlapped with the on_node product.
     """
 
     def __init__(self, rowptr, col, val, n: int, n_p: int, ppn: int, mode: str = "standard",

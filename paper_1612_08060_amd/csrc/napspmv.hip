@@ -35,7 +35,8 @@ int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Schedules {
     int32_t *onblk = nullptr, *onptr = nullptr, *win = nullptr;
     int32_t *offblk = nullptr, *offptr = nullptr, *items = nullptr, *tasks = nullptr;
-    int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, bytes = 0;
+    int32_t *ndblk = nullptr, *ndptr = nullptr;     // three-way: on_node row blocks
+    int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, n_nd = 0, bytes = 0;
     // per-partition schedules only: each process's range of tasks and of
     // off-process blocks
     std::vector<int64_t> task_ptr, off_ptr;
@@ -55,6 +56,12 @@ struct napspmv_plan_s {
     void *d_val_on = nullptr, *d_val_off = nullptr;
     int32_t *d_gather = nullptr, *d_pack = nullptr;
     int32_t *d_ssrc = nullptr, *d_sdst = nullptr, *d_lsrc = nullptr, *d_ldst = nullptr;
+    // three-way plans: the on_node block, and the helper stream and events
+    // that run the inter-node hop and scatter beside the on_node product
+    int32_t *d_rp_nd = nullptr, *d_col_nd = nullptr;
+    void *d_val_nd = nullptr;
+    hipStream_t helper = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void *d_ws = nullptr;            // the plan's own workspace (ghost, send, receive)
     Schedules sched;                 // all partitions in one launch pair
     Schedules part;                  // per-partition schedules (built on request)
@@ -174,7 +181,7 @@ void charge(napspmv_plan_s *p, int64_t bytes) {
 }
 
 void free_schedules(napspmv_plan_s *p, Schedules &s) {
-    void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks};
+    void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks, s.ndblk, s.ndptr};
     for (void *q : ptrs) free_ptr(q);
     charge(p, -s.bytes);
     s = Schedules();
@@ -186,8 +193,15 @@ void free_device(napspmv_plan_s *p) {
     p->part_ready = false;
     void *ptrs[] = {p->d_rp_on, p->d_col_on, p->d_rp_off, p->d_col_off, p->d_val_on,
                     p->d_val_off, p->d_gather, p->d_pack, p->d_ssrc, p->d_sdst, p->d_lsrc,
-                    p->d_ldst, p->d_ws};
+                    p->d_ldst, p->d_ws, p->d_rp_nd, p->d_col_nd, p->d_val_nd};
     for (void *q : ptrs) free_ptr(q);
+    p->d_rp_nd = p->d_col_nd = nullptr;
+    p->d_val_nd = nullptr;
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->helper) (void)hipStreamDestroy(p->helper);
+    p->ev_fork = p->ev_join = nullptr;
+    p->helper = nullptr;
     p->d_rp_on = p->d_col_on = p->d_rp_off = p->d_col_off = nullptr;
     p->d_val_on = p->d_val_off = p->d_ws = nullptr;
     p->d_gather = p->d_pack = p->d_ssrc = p->d_sdst = p->d_lsrc = p->d_ldst = nullptr;
@@ -200,6 +214,7 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
     const HostPlan &hp = p->hp;
     int64_t b = (int64_t)(hp.rowptr_on.size() + hp.col_on.size() + hp.rowptr_off.size() +
                           hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
+    b += (int64_t)(hp.rowptr_nd.size() + hp.col_nd.size()) * 4 + (int64_t)hp.val_nd.size();
     b += (int64_t)(hp.gather_idx.size() + hp.pack_idx.size() + hp.scat_src.size() +
                    hp.scat_dst.size() + hp.l2_src.size() + hp.l2_dst.size()) * 4;
     return b + ws_layout(p).total;
@@ -208,10 +223,13 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
 void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t> &onblk,
                       const std::vector<int32_t> &onptr, const std::vector<int32_t> &wins,
                       const std::vector<int32_t> &offblk, const std::vector<int32_t> &offptr,
-                      const std::vector<int32_t> &items, const std::vector<int32_t> &tasks) {
+                      const std::vector<int32_t> &items, const std::vector<int32_t> &tasks,
+                      const std::vector<int32_t> &ndblk = {}, const std::vector<int32_t> &ndptr = {}) {
     free_schedules(p, s);
     int64_t total = 0;
     try {
+        upload(s.ndblk, ndblk, total);
+        upload(s.ndptr, ndptr, total);
         upload(s.onblk, onblk, total);
         upload(s.onptr, onptr, total);
         upload(s.win, wins, total);
@@ -230,6 +248,7 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
     s.n_off = (int64_t)offblk.size() - 1;
     s.n_items = (int64_t)items.size() / 2;
     s.n_tasks = (int64_t)tasks.size();
+    s.n_nd = ndblk.empty() ? 0 : (int64_t)ndblk.size() - 1;
 }
 
 int cur_cap(const napspmv_plan_s *p) { return p->block_nnz >= 0 ? p->block_nnz : p->auto_block_nnz; }
@@ -298,7 +317,9 @@ void refresh_schedules(napspmv_plan_s *p) {
     else
         napspmv::flat_items(p->E, kMaxItem, items);
     napspmv::merge_tasks((int64_t)items.size() / 2, (int64_t)onblk.size() - 1, tasks);
-    upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks);
+    std::vector<int32_t> ndblk, ndptr;
+    if (hp.three_way) napspmv::row_blocks(hp.rowptr_nd.data(), hp.n, cap, kMaxRowsPerBlock, ndblk, ndptr);
+    upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr);
     p->cur_block_nnz = cap;
     p->cur_window = win;
     p->cur_bands = bands;
@@ -328,6 +349,14 @@ void to_device(napspmv_plan_s *p) {
         };
         upload_bytes(p->d_val_on, hp.val_on);
         upload_bytes(p->d_val_off, hp.val_off);
+        if (hp.three_way) {
+            upload(p->d_rp_nd, hp.rowptr_nd, total);
+            upload(p->d_col_nd, hp.col_nd, total);
+            upload_bytes(p->d_val_nd, hp.val_nd);
+            HIP_OK(hipStreamCreateWithFlags(&p->helper, hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+            HIP_OK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+        }
         upload(p->d_gather, hp.gather_idx, total);
         upload(p->d_pack, hp.pack_idx, total);
         upload(p->d_ssrc, hp.scat_src, total);
@@ -376,16 +405,18 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
     return L;
 }
 
+// Off-process product view; `on_node` selects a three-way plan's on_node
+// block instead of the (off_node) off-process block.
 template <typename VT, typename XT>
 napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules &s, const Ws &ws,
-                                        XT *w, int64_t blk0, int64_t n_blk) {
+                                        XT *w, int64_t blk0, int64_t n_blk, bool on_node = false) {
     napspmv::RemoteView<VT, XT> R;
     R.n_blocks = (int32_t)n_blk;
-    R.rowblk = s.offblk + blk0;
-    R.blkptr = s.offptr + blk0;
-    R.rowptr = p->d_rp_off;
-    R.col = p->d_col_off;
-    R.val = static_cast<const VT *>(p->d_val_off);
+    R.rowblk = (on_node ? s.ndblk : s.offblk) + blk0;
+    R.blkptr = (on_node ? s.ndptr : s.offptr) + blk0;
+    R.rowptr = on_node ? p->d_rp_nd : p->d_rp_off;
+    R.col = on_node ? p->d_col_nd : p->d_col_off;
+    R.val = static_cast<const VT *>(on_node ? p->d_val_nd : p->d_val_off);
     R.ghost = static_cast<const XT *>(ws.ghost);
     R.w = w;
     return R;
@@ -424,17 +455,41 @@ void launch_local(int win, const napspmv::LocalView<VT, XT> &L, hipStream_t s) {
     }
 }
 
+// The inter-node hop (explicit copy, if any) and the scatter of received
+// values (`hop`), and the fully local gathers (`local`), into the ghost buffer.
 template <typename XT>
-void launch_hop_scatter(const napspmv_plan_s *p, const Ws &ws, const XT *v, hipStream_t s) {
+void launch_hop_scatter(const napspmv_plan_s *p, const Ws &ws, const XT *v, hipStream_t s,
+                        bool hop = true, bool local = true) {
     using namespace napspmv;
-    if (p->E > 0 && ws.recv != ws.send)
+    if (hop && p->E > 0 && ws.recv != ws.send)
         k_copy<XT><<<blocks_for(p->E), kBlock, 0, s>>>((int32_t)p->E, static_cast<const XT *>(ws.send),
                                                      static_cast<XT *>(ws.recv));
-    const uint32_t nb1 = blocks_for(p->H), nb2 = blocks_for(p->Gon);
+    const uint32_t nb1 = hop ? blocks_for(p->H) : 0, nb2 = local ? blocks_for(p->Gon) : 0;
     if (nb1 + nb2 > 0)
         k_scatter2<XT><<<nb1 + nb2, kBlock, 0, s>>>(
-            (int32_t)p->H, p->d_ssrc, p->d_sdst, static_cast<const XT *>(ws.recv),
-            (int32_t)p->Gon, p->d_lsrc, p->d_ldst, v, static_cast<XT *>(ws.ghost), nb1);
+            hop ? (int32_t)p->H : 0, p->d_ssrc, p->d_sdst, static_cast<const XT *>(ws.recv),
+            local ? (int32_t)p->Gon : 0, p->d_lsrc, p->d_ldst, v, static_cast<XT *>(ws.ghost), nb1);
+}
+
+// REMOTE stage of a three-way plan (algorithm NAPSpMV): on the caller's
+// stream the fully local gathers and the on_node product; meanwhile on the
+// helper stream the inter-node hop and the scatter of received values; then,
+// joined, the off_node product.
+template <typename VT, typename XT, int CAP>
+void launch_three_way(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, const XT *v,
+                      XT *w, hipStream_t s) {
+    HIP_OK(hipEventRecord(p->ev_fork, s));
+    HIP_OK(hipStreamWaitEvent(p->helper, p->ev_fork, 0));
+    launch_hop_scatter<XT>(p, ws, v, p->helper, true, false);
+    HIP_OK(hipEventRecord(p->ev_join, p->helper));
+    launch_hop_scatter<XT>(p, ws, v, s, false, true);
+    if (sc.n_nd > 0 && p->hp.nnz_nd > 0)
+        napspmv::k_remote<VT, XT, CAP><<<(uint32_t)sc.n_nd, napspmv::kBlock, 0, s>>>(
+            remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_nd, true));
+    HIP_OK(hipStreamWaitEvent(s, p->ev_join, 0));
+    if (p->hp.nnz_off - p->hp.nnz_nd > 0 && sc.n_off > 0)
+        napspmv::k_remote<VT, XT, CAP><<<(uint32_t)sc.n_off, napspmv::kBlock, 0, s>>>(
+            remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_off));
 }
 
 template <typename VT, typename XT, int CAP>
@@ -443,6 +498,10 @@ void launch_cap(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, int 
                 int64_t n_blk) {
     if (stage == NAPSPMV_STAGE_LOCAL) {
         launch_local<VT, XT, CAP>(p->cur_window, local_view<VT, XT>(p, sc, ws, v, w, task0, n_tasks), s);
+        return;
+    }
+    if (p->hp.three_way) {
+        launch_three_way<VT, XT, CAP>(p, sc, ws, v, w, s);
         return;
     }
     if (p->hp.mode == NAPSPMV_NAP) launch_hop_scatter<XT>(p, ws, v, s);
@@ -529,6 +588,7 @@ void fill_stats(const napspmv_plan_s *p, napspmv_stats_t *s) {
     s->device_bytes = p->device_bytes;
     s->build_seconds = p->build_s;
     s->upload_seconds = p->upload_s;
+    s->flags = p->flags;
 }
 
 // ---- batched launches -----------------------------------------------------------
@@ -643,7 +703,7 @@ std::string tune_key(const napspmv_plan_s *p) {
     std::ostringstream k;
     k << dev << ";n=" << p->hp.n << ";nnz=" << p->hp.nnz << ";np=" << p->hp.n_p << ";ppn="
       << p->hp.ppn << ";mode=" << p->hp.mode << ";dtype=" << p->hp.dtype << ";G=" << p->G
-      << ";on=" << p->hp.nnz_on;
+      << ";on=" << p->hp.nnz_on << ";three_way=" << (p->hp.three_way ? 1 : 0);
     std::string s = k.str();
     std::replace(s.begin(), s.end(), ' ', '_');
     return s;
@@ -691,7 +751,7 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
     if (!plan_out) return fail(NAPSPMV_EINVAL, "plan_out is NULL");
     *plan_out = nullptr;
     if (flags & ~(NAPSPMV_HOST_ONLY | NAPSPMV_EXCHANGE_COPY | NAPSPMV_NAP_OWNER_MAP |
-                  NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP))
+                  NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY))
         return fail(NAPSPMV_EINVAL, "unknown flag bits");
     napspmv_plan_s *p = nullptr;
     const int rc = guarded([&]() {
@@ -699,7 +759,8 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         p->flags = flags;
         const auto t0 = std::chrono::steady_clock::now();
         napspmv::build_plan(p->hp, rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts,
-                            flags & (NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP));
+                            flags & (NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP |
+                                     NAPSPMV_NAP_THREE_WAY));
         const auto t1 = std::chrono::steady_clock::now();
         p->build_s = std::chrono::duration<double>(t1 - t0).count();
         p->G = p->hp.ghost_ptr.back();
@@ -827,6 +888,8 @@ int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *
             return fail(NAPSPMV_EINVAL, "a batch needs one value type, BLOCK_NNZ and VWINDOW");
         if (p->hp.mode == NAPSPMV_NAP && (p->flags & NAPSPMV_EXCHANGE_COPY))
             return fail(NAPSPMV_EUNSUPPORTED, "batched applies receive NAP messages in place");
+        if (p->hp.three_way)
+            return fail(NAPSPMV_EUNSUPPORTED, "batched applies use the two-part product");
     }
     return guarded([&]() {
         DeviceGuard g(batch->device);

@@ -20,7 +20,9 @@
 //    local process owning most of E(n, m)), the split of a partner over
 //    several processes when a node has fewer partners or senders than ppn
 //    (section 4.1), and the fully local step deduplicated against the
-//    on_node -> off_node step.
+//    on_node -> off_node step; and the three-way product, which keeps the
+//    sets and splits the off-process block into its on_node and off_node
+//    parts (algorithm NAPSpMV's three local products).
 //  * on_node -> off_node (L0): the indices of the inter-node messages sent by
 //    s that s does not own, unique per (owner, s).
 //  * off_node -> on_node (L1): every off-node ghost j of t arrives at the
@@ -44,7 +46,8 @@ namespace {
 // (an index plus at most one block's worth of work) is representable.
 constexpr int64_t kInt32Max = 0x7fffffff - 0x10000;
 
-constexpr uint32_t kVariantFlags = NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP;
+constexpr uint32_t kVariantFlags =
+    NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY;
 
 struct Owner {
     const std::vector<int64_t> &starts;
@@ -145,6 +148,8 @@ void validate(const int64_t *rowptr, const int32_t *col, const void *val, int dt
 void release_device_arrays(HostPlan &hp) {
     std::vector<int32_t>().swap(hp.col_on);
     std::vector<int32_t>().swap(hp.col_off);
+    std::vector<int32_t>().swap(hp.col_nd);
+    std::vector<uint8_t>().swap(hp.val_nd);
     std::vector<uint8_t>().swap(hp.val_on);
     std::vector<uint8_t>().swap(hp.val_off);
     std::vector<int32_t>().swap(hp.gather_idx);
@@ -261,6 +266,56 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
                 }
             }
         }
+    }
+
+    // Three-way plans: move the on_node entries of every row (stored order
+    // kept) out of the off-process block.
+    if (variant & NAPSPMV_NAP_THREE_WAY) {
+        hp.three_way = true;
+        std::vector<uint8_t> on_node(hp.nnz_off);
+        hp.rowptr_nd.assign(n + 1, 0);
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t t = 0; t < n_p; ++t) {
+            const int64_t nlo = hp.starts[node_of(t) * ppn], nhi = hp.starts[(node_of(t) + 1) * ppn];
+            for (int64_t i = hp.starts[t]; i < hp.starts[t + 1]; ++i) {
+                int32_t c = 0;
+                for (int64_t b = hp.rowptr_off[i]; b < hp.rowptr_off[i + 1]; ++b) {
+                    const int32_t j = hp.ghost_col[hp.col_off[b]];
+                    on_node[b] = j >= nlo && j < nhi;
+                    c += on_node[b];
+                }
+                hp.rowptr_nd[i + 1] = c;
+            }
+        }
+        for (int64_t i = 0; i < n; ++i) hp.rowptr_nd[i + 1] += hp.rowptr_nd[i];
+        hp.nnz_nd = hp.rowptr_nd[n];
+        std::vector<int32_t> rp_fn(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i)
+            rp_fn[i + 1] = rp_fn[i] + (hp.rowptr_off[i + 1] - hp.rowptr_off[i]) -
+                           (hp.rowptr_nd[i + 1] - hp.rowptr_nd[i]);
+        std::vector<int32_t> col_fn(rp_fn[n]);
+        std::vector<uint8_t> val_fn((size_t)(rp_fn[n] * vs));
+        hp.col_nd.resize(hp.nnz_nd);
+        hp.val_nd.resize((size_t)(hp.nnz_nd * vs));
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t a = hp.rowptr_nd[i], f = rp_fn[i];
+            for (int64_t b = hp.rowptr_off[i]; b < hp.rowptr_off[i + 1]; ++b) {
+                const uint8_t *src = &hp.val_off[(size_t)(b * vs)];
+                if (on_node[b]) {
+                    hp.col_nd[a] = hp.col_off[b];
+                    std::memcpy(&hp.val_nd[(size_t)(a * vs)], src, (size_t)vs);
+                    ++a;
+                } else {
+                    col_fn[f] = hp.col_off[b];
+                    std::memcpy(&val_fn[(size_t)(f * vs)], src, (size_t)vs);
+                    ++f;
+                }
+            }
+        }
+        hp.rowptr_off.swap(rp_fn);
+        hp.col_off.swap(col_fn);
+        hp.val_off.swap(val_fn);
     }
 
     // Runs of gh(t) by owner: the standard messages D(r, t).

@@ -49,6 +49,14 @@ struct HostPlan {
     std::vector<uint8_t> val_on;                 // nnz_on * value_size
     std::vector<int32_t> rowptr_off, col_off;    // n + 1, nnz_off
     std::vector<uint8_t> val_off;                // nnz_off * value_size
+    // Three-way plans only: the on_node part of the off-process block (ghosts
+    // owned by another process of the row's node), taken out of
+    // rowptr_off/col_off/val_off, which then hold the off_node part.
+    // nnz_off still counts both parts.
+    bool three_way = false;
+    std::vector<int32_t> rowptr_nd, col_nd;      // n + 1, nnz_nd
+    std::vector<uint8_t> val_nd;                 // nnz_nd * value_size
+    int64_t nnz_nd = 0;
     // Smallest and largest on-process column of each row (lo > hi if none):
     // the window of v a row block reads directly.
     std::vector<int32_t> on_lo, on_hi;

@@ -54,6 +54,7 @@ struct ServerPlan {
     napspmv_plan_t plan = nullptr;
     int64_t ws_bytes = 0;
     int key_dtype = 0, key_cap = 0, key_win = 0;
+    bool solo = false;      // never batched (explicit exchange copy, three-way product)
     std::vector<void *> free_ws, all_ws;
 };
 
@@ -155,7 +156,8 @@ int64_t retire(napspmv_server_s *s) {
 
 // Fill free slots from the queue, oldest request first; a batch takes the
 // oldest request's kernel group (value type, block size, window) and every
-// later queued request of that group that gets a workspace.
+// later queued request of that group that gets a workspace.  A plan that
+// batches cannot take (solo) runs alone.
 void admit(napspmv_server_s *s) {
     for (ServerSlot &sl : s->slots) {
         if (sl.busy) continue;
@@ -165,7 +167,8 @@ void admit(napspmv_server_s *s) {
         for (auto it = s->queue.begin(); it != s->queue.end() && (int)take.size() < s->max_batch;) {
             ServerRequest &R = s->reqs[*it];
             const ServerPlan &P = s->plans[R.plan];
-            if (key[0] >= 0 && (P.key_dtype != key[0] || P.key_cap != key[1] || P.key_win != key[2])) {
+            if (key[0] >= 0 && (P.solo || P.key_dtype != key[0] || P.key_cap != key[1] ||
+                                P.key_win != key[2])) {
                 ++it;
                 continue;
             }
@@ -180,6 +183,7 @@ void admit(napspmv_server_s *s) {
             key[2] = P.key_win;
             take.push_back(*it);
             it = s->queue.erase(it);
+            if (P.solo) break;
         }
         if (take.empty()) return;
         const int n = (int)take.size();
@@ -248,6 +252,8 @@ int napspmv_server_add_plan(napspmv_server_t s, napspmv_plan_t plan, int *id_out
     P.key_dtype = st.dtype;
     P.key_cap = napspmv_plan_get_param(plan, NAPSPMV_PARAM_BLOCK_NNZ);
     P.key_win = napspmv_plan_get_param(plan, NAPSPMV_PARAM_VWINDOW);
+    P.solo = st.mode == NAPSPMV_NAP &&
+             (st.flags & (NAPSPMV_EXCHANGE_COPY | NAPSPMV_NAP_THREE_WAY)) != 0;
     s->plans.push_back(P);
     *id_out = (int)s->plans.size() - 1;
     return NAPSPMV_OK;

@@ -11,7 +11,8 @@ from tests.helpers import example_2_1
 from workloads import config, random_pattern
 
 VARIANTS = [("owner_map",), ("split",), ("dedup",), ("owner_map", "split"),
-            ("owner_map", "split", "dedup")]
+            ("owner_map", "split", "dedup"), ("three_way",), ("split", "three_way")]
+FLAGS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20}
 
 
 def _compare(a, n_p, ppn, variant, row_starts=None):
@@ -20,6 +21,7 @@ def _compare(a, n_p, ppn, variant, row_starts=None):
                   host_only=True, variant=variant) as p:
         assert p.variant == tuple(sorted(variant))
         st = p.stats
+        assert st["flags"] == 0x1 | sum(FLAGS[v] for v in variant)
         for ph in lib.PHASES:
             got, exp = p.export(ph), ref["phases"][ph]
             for g, e in zip(got, exp):
@@ -71,6 +73,8 @@ def test_variants_keep_inter_node_volume():
         assert st["phases"]["INTER"]["elems"] == base["phases"]["INTER"]["elems"]
         if "split" not in variant:
             assert st["phases"]["L1"] == base["phases"]["L1"]
+        assert (st["nnz_on"], st["nnz_off"], st["ghosts"]) == (
+            base["nnz_on"], base["nnz_off"], base["ghosts"])
 
 
 def test_variant_flags_rejected_for_standard_and_unknown():
