@@ -33,8 +33,11 @@ def matvec(csr, v: np.ndarray) -> np.ndarray:
     return dense(csr) @ np.asarray(v, dtype=np.float64)
 
 
-def blocks(n: int, n_p: int, row_starts=None):
-    """R(r) as Python ranges, with the remainder rows on the last rank."""
+def blocks(n: int, n_p: int, row_starts=None, strided: bool = False):
+    """R(r) as Python ranges, with the remainder rows on the last rank; or,
+    strided, rows r, r + n_p, r + 2 n_p, ..."""
+    if strided:
+        return [range(r, n, n_p) for r in range(n_p)]
     if row_starts is None:
         b = n // n_p
         row_starts = [b * r for r in range(n_p)] + [n]
@@ -45,10 +48,10 @@ def _exists(S, rows, cols) -> bool:
     return any(S[i, j] for i in rows for j in cols)
 
 
-def standard_sets(csr, n_p: int, ppn: int, row_starts=None) -> dict:
+def standard_sets(csr, n_p: int, ppn: int, row_starts=None, strided: bool = False) -> dict:
     """P(r) and D(r, t), straight from their quantifiers."""
     S = pattern(csr)
-    R = blocks(csr.n, n_p, row_starts)
+    R = blocks(csr.n, n_p, row_starts, strided)
     P = {r: [t for t in range(n_p) if t != r and _exists(S, R[t], R[r])] for r in range(n_p)}
     D = {}
     for r in range(n_p):
@@ -57,10 +60,10 @@ def standard_sets(csr, n_p: int, ppn: int, row_starts=None) -> dict:
     return {"P": P, "D": D}
 
 
-def node_sets(csr, n_p: int, ppn: int, row_starts=None):
+def node_sets(csr, n_p: int, ppn: int, row_starts=None, strided: bool = False):
     """N(n) and E(n, m), straight from their quantifiers over (p, q)."""
     S = pattern(csr)
-    R = blocks(csr.n, n_p, row_starts)
+    R = blocks(csr.n, n_p, row_starts, strided)
     nodes = n_p // ppn
     rank = lambda p, n: n * ppn + p  # noqa: E731
     E = {}
@@ -96,12 +99,12 @@ def mapping(n_p: int, ppn: int, E: dict):
     return send_rank, recv_rank
 
 
-def nap_sets(csr, n_p: int, ppn: int, row_starts=None) -> dict:
+def nap_sets(csr, n_p: int, ppn: int, row_starts=None, strided: bool = False) -> dict:
     """I, and J of the three local steps, from their quantifiers, given E and
     the mapping."""
     S = pattern(csr)
-    R = blocks(csr.n, n_p, row_starts)
-    N, E = node_sets(csr, n_p, ppn, row_starts)
+    R = blocks(csr.n, n_p, row_starts, strided)
+    N, E = node_sets(csr, n_p, ppn, row_starts, strided)
     send_rank, recv_rank = mapping(n_p, ppn, E)
     node = lambda r: r // ppn  # noqa: E731
     I = {(send_rank[k], recv_rank[k]): E[k] for k in E}

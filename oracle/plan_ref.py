@@ -75,15 +75,24 @@ VARIANTS = frozenset({"owner_map", "dedup", "split", "three_way"})
 
 
 class Layout:
-    """Processes, nodes and row blocks (section 2)."""
+    """Processes, nodes and row blocks (section 2).  ``strided=True`` gives
+    the strided partition of section 5.3 instead: row r on process
+    r mod n_p."""
 
-    def __init__(self, n: int, n_p: int, ppn: int, row_starts=None):
+    def __init__(self, n: int, n_p: int, ppn: int, row_starts=None, strided: bool = False):
         if n_p < 1 or ppn < 1 or n_p % ppn != 0:
             raise ValueError("need n_p >= 1, ppn >= 1 and ppn dividing n_p")
         if n < n_p:
             raise ValueError("need at least one row per process")
         self.n, self.n_p, self.ppn = int(n), int(n_p), int(ppn)
         self.n_nodes = self.n_p // self.ppn
+        self.strided = bool(strided)
+        if strided:
+            if row_starts is not None:
+                raise ValueError("a strided partition takes no row_starts")
+            self.starts = None
+            self._owner = np.arange(self.n, dtype=np.int64) % self.n_p
+            return
         if row_starts is None:
             b = self.n // self.n_p
             starts = [b * r for r in range(self.n_p)] + [self.n]
@@ -98,6 +107,8 @@ class Layout:
             self._owner[starts[r]:starts[r + 1]] = r
 
     def R(self, r: int) -> range:
+        if self.strided:
+            return range(r, self.n, self.n_p)
         return range(self.starts[r], self.starts[r + 1])
 
     def owner(self, j: int) -> int:

@@ -39,15 +39,24 @@ def owner(starts: np.ndarray, j: np.ndarray) -> np.ndarray:
     return np.searchsorted(starts, j, side="right") - 1
 
 
-def ghost_pairs(csr, starts: np.ndarray):
+def owner_fn(starts, n_p: int):
+    """The owner map of a partition: contiguous blocks given by ``starts``,
+    or, when ``starts`` is None, the strided partition (row r on process
+    r mod n_p, section 5.3)."""
+    if starts is None:
+        return lambda j: np.asarray(j, dtype=np.int64) % n_p
+    return lambda j: owner(starts, j)
+
+
+def ghost_pairs(csr, own):
     """All (t, j) with j in gh(t): the sorted, unique off-process columns of
     every rank t (the off_process block of section 2), ordered by (t, j)."""
     n = csr.n
     rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(csr.rowptr))
-    t = owner(starts, rows)
+    t = own(rows)
     del rows
     j = csr.col.astype(np.int64)
-    r = owner(starts, j)
+    r = own(j)
     off = r != t
     key = np.unique(t[off] * n + j[off])
     return key // n, key % n
@@ -67,11 +76,22 @@ def _segments(src, dst, idx):
             idx.astype(np.int32))
 
 
-def standard_plan(csr, n_p: int, ppn: int, given_starts=None) -> dict:
+def _partition(n, n_p, given_starts, strided):
+    if strided:
+        if given_starts is not None:
+            raise ValueError("a strided partition takes no row_starts")
+        if n < n_p:
+            raise ValueError("need at least one row per process")
+        return None, owner_fn(None, n_p)
+    starts = row_starts(n, n_p, given_starts)
+    return starts, owner_fn(starts, n_p)
+
+
+def standard_plan(csr, n_p: int, ppn: int, given_starts=None, strided: bool = False) -> dict:
     """D(r, t) for every pair, split into inter-node and intra-node classes."""
-    starts = row_starts(csr.n, n_p, given_starts)
-    t, j = ghost_pairs(csr, starts)
-    r = owner(starts, j)
+    starts, own = _partition(csr.n, n_p, given_starts, strided)
+    t, j = ghost_pairs(csr, own)
+    r = own(j)
     inter = (r // ppn) != (t // ppn)
     return {
         "mode": "standard", "starts": starts, "ghost_t": t, "ghost_j": j,
@@ -94,17 +114,17 @@ def _rank_within(group: np.ndarray) -> np.ndarray:
     return k - np.maximum.accumulate(start)
 
 
-def nap_plan(csr, n_p: int, ppn: int, given_starts=None, variant=()) -> dict:
+def nap_plan(csr, n_p: int, ppn: int, given_starts=None, variant=(), strided: bool = False) -> dict:
     """E(n, m), the T/U mapping, the inter-node messages I and the three
     local steps of section 4, under the readings and variants of
     ``plan_ref`` (module docstring there)."""
     variant = set(variant)
     if variant - VARIANTS:
         raise ValueError(f"unknown variant(s) {sorted(variant - VARIANTS)}")
-    starts = row_starts(csr.n, n_p, given_starts)
+    starts, own = _partition(csr.n, n_p, given_starts, strided)
     n_nodes = n_p // ppn
-    t, j = ghost_pairs(csr, starts)
-    r = owner(starts, j)
+    t, j = ghost_pairs(csr, own)
+    r = own(j)
     src_node, dst_node = r // ppn, t // ppn
     offn = src_node != dst_node
 
@@ -123,7 +143,7 @@ def nap_plan(csr, n_p: int, ppn: int, given_starts=None, variant=()) -> dict:
     if "owner_map" in variant:
         # the local process owning the most indices of E(n, m) (lowest on ties)
         pair_of_e = np.searchsorted(pairs, e_pair)
-        own_loc = owner(starts, e_j) % ppn
+        own_loc = own(e_j) % ppn
         counts = np.zeros((pairs.size, ppn), dtype=np.int64)
         np.add.at(counts, (pair_of_e, own_loc), 1)
         t_loc = counts.argmax(axis=1)
@@ -165,9 +185,9 @@ def nap_plan(csr, n_p: int, ppn: int, given_starts=None, variant=()) -> dict:
         i_src, i_dst = send_rank[pair_of], recv_rank[pair_of]
 
     # on_node -> off_node: owner -> inter-node sender, deduplicated per pair.
-    own = owner(starts, e_j)
-    need = own != i_src
-    l0 = np.unique((own[need] * n_p + i_src[need]) * csr.n + e_j[need])
+    o_e = own(e_j)
+    need = o_e != i_src
+    l0 = np.unique((o_e[need] * n_p + i_src[need]) * csr.n + e_j[need])
     l0_src, l0_dst, l0_j = l0 // csr.n // n_p, (l0 // csr.n) % n_p, l0 % csr.n
 
     # off_node -> on_node: receiver of j on the destination node -> each other user.
@@ -197,11 +217,12 @@ def nap_plan(csr, n_p: int, ppn: int, given_starts=None, variant=()) -> dict:
     }
 
 
-def plan(csr, n_p: int, ppn: int, mode: str, given_starts=None, variant=()) -> dict:
+def plan(csr, n_p: int, ppn: int, mode: str, given_starts=None, variant=(),
+         strided: bool = False) -> dict:
     if mode == "standard":
-        return standard_plan(csr, n_p, ppn, given_starts)
+        return standard_plan(csr, n_p, ppn, given_starts, strided)
     if mode == "nap":
-        return nap_plan(csr, n_p, ppn, given_starts, variant)
+        return nap_plan(csr, n_p, ppn, given_starts, variant, strided)
     raise ValueError(mode)
 
 

@@ -26,15 +26,14 @@ class DeliveryError(AssertionError):
 
 
 def _local_v(lay: Layout, v):
-    return [np.asarray(v[lay.R(r).start:lay.R(r).stop], dtype=np.float64)
-            for r in range(lay.n_p)]
+    """v|R(r) of every rank, keyed by global index."""
+    return [{j: float(v[j]) for j in lay.R(r)} for r in range(lay.n_p)]
 
 
 def _send(lay, v_loc, r, idx):
     """The pack loop: values of R(r) at global indices idx, read from r's own
-    slice of v."""
-    base = lay.R(r).start
-    return [float(v_loc[r][j - base]) for j in idx]
+    part of v."""
+    return [v_loc[r][j] for j in idx]
 
 
 def _receive(slots, counts, idx, vals, expect=None):
@@ -97,7 +96,7 @@ def simulate_nap(csr, lay: Layout, plan: dict, v):
         g_send = []
         for j in idx:
             if lay.owner(j) == s:
-                g_send.append(float(v_loc[s][j - lay.R(s).start]))
+                g_send.append(v_loc[s][j])
             elif j in b_lnl[s]:
                 g_send.append(b_lnl[s][j])
             else:
@@ -153,14 +152,13 @@ def _split_product(csr, lay, v_loc, ghost_vals, three_way: bool):
     """local_spmv on the split blocks of every rank."""
     w = np.zeros(csr.n)
     for t in range(lay.n_p):
-        base = lay.R(t).start
         for i in lay.R(t):
             parts = [0.0, 0.0, 0.0]
             for k in range(int(csr.rowptr[i]), int(csr.rowptr[i + 1])):
                 j, a = int(csr.col[k]), float(csr.val[k])
                 r = lay.owner(j)
                 if r == t:
-                    parts[0] += a * float(v_loc[t][j - base])
+                    parts[0] += a * v_loc[t][j]
                 elif three_way and lay.node(r) == lay.node(t):
                     parts[1] += a * ghost_vals[t][j]
                 else:

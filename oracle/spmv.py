@@ -50,6 +50,9 @@ def _load():
         lib.spmv_split3_ref_f64.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 5
                                             + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                                ctypes.c_int])
+        lib.spmv_split_owner_ref_f64.restype = None
+        lib.spmv_split_owner_ref_f64.argtypes = ([ctypes.c_int64] + [ctypes.c_void_p] * 6
+                                                 + [ctypes.c_int64, ctypes.c_int, ctypes.c_int])
         lib.spmv_ref_threads.restype = ctypes.c_int
         lib.spmv_ref_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -84,10 +87,42 @@ def block_starts(n: int, n_p: int, row_starts=None) -> np.ndarray:
     return s
 
 
-def spmv_split(csr, v, n_p: int, row_starts=None, threads: int = 0, out=None) -> np.ndarray:
+def owners(n: int, n_p: int, row_starts=None, strided: bool = False) -> np.ndarray:
+    """owner[i]: the process holding row i (and v_i)."""
+    if strided:
+        return (np.arange(n, dtype=np.int64) % n_p).astype(np.int32)
+    st = block_starts(n, n_p, row_starts)
+    return (np.searchsorted(st, np.arange(n), side="right") - 1).astype(np.int32)
+
+
+def spmv_split_owner(csr, v, owner, ppn: int = 1, parts: int = 2, threads: int = 0,
+                     out=None) -> np.ndarray:
+    """The split-order product for any partition given by owner[i]
+    (C routine spmv_split_owner_ref_f64): parts=2 is standard_spmv's order,
+    parts=3 NAPSpMV's with nodes of ppn processes."""
+    if parts not in (2, 3):
+        raise ValueError("parts must be 2 or 3")
+    lib = _load()
+    rp = np.ascontiguousarray(csr.rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(csr.col, dtype=np.int32)
+    val = np.ascontiguousarray(csr.val, dtype=np.float64)
+    x = np.ascontiguousarray(v, dtype=np.float64)
+    own = np.ascontiguousarray(owner, dtype=np.int32)
+    w = np.empty(csr.n, dtype=np.float64) if out is None else out
+    lib.spmv_split_owner_ref_f64(csr.n, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                 x.ctypes.data, w.ctypes.data, own.ctypes.data, int(ppn),
+                                 int(parts), int(threads))
+    return w
+
+
+def spmv_split(csr, v, n_p: int, row_starts=None, threads: int = 0, out=None,
+               strided: bool = False) -> np.ndarray:
     """w = A v summed as standard_spmv does on every process: the
     on-process block first, then the off-process block, each in stored
-    order (C routine spmv_split_ref_f64)."""
+    order (C routine spmv_split_ref_f64; strided partitions through
+    spmv_split_owner)."""
+    if strided:
+        return spmv_split_owner(csr, v, owners(csr.n, n_p, strided=True), 1, 2, threads, out)
     lib = _load()
     rp = np.ascontiguousarray(csr.rowptr, dtype=np.int64)
     col = np.ascontiguousarray(csr.col, dtype=np.int32)
@@ -101,12 +136,15 @@ def spmv_split(csr, v, n_p: int, row_starts=None, threads: int = 0, out=None) ->
 
 
 def spmv_split3(csr, v, n_p: int, ppn: int, row_starts=None, threads: int = 0,
-                out=None) -> np.ndarray:
+                out=None, strided: bool = False) -> np.ndarray:
     """w = A v summed as algorithm NAPSpMV does on every process: the
     on_process block, then the on_node block, then the off_node block, each
-    in stored order (C routine spmv_split3_ref_f64)."""
+    in stored order (C routine spmv_split3_ref_f64; strided partitions
+    through spmv_split_owner)."""
     if n_p % ppn:
         raise ValueError("ppn must divide n_p")
+    if strided:
+        return spmv_split_owner(csr, v, owners(csr.n, n_p, strided=True), ppn, 3, threads, out)
     lib = _load()
     rp = np.ascontiguousarray(csr.rowptr, dtype=np.int64)
     col = np.ascontiguousarray(csr.col, dtype=np.int32)

@@ -100,6 +100,38 @@ void spmv_split3_ref_f64(int64_t n, const int64_t *rowptr, const int32_t *col,
     }
 }
 
+/*
+ * The split-order products above for any partition, given as the owner of
+ * every index (owner[i] = the process holding row i and v_i): row i of
+ * process t = owner[i] adds, sequentially from 0, its entries with
+ * owner[col] == t, then (parts == 3 only) those with owner[col] on t's node
+ * (owner[col] / ppn == t / ppn), then the rest, each group in stored order.
+ * parts == 2 is standard_spmv's order, parts == 3 NAPSpMV's.
+ */
+void spmv_split_owner_ref_f64(int64_t n, const int64_t *rowptr, const int32_t *col,
+                              const double *val, const double *v, double *w,
+                              const int32_t *owner, int64_t ppn, int parts, int threads)
+{
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t t = owner[i];
+        double s = 0.0;
+        for (int part = 0; part < 3; ++part) {
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int32_t r = owner[col[k]];
+                int which = 2;
+                if (r == t) which = 0;
+                else if (parts == 3 && r / ppn == t / ppn) which = 1;
+                if (which != part) continue;
+                double prod = val[k] * v[col[k]];
+                s = s + prod;
+            }
+        }
+        w[i] = s;
+    }
+}
+
 /* Number of threads an OpenMP parallel region actually uses. */
 int spmv_ref_threads(int threads)
 {

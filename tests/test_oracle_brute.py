@@ -113,3 +113,55 @@ def test_mapping_invariants_many_partners():
         assert sorted(got) == senders
         cnt = [len(nap["U"][r]) for r in ranks]
         assert max(cnt) - min(cnt) <= 1
+
+
+@pytest.mark.parametrize("n_p,ppn", [(2, 1), (4, 2), (6, 3), (8, 4), (6, 2)])
+def test_strided_literal_vs_brute_and_vectorised(n_p, ppn):
+    """Strided partition (row r on process r mod n_p): the literal sets equal
+    the brute-force quantifiers and the vectorised evaluation, and every
+    ghost is delivered once with the owner's value."""
+    from oracle import brute, plan_ref, plan_vec, simulate
+    from tests.helpers import arrays_to_triples, triples
+    for seed in range(3):
+        n = 19 + 5 * n_p + seed
+        a = random_pattern(n, 0.15, seed=70 + 7 * n_p + seed, empty_rows=1, duplicates=2)
+        lay = plan_ref.Layout(n, n_p, ppn, strided=True)
+        std = plan_ref.standard_plan(a, lay)
+        b = brute.standard_sets(a, n_p, ppn, strided=True)
+        assert std["P"] == b["P"] and std["D"] == {k: v for k, v in b["D"].items()}
+        nap = plan_ref.nap_plan(a, lay)
+        bn = brute.nap_sets(a, n_p, ppn, strided=True)
+        assert triples(nap["phases"]["INTER"]) == triples([(s, q, idx) for (s, q), idx in bn["I"].items()])
+        for ph, J in (("L0", "J0"), ("L1", "J1"), ("L2", "J2")):
+            assert triples(nap["phases"][ph]) == triples([(p, s, idx) for (p, s), idx in bn[J].items()])
+        for mode, lit in (("standard", std), ("nap", nap)):
+            vec = plan_vec.plan(a, n_p, ppn, mode, strided=True)
+            for ph in plan_ref.PHASES:
+                assert arrays_to_triples(vec["phases"][ph]) == triples(lit["phases"][ph]), (mode, ph)
+        v = np.random.default_rng(seed).standard_normal(n)
+        simulate.simulate_standard(a, lay, std, v)
+        simulate.simulate_nap(a, lay, nap, v)
+
+
+def test_strided_is_a_symmetric_permutation_of_contiguous():
+    """Renumbering row r to its position in process-major order (process
+    r mod n_p, slot r div n_p) turns the strided plan into the contiguous plan
+    of the permuted matrix, message for message."""
+    from oracle import plan_ref
+    from tests.helpers import csr_from_rows, triples
+    n, n_p, ppn = 37, 6, 2
+    a = random_pattern(n, 0.12, seed=5, duplicates=1)
+    counts = [len(range(p, n, n_p)) for p in range(n_p)]
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    new = np.array([starts[r % n_p] + r // n_p for r in range(n)])
+    old_of = np.argsort(new)
+    rows = [[int(new[c]) for c in a.col[a.rowptr[o]:a.rowptr[o + 1]]] for o in old_of]
+    b = csr_from_rows(rows)
+    lay_s = plan_ref.Layout(n, n_p, ppn, strided=True)
+    lay_c = plan_ref.Layout(n, n_p, ppn, row_starts=starts)
+    for mode in ("standard", "nap"):
+        ps = plan_ref.plan(a, lay_s, mode)
+        pc = plan_ref.plan(b, lay_c, mode)
+        for ph in plan_ref.PHASES:
+            mapped = [(s, d, tuple(sorted(int(new[j]) for j in idx))) for s, d, idx in ps["phases"][ph]]
+            assert triples(mapped) == triples(pc["phases"][ph]), (mode, ph)

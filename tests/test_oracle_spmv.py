@@ -135,3 +135,47 @@ def test_three_way_order_differs_from_two_way():
     assert spmv_split(a, v, 4)[0] == 1.0
     assert spmv_split3(a, v, 4, 2)[0] == 0.0
     assert spmv_split3(a, v, 4, 1)[0] == 1.0      # no on-node block: two-way order
+
+
+def test_owner_routine_matches_block_routines():
+    """The owner-array routine reproduces the block routines bit for bit on
+    contiguous partitions (a second code path), and on a strided partition
+    is exact on integer inputs and within rounding of the dense product."""
+    from oracle.spmv import owners, spmv_split, spmv_split3, spmv_split_owner
+    for seed in range(3):
+        a = random_pattern(70, 0.1, seed + 40, empty_rows=2, duplicates=3)
+        a = CSR(a.n, a.rowptr, a.col, np.random.default_rng(seed).standard_normal(a.nnz))
+        v = vec_normal(70, seed + 3)
+        starts = np.array([0, 9, 10, 33, 50, 61, 70], np.int64)
+        for n_p, ppn, rs in ((6, 2, None), (6, 3, starts), (7, 7, None), (5, 1, None)):
+            own = owners(70, n_p, rs)
+            assert np.array_equal(spmv_split_owner(a, v, own, ppn, 2), spmv_split(a, v, n_p, rs))
+            assert np.array_equal(spmv_split_owner(a, v, own, ppn, 3),
+                                  spmv_split3(a, v, n_p, ppn, rs))
+        ref = brute.matvec(a, v)
+        for n_p, ppn in ((6, 2), (8, 4)):
+            for w in (spmv_split(a, v, n_p, strided=True),
+                      spmv_split3(a, v, n_p, ppn, strided=True)):
+                assert np.linalg.norm(w - ref) <= 1e-14 * np.linalg.norm(ref)
+        ai = CSR(a.n, a.rowptr, a.col, np.round(a.val * 4))
+        vi = np.round(v * 4)
+        assert np.array_equal(spmv_split3(ai, vi, 8, 4, strided=True), brute.matvec(ai, vi))
+    # strided owner: row i on process i mod n_p
+    assert owners(10, 4, strided=True).tolist() == [0, 1, 2, 3, 0, 1, 2, 3, 0, 1]
+
+
+def test_strided_split_order_planted():
+    """Row 0 stores (col 1: 1), (col 2: 2^53), (col 4: -2^53), 8 rows on 4
+    processes.  Strided (process 0 owns rows and columns 0 and 4): the
+    on-process -2^53 first, then 1 and 2^53 in stored order,
+    (-2^53 + 1) + 2^53 = 1.  Contiguous (process 0 owns 0 and 1): the
+    on-process 1 first, then (1 + 2^53) - 2^53 = 0."""
+    from oracle.spmv import spmv_split
+    big = 2.0 ** 53
+    a = CSR(8, np.array([0, 3, 4, 5, 6, 7, 8, 9, 10], np.int64),
+            np.array([1, 2, 4, 1, 2, 3, 4, 5, 6, 7], np.int32),
+            np.array([1.0, big, -big, 1, 1, 1, 1, 1, 1, 1]))
+    v = np.ones(8)
+    assert spmv.spmv(a, v)[0] == 0.0            # (1 + 2^53) - 2^53
+    assert spmv_split(a, v, 4, strided=True)[0] == 1.0
+    assert spmv_split(a, v, 4)[0] == 0.0        # contiguous: rows 0, 1 own cols 0, 1
