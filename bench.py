@@ -411,6 +411,25 @@ def main():
             var[name] = {k: {"msgs": q[k]["msgs"], "elems": q[k]["elems"],
                              "max_msgs_sent": q[k]["max_msgs_sent"]} for k in ("INTER", "L0", "L1", "L2")}
         result["nap_variant_messages"] = var
+        # strided partition (row r on process r mod n_p): process-major v and w
+        strided = {}
+        for mode in ("standard", "nap"):
+            ps_ = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode=mode, dtype="f64",
+                           strided=True)
+            rows = torch.from_numpy(ps_.rows()).to(dev)
+            vs_ = v[rows].contiguous()
+            ws_ = torch.empty_like(vs_)
+            ms_s, ex_s, sp_s = time_apply(ps_, vs_, ws_, max(10, args.steps // 2), 2, torch, nap)
+            ss = ps_.stats
+            bs = spmv_bytes(ss, 8, 8) + exchange_bytes(ss, 8)
+            q = ss["phases"]
+            strided[mode] = {"ms": round(ms_s, 5), "gbs": round(bs / (ms_s * 1e-3) / 1e9, 1),
+                             "ghosts": ss["ghosts"], "inter_msgs": q["INTER"]["msgs"],
+                             "inter_bytes": q["INTER"]["elems"] * 8,
+                             "max_inter_msgs_sent": q["INTER"]["max_msgs_sent"]}
+            ps_.close()
+            del vs_, ws_, rows
+        result["strided_partition"] = strided
         # reduced-precision values, float32 accumulation; error against the
         # float64 apply above (itself checked against the oracle by the tests)
         ref = w.cpu().numpy()

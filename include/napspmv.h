@@ -114,6 +114,14 @@ extern "C" {
  * the call order).  Batches refuse such plans (EUNSUPPORTED); servers run
  * them alone. */
 #define NAPSPMV_NAP_THREE_WAY 0x20u
+/* Strided partition (section 5.3): row r, and v_r, on process r mod n_p
+ * (row_starts must be NULL; EINVAL with NAPSPMV_NAP_SPLIT, whose pieces
+ * follow index order).  The plan, its exports and napspmv_apply work in the
+ * process-major numbering that a distributed code stores: position
+ * starts[p] + q holds row p + q n_p, with starts[p] = the rows of processes
+ * before p.  napspmv_plan_rows gives the original row of every position;
+ * v and w of an apply are in process-major order. */
+#define NAPSPMV_PARTITION_STRIDED 0x40u
 
 /* Stages of an apply; napspmv_apply runs LOCAL then REMOTE.  LOCAL is one
  * launch: the exchange gather (standard: every ghost from its owner; NAP:
@@ -182,6 +190,11 @@ NAPSPMV_API int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, c
                         int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
                         const int64_t *row_starts, uint32_t flags,
                         napspmv_plan_t *plan_out, napspmv_stats_t *stats_out);
+
+/* rows_out[k] (n entries, caller-owned host array) = the original row index
+ * held at position k of the plan's numbering: k itself unless the plan was
+ * built with NAPSPMV_PARTITION_STRIDED.  Works for host-only plans. */
+NAPSPMV_API int napspmv_plan_rows(napspmv_plan_t plan, int64_t *rows_out);
 
 /*
  * w = A v on the GPU, asynchronously on `stream` (standard_spmv or NAPSpMV,

@@ -25,6 +25,7 @@ PHASES = ("INTER", "L0", "L1", "L2")
 STAGE_LOCAL, STAGE_REMOTE = 0, 1
 HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
 VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20}
+PARTITION_STRIDED = 0x40
 PARAMS = {"block_nnz": 0, "bands": 1, "window": 2}
 _VAL_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
@@ -60,6 +61,7 @@ _SIGS = {
     "napspmv_apply": (I32, [P, P, P, P]),
     "napspmv_apply_stage": (I32, [P, I32, P, P, P]),
     "napspmv_plan_stats": (I32, [P, P]),
+    "napspmv_plan_rows": (I32, [P, P]),
     "napspmv_plan_export": (I32, [P, I32, P, P, P, P, P, P]),
     "napspmv_plan_ghosts": (I32, [P, P, P]),
     "napspmv_plan_read_ghost_values": (I32, [P, P, P, P]),
@@ -141,12 +143,14 @@ class Plan:
     NAP plan variants ("owner_map", "split", "dedup"; section 4.1): they
     change the messages, not the result; "three_way" sums each row in the
     three parts of algorithm NAPSpMV (on_process, on_node, off_node) with the
-    inter-node hop overlapped with the on_node product.
+    inter-node hop overlapped with the on_node product.  ``strided`` puts
+    row r on process r mod n_p (section 5.3); the plan, its exports and v, w
+    are then in process-major order (see ``rows``).
     """
 
     def __init__(self, rowptr, col, val, n: int, n_p: int, ppn: int, mode: str = "standard",
                  dtype: str = "f64", row_starts=None, host_only: bool = False,
-                 exchange_copy: bool = False, variant=()):
+                 exchange_copy: bool = False, variant=(), strided: bool = False):
         lib = load_library()
         unknown = set(variant) - set(VARIANTS)
         if unknown:
@@ -168,6 +172,9 @@ class Plan:
         flags = (HOST_ONLY if host_only else 0) | (EXCHANGE_COPY if exchange_copy else 0)
         for name in variant:
             flags |= VARIANTS[name]
+        if strided:
+            flags |= PARTITION_STRIDED
+        self.strided = bool(strided)
         self.variant = tuple(sorted(set(variant)))
         handle = ctypes.c_void_p()
         st = Stats()
@@ -208,6 +215,12 @@ class Plan:
         _check(lib.napspmv_plan_export(self._h, ph, None, None, src.ctypes.data,
                                        dst.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
         return src, dst, ptr, idx
+
+    def rows(self) -> np.ndarray:
+        """Original row index of every position of the plan's numbering."""
+        out = np.empty(self.n, np.int64)
+        _check(load_library().napspmv_plan_rows(self._h, out.ctypes.data))
+        return out
 
     def ghosts(self):
         """(ghost_ptr int64[n_p+1], ghost_col int32[G])."""

@@ -751,7 +751,8 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
     if (!plan_out) return fail(NAPSPMV_EINVAL, "plan_out is NULL");
     *plan_out = nullptr;
     if (flags & ~(NAPSPMV_HOST_ONLY | NAPSPMV_EXCHANGE_COPY | NAPSPMV_NAP_OWNER_MAP |
-                  NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY))
+                  NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY |
+                  NAPSPMV_PARTITION_STRIDED))
         return fail(NAPSPMV_EINVAL, "unknown flag bits");
     napspmv_plan_s *p = nullptr;
     const int rc = guarded([&]() {
@@ -760,7 +761,8 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         const auto t0 = std::chrono::steady_clock::now();
         napspmv::build_plan(p->hp, rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts,
                             flags & (NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP |
-                                     NAPSPMV_NAP_THREE_WAY));
+                                     NAPSPMV_NAP_THREE_WAY),
+                            (flags & NAPSPMV_PARTITION_STRIDED) != 0);
         const auto t1 = std::chrono::steady_clock::now();
         p->build_s = std::chrono::duration<double>(t1 - t0).count();
         p->G = p->hp.ghost_ptr.back();
@@ -1046,6 +1048,16 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
         if (best_ms) *best_ms = best;
         return NAPSPMV_OK;
     });
+}
+
+int napspmv_plan_rows(napspmv_plan_t plan, int64_t *rows_out) {
+    if (!plan || !rows_out) return fail(NAPSPMV_EINVAL, "plan or rows_out is NULL");
+    const HostPlan &hp = plan->hp;
+    if (hp.strided)
+        for (int64_t k = 0; k < hp.n; ++k) rows_out[k] = hp.rows_natural[k];
+    else
+        for (int64_t k = 0; k < hp.n; ++k) rows_out[k] = k;
+    return NAPSPMV_OK;
 }
 
 int napspmv_plan_stats(napspmv_plan_t plan, napspmv_stats_t *out) {

@@ -160,13 +160,56 @@ void release_device_arrays(HostPlan &hp) {
     std::vector<int32_t>().swap(hp.l2_dst);
 }
 
+namespace {
+
+// Strided partition (section 5.3: row r on process r mod n_p) as the
+// contiguous partition of the symmetrically permuted matrix P A P^T, with
+// row r at position starts[r mod n_p] + r div n_p: every set of the paper
+// depends only on which process owns which index, so the plan of the
+// permuted matrix is the strided plan with indices renumbered.
+void build_strided(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
+                   int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode, uint32_t variant) {
+    std::vector<int64_t> st(n_p + 1, 0);
+    for (int64_t p = 0; p < n_p; ++p) st[p + 1] = st[p] + (n - p + n_p - 1) / n_p;
+    auto pos = [&](int64_t r) { return st[r % n_p] + r / n_p; };
+    std::vector<int32_t> natural(n);
+    for (int64_t r = 0; r < n; ++r) natural[pos(r)] = (int32_t)r;
+    const int64_t vs = dtype == NAPSPMV_F64 ? 8 : dtype == NAPSPMV_F32 ? 4 : 2;
+    std::vector<int64_t> rp(n + 1, 0);
+    for (int64_t k = 0; k < n; ++k) rp[k + 1] = rp[k] + (rowptr[natural[k] + 1] - rowptr[natural[k]]);
+    std::vector<int32_t> c2(rp[n]);
+    std::vector<uint8_t> v2((size_t)(rp[n] * vs));
+    const uint8_t *vb = static_cast<const uint8_t *>(val);
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t r = natural[k], len = rowptr[r + 1] - rowptr[r];
+        for (int64_t e = 0; e < len; ++e) c2[rp[k] + e] = (int32_t)pos(col[rowptr[r] + e]);
+        if (len) std::memcpy(&v2[(size_t)(rp[k] * vs)], vb + rowptr[r] * vs, (size_t)(len * vs));
+    }
+    build_plan(hp, rp.data(), c2.data(), v2.data(), dtype, n, n_p, ppn, mode, st.data(), variant,
+               false);
+    hp.strided = true;
+    hp.rows_natural.swap(natural);
+}
+
+}  // namespace
+
 void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
-                const int64_t *row_starts, uint32_t variant) {
+                const int64_t *row_starts, uint32_t variant, bool strided) {
     validate(rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts);
     if (variant & ~kVariantFlags) throw Error(NAPSPMV_EINVAL, "unknown plan variant flag");
     if (variant && mode != NAPSPMV_NAP)
         throw Error(NAPSPMV_EINVAL, "plan variant flags apply to NAP plans only");
+    if (strided) {
+        if (row_starts) throw Error(NAPSPMV_EINVAL, "a strided partition takes no row_starts");
+        if (variant & NAPSPMV_NAP_SPLIT)
+            throw Error(NAPSPMV_EINVAL,
+                        "the split variant cuts E(n, m) in index order, which a strided "
+                        "partition does not keep");
+        build_strided(hp, rowptr, col, val, dtype, n, n_p, ppn, mode, variant);
+        return;
+    }
     hp.n = n;
     hp.nnz = rowptr[n];
     hp.n_p = n_p;

@@ -37,6 +37,11 @@ struct HostPlan {
     int mode = 0, dtype = 0;
     int64_t value_size = 8;            // bytes of one stored value of A
     std::vector<int64_t> starts;       // row block boundaries, n_p + 1
+    // Strided partition (row r on process r mod n_p): the plan works on the
+    // process-major renumbering (position starts[r mod n_p] + r div n_p);
+    // rows_natural[k] is the original row at position k.  Empty otherwise.
+    bool strided = false;
+    std::vector<int32_t> rows_natural;
     std::vector<int64_t> ghost_ptr;    // n_p + 1
     std::vector<int32_t> ghost_col;    // G, each process's list ascending
     int64_t nnz_on = 0, nnz_off = 0;
@@ -72,10 +77,11 @@ struct HostPlan {
 };
 
 // Validates the inputs and builds the plan.  `variant` holds NAPSPMV_NAP_*
-// flags (NAP mode only).  Throws Error or std::bad_alloc.
+// flags (NAP mode only); `strided` selects the strided partition (then
+// row_starts must be NULL).  Throws Error or std::bad_alloc.
 void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
-                const int64_t *row_starts, uint32_t variant);
+                const int64_t *row_starts, uint32_t variant, bool strided = false);
 
 // Frees the host copies of the split matrix and device lists after upload
 // (row pointers and row windows stay: launch schedules are rebuilt from them).
