@@ -411,6 +411,16 @@ def main():
             var[name] = {k: {"msgs": q[k]["msgs"], "elems": q[k]["elems"],
                              "max_msgs_sent": q[k]["max_msgs_sent"]} for k in ("INTER", "L0", "L1", "L2")}
         result["nap_variant_messages"] = var
+        # third hierarchy level: intra-node messages on and off a socket of 8 ranks
+        lev = {"procs_per_socket": 8}
+        for mode in ("standard", "nap"):
+            with nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode=mode,
+                          row_starts=wl.row_starts, host_only=True) as ph:
+                q = ph.level_stats(8)
+            lev[mode] = {k: {side: {"msgs": q[k][side]["msgs"], "bytes": q[k][side]["elems"] * 8}
+                             for side in ("on_socket", "off_socket")}
+                         for k in ("L0", "L1", "L2") if mode == "nap" or k == "L2"}
+        result["socket_level"] = lev
         # strided partition (row r on process r mod n_p): process-major v and w
         strided = {}
         for mode in ("standard", "nap"):

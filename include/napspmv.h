@@ -191,6 +191,15 @@ NAPSPMV_API int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, c
                         const int64_t *row_starts, uint32_t flags,
                         napspmv_plan_t *plan_out, napspmv_stats_t *stats_out);
 
+/* Third hierarchy level (section 6, future work: intra-node messages split
+ * into on-socket and off-socket).  Sockets hold procs_per_socket
+ * consecutive ranks (it must divide ppn).  out[2 phase] receives the
+ * statistics of the phase's messages whose source and destination share a
+ * socket, out[2 phase + 1] those of the others (8 entries, caller-owned).
+ * Inter-node messages are always off-socket.  Works for host-only plans. */
+NAPSPMV_API int napspmv_plan_level_stats(napspmv_plan_t plan, int64_t procs_per_socket,
+                                         napspmv_phase_stats_t *out);
+
 /* rows_out[k] (n entries, caller-owned host array) = the original row index
  * held at position k of the plan's numbering: k itself unless the plan was
  * built with NAPSPMV_PARTITION_STRIDED.  Works for host-only plans. */

@@ -239,3 +239,17 @@ def phase_stats(phase, n_p: int) -> dict:
     out["max_elems_recv"] = int(np.bincount(dst, weights=sizes, minlength=n_p).max()) if src.size else 0
     out["max_msg_elems"] = int(sizes.max()) if src.size else 0
     return out
+
+
+def level_stats(phase, n_p: int, pps: int) -> dict:
+    """A third hierarchy level (section 6): the phase's messages split into
+    those whose source and destination lie on the same socket of ``pps``
+    consecutive ranks, and the others, each with ``phase_stats``."""
+    src, dst, ptr, idx = phase
+    out = {}
+    for side, keep in (("on_socket", src // pps == dst // pps), ("off_socket", src // pps != dst // pps)):
+        k = np.flatnonzero(keep)
+        sizes = np.diff(ptr)[k]
+        sub_ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        out[side] = phase_stats((src[k], dst[k], sub_ptr, None), n_p)
+    return out

@@ -62,6 +62,7 @@ _SIGS = {
     "napspmv_apply_stage": (I32, [P, I32, P, P, P]),
     "napspmv_plan_stats": (I32, [P, P]),
     "napspmv_plan_rows": (I32, [P, P]),
+    "napspmv_plan_level_stats": (I32, [P, I64, P]),
     "napspmv_plan_export": (I32, [P, I32, P, P, P, P, P, P]),
     "napspmv_plan_ghosts": (I32, [P, P, P]),
     "napspmv_plan_read_ghost_values": (I32, [P, P, P, P]),
@@ -215,6 +216,15 @@ class Plan:
         _check(lib.napspmv_plan_export(self._h, ph, None, None, src.ctypes.data,
                                        dst.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
         return src, dst, ptr, idx
+
+    def level_stats(self, procs_per_socket: int) -> dict:
+        """Per phase, statistics of its on-socket and off-socket messages
+        (sockets of ``procs_per_socket`` consecutive ranks)."""
+        out = (PhaseStats * 8)()
+        _check(load_library().napspmv_plan_level_stats(self._h, int(procs_per_socket), out))
+        return {PHASES[ph]: {side: {k: getattr(out[2 * ph + i], k) for k, _ in PhaseStats._fields_}
+                             for i, side in enumerate(("on_socket", "off_socket"))}
+                for ph in range(4)}
 
     def rows(self) -> np.ndarray:
         """Original row index of every position of the plan's numbering."""

@@ -1050,6 +1050,22 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
     });
 }
 
+int napspmv_plan_level_stats(napspmv_plan_t plan, int64_t procs_per_socket,
+                             napspmv_phase_stats_t *out) {
+    if (!plan || !out) return fail(NAPSPMV_EINVAL, "plan or out is NULL");
+    if (procs_per_socket < 1 || plan->hp.ppn % procs_per_socket != 0)
+        return fail(NAPSPMV_EINVAL, "procs_per_socket must divide ppn");
+    return guarded([&]() {
+        napspmv::PhaseStats st[8];
+        napspmv::level_stats(plan->hp, procs_per_socket, st);
+        for (int k = 0; k < 8; ++k)
+            out[k] = napspmv_phase_stats_t{st[k].msgs, st[k].elems, st[k].max_msgs_sent,
+                                           st[k].max_elems_sent, st[k].max_msgs_recv,
+                                           st[k].max_elems_recv, st[k].max_msg_elems};
+        return NAPSPMV_OK;
+    });
+}
+
 int napspmv_plan_rows(napspmv_plan_t plan, int64_t *rows_out) {
     if (!plan || !rows_out) return fail(NAPSPMV_EINVAL, "plan or rows_out is NULL");
     const HostPlan &hp = plan->hp;

@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <numeric>
 
 #include <omp.h>
@@ -88,14 +89,16 @@ void finalize_phase(std::vector<MsgRef> &refs, Phase &ph) {
         std::memcpy(ph.idx.data() + ph.ptr[k], refs[k].data, sizeof(int32_t) * refs[k].len);
 }
 
-PhaseStats phase_stats(const Phase &ph, int64_t n_p) {
+// Statistics of the messages of `ph` for which keep(k) holds (all if null).
+PhaseStats phase_stats(const Phase &ph, int64_t n_p, const std::function<bool(size_t)> &keep = nullptr) {
     PhaseStats s;
     const size_t m = ph.src.size();
-    s.msgs = (int64_t)m;
-    s.elems = ph.ptr.back();
     std::vector<int64_t> ms(n_p, 0), es(n_p, 0), mr(n_p, 0), er(n_p, 0);
     for (size_t k = 0; k < m; ++k) {
+        if (keep && !keep(k)) continue;
         int64_t len = ph.ptr[k + 1] - ph.ptr[k];
+        s.msgs += 1;
+        s.elems += len;
         ms[ph.src[k]] += 1;
         es[ph.src[k]] += len;
         mr[ph.dst[k]] += 1;
@@ -144,6 +147,14 @@ void validate(const int64_t *rowptr, const int32_t *col, const void *val, int dt
 }
 
 }  // namespace
+
+void level_stats(const HostPlan &hp, int64_t pps, PhaseStats out[8]) {
+    for (int ph = 0; ph < 4; ++ph) {
+        const Phase &P = hp.phase[ph];
+        out[2 * ph] = phase_stats(P, hp.n_p, [&](size_t k) { return P.src[k] / pps == P.dst[k] / pps; });
+        out[2 * ph + 1] = phase_stats(P, hp.n_p, [&](size_t k) { return P.src[k] / pps != P.dst[k] / pps; });
+    }
+}
 
 void release_device_arrays(HostPlan &hp) {
     std::vector<int32_t>().swap(hp.col_on);

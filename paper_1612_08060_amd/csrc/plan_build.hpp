@@ -83,6 +83,12 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
                 const int64_t *row_starts, uint32_t variant, bool strided = false);
 
+// Message statistics split by a third hierarchy level (section 6 names
+// on-socket and off-socket intra-node messages): sockets of `pps`
+// consecutive ranks; out[2 ph] = messages of phase ph whose source and
+// destination share a socket, out[2 ph + 1] = the others.
+void level_stats(const HostPlan &hp, int64_t pps, PhaseStats out[8]);
+
 // Frees the host copies of the split matrix and device lists after upload
 // (row pointers and row windows stay: launch schedules are rebuilt from them).
 void release_device_arrays(HostPlan &hp);
