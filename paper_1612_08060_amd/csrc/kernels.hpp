@@ -116,6 +116,12 @@ __device__ __forceinline__ void gather_item(int2 it, const int32_t *__restrict__
 // x comes from `xsrc` (v for the on-process part, the ghost buffer for the
 // off-process part), or, for on-process columns inside the block's window
 // win = (first, length) of v, from a copy of that window staged in LDS.
+//
+// Off-process blocks of at most CAP entries are stored in gather order
+// (ascending ghost position, so a wave's lanes read nearby ghost values and
+// share cache lines); slot[k] is the stored position of entry k inside its
+// block, where its product lands in LDS, so the row sums still run in
+// stored order.
 constexpr int kMaxRows = 1024;
 
 template <typename VT, typename XT, int CAP, int W, bool REMOTE>
@@ -123,6 +129,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
                                               int2 win, const int32_t *__restrict__ rowptr,
                                               const int32_t *__restrict__ col,
                                               const VT *__restrict__ val,
+                                              const uint16_t *__restrict__ slot,
                                               const XT *__restrict__ xsrc, XT *__restrict__ w,
                                               XT *prod, XT *wbuf) {
     constexpr int U = CAP / kBlock;
@@ -146,12 +153,14 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
     }
     int32_t c[U];
     XT a[U];
+    int32_t sl[REMOTE ? U : 1];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t k = k0 + u * kBlock + tid;
         if (k < k1) {
             c[u] = __builtin_nontemporal_load(col + k);
             a[u] = (XT)load_val(val, k);
+            if (REMOTE) sl[REMOTE ? u : 0] = __builtin_nontemporal_load(slot + k);
         }
     }
     XT t[W > 0 ? W / kBlock : 1];
@@ -192,7 +201,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
         const int32_t k = k0 + u * kBlock + tid;
         if (k < k1) {
             if (W > 0 && (uint32_t)(c[u] - win.x) < (uint32_t)win.y) x[u] = wbuf[c[u] - win.x];
-            prod[k - k0] = a[u] * x[u];
+            prod[REMOTE ? sl[REMOTE ? u : 0] : k - k0] = a[u] * x[u];
         }
     }
     __syncthreads();
@@ -229,6 +238,7 @@ struct RemoteView {
     int32_t n_blocks;
     const int32_t *rowblk, *blkptr, *rowptr, *col;
     const VT *val;
+    const uint16_t *slot;      // stored position of each entry inside its block
     const XT *ghost;
     XT *w;
 };
@@ -254,15 +264,15 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
     }
     const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
     product_block<VT, XT, CAP, W, false>(L.rowblk[task], L.rowblk[task + 1], L.blkptr[task],
-                                         L.blkptr[task + 1], wn, L.rowptr, L.col, L.val, L.v,
-                                         L.w, prod, wbuf);
+                                         L.blkptr[task + 1], wn, L.rowptr, L.col, L.val, nullptr,
+                                         L.v, L.w, prod, wbuf);
 }
 
 template <typename VT, typename XT, int CAP>
 __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
     product_block<VT, XT, CAP, 0, true>(R.rowblk[b], R.rowblk[b + 1], R.blkptr[b],
                                         R.blkptr[b + 1], make_int2(0, 0), R.rowptr, R.col, R.val,
-                                        R.ghost, R.w, prod, nullptr);
+                                        R.slot, R.ghost, R.w, prod, nullptr);
 }
 
 // Index of the entry of prefix[0..count] (ascending, prefix[0] = 0) whose

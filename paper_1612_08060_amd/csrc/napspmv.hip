@@ -60,6 +60,9 @@ struct napspmv_plan_s {
     // that run the inter-node hop and scatter beside the on_node product
     int32_t *d_rp_nd = nullptr, *d_col_nd = nullptr;
     void *d_val_nd = nullptr;
+    // gather order of the off-process (and on_node) blocks; see sort_blocks
+    uint16_t *d_slot_off = nullptr, *d_slot_nd = nullptr;
+    int sorted_cap = 0;              // block size the device entry order was sorted for
     hipStream_t helper = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void *d_ws = nullptr;            // the plan's own workspace (ghost, send, receive)
@@ -193,10 +196,13 @@ void free_device(napspmv_plan_s *p) {
     p->part_ready = false;
     void *ptrs[] = {p->d_rp_on, p->d_col_on, p->d_rp_off, p->d_col_off, p->d_val_on,
                     p->d_val_off, p->d_gather, p->d_pack, p->d_ssrc, p->d_sdst, p->d_lsrc,
-                    p->d_ldst, p->d_ws, p->d_rp_nd, p->d_col_nd, p->d_val_nd};
+                    p->d_ldst, p->d_ws, p->d_rp_nd, p->d_col_nd, p->d_val_nd,
+                    p->d_slot_off, p->d_slot_nd};
     for (void *q : ptrs) free_ptr(q);
     p->d_rp_nd = p->d_col_nd = nullptr;
     p->d_val_nd = nullptr;
+    p->d_slot_off = p->d_slot_nd = nullptr;
+    p->sorted_cap = 0;
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->helper) (void)hipStreamDestroy(p->helper);
@@ -215,6 +221,7 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
     int64_t b = (int64_t)(hp.rowptr_on.size() + hp.col_on.size() + hp.rowptr_off.size() +
                           hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
     b += (int64_t)(hp.rowptr_nd.size() + hp.col_nd.size()) * 4 + (int64_t)hp.val_nd.size();
+    b += (int64_t)(hp.col_off.size() + hp.col_nd.size()) * 2;   // gather-order slots
     b += (int64_t)(hp.gather_idx.size() + hp.pack_idx.size() + hp.scat_src.size() +
                    hp.scat_dst.size() + hp.l2_src.size() + hp.l2_dst.size()) * 4;
     return b + ws_layout(p).total;
@@ -299,6 +306,21 @@ void build_partitions(napspmv_plan_s *p) {
     p->part_ready = true;
 }
 
+// Reorder the entries of every block into gather order (sort_blocks) and
+// copy them, with their slots, over the device arrays (already allocated).
+void sort_upload(const std::vector<int32_t> &col, const std::vector<uint8_t> &val, int vs,
+                 const std::vector<int32_t> &blkptr, int cap, int32_t *d_col, void *d_val,
+                 uint16_t *d_slot) {
+    if (col.empty()) return;
+    std::vector<int32_t> c2(col.size());
+    std::vector<uint8_t> v2(val.size());
+    std::vector<uint16_t> s2(col.size());
+    napspmv::sort_blocks(blkptr, cap, col.data(), val.data(), vs, c2.data(), v2.data(), s2.data());
+    HIP_OK(hipMemcpy(d_col, c2.data(), c2.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d_val, v2.data(), v2.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d_slot, s2.data(), s2.size() * 2, hipMemcpyHostToDevice));
+}
+
 // (Re)build the launch schedules for the current tuning: on-process row
 // blocks with their v windows, off-process row blocks, the exchange items
 // (standard: ghost gather by column band; NAP: pack in order) and the task
@@ -311,14 +333,27 @@ void refresh_schedules(napspmv_plan_s *p) {
     std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks;
     napspmv::row_blocks(hp.rowptr_on.data(), hp.n, cap, kMaxRowsPerBlock, onblk, onptr);
     if (win > 0) napspmv::row_block_windows(onblk, hp.on_lo, hp.on_hi, hp.n, win, wins);
-    napspmv::row_blocks(hp.rowptr_off.data(), hp.n, cap, kMaxRowsPerBlock, offblk, offptr);
+    napspmv::row_blocks_per_process(hp.rowptr_off.data(), hp.starts, cap, kMaxRowsPerBlock, offblk,
+                                    offptr);
     if (hp.mode == NAPSPMV_STANDARD)
         napspmv::gather_items(hp.ghost_ptr, hp.ghost_col, hp.n, bands, kMaxItem, items);
     else
         napspmv::flat_items(p->E, kMaxItem, items);
     napspmv::merge_tasks((int64_t)items.size() / 2, (int64_t)onblk.size() - 1, tasks);
     std::vector<int32_t> ndblk, ndptr;
-    if (hp.three_way) napspmv::row_blocks(hp.rowptr_nd.data(), hp.n, cap, kMaxRowsPerBlock, ndblk, ndptr);
+    if (hp.three_way)
+        napspmv::row_blocks_per_process(hp.rowptr_nd.data(), hp.starts, cap, kMaxRowsPerBlock,
+                                        ndblk, ndptr);
+    if (cap != p->sorted_cap) {
+        // entry order of the off-process blocks follows the block cuts
+        HIP_OK(hipDeviceSynchronize());
+        sort_upload(hp.col_off, hp.val_off, (int)hp.value_size, offptr, cap, p->d_col_off,
+                    p->d_val_off, p->d_slot_off);
+        if (hp.three_way)
+            sort_upload(hp.col_nd, hp.val_nd, (int)hp.value_size, ndptr, cap, p->d_col_nd,
+                        p->d_val_nd, p->d_slot_nd);
+        p->sorted_cap = cap;
+    }
     upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr);
     p->cur_block_nnz = cap;
     p->cur_window = win;
@@ -340,7 +375,16 @@ void to_device(napspmv_plan_s *p) {
         upload(p->d_rp_on, hp.rowptr_on, total);
         upload(p->d_col_on, hp.col_on, total);
         upload(p->d_rp_off, hp.rowptr_off, total);
-        upload(p->d_col_off, hp.col_off, total);
+        auto alloc = [&](auto *&dst, size_t bytes) {
+            if (!bytes) return;
+            HIP_OK(hipMalloc(reinterpret_cast<void **>(&dst), bytes));
+            total += (int64_t)bytes;
+        };
+        // entry arrays of the off-process blocks: filled in gather order by
+        // refresh_schedules
+        alloc(p->d_col_off, hp.col_off.size() * 4);
+        alloc(p->d_val_off, hp.val_off.size());
+        alloc(p->d_slot_off, hp.col_off.size() * 2);
         auto upload_bytes = [&](void *&dst, const std::vector<uint8_t> &src) {
             if (src.empty()) return;
             HIP_OK(hipMalloc(&dst, src.size()));
@@ -348,11 +392,11 @@ void to_device(napspmv_plan_s *p) {
             HIP_OK(hipMemcpy(dst, src.data(), src.size(), hipMemcpyHostToDevice));
         };
         upload_bytes(p->d_val_on, hp.val_on);
-        upload_bytes(p->d_val_off, hp.val_off);
         if (hp.three_way) {
             upload(p->d_rp_nd, hp.rowptr_nd, total);
-            upload(p->d_col_nd, hp.col_nd, total);
-            upload_bytes(p->d_val_nd, hp.val_nd);
+            alloc(p->d_col_nd, hp.col_nd.size() * 4);
+            alloc(p->d_val_nd, hp.val_nd.size());
+            alloc(p->d_slot_nd, hp.col_nd.size() * 2);
             HIP_OK(hipStreamCreateWithFlags(&p->helper, hipStreamNonBlocking));
             HIP_OK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
             HIP_OK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
@@ -417,6 +461,7 @@ napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules
     R.rowptr = on_node ? p->d_rp_nd : p->d_rp_off;
     R.col = on_node ? p->d_col_nd : p->d_col_off;
     R.val = static_cast<const VT *>(on_node ? p->d_val_nd : p->d_val_off);
+    R.slot = on_node ? p->d_slot_nd : p->d_slot_off;
     R.ghost = static_cast<const XT *>(ws.ghost);
     R.w = w;
     return R;

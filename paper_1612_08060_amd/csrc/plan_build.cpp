@@ -158,11 +158,7 @@ void level_stats(const HostPlan &hp, int64_t pps, PhaseStats out[8]) {
 
 void release_device_arrays(HostPlan &hp) {
     std::vector<int32_t>().swap(hp.col_on);
-    std::vector<int32_t>().swap(hp.col_off);
-    std::vector<int32_t>().swap(hp.col_nd);
-    std::vector<uint8_t>().swap(hp.val_nd);
     std::vector<uint8_t>().swap(hp.val_on);
-    std::vector<uint8_t>().swap(hp.val_off);
     std::vector<int32_t>().swap(hp.gather_idx);
     std::vector<int32_t>().swap(hp.pack_idx);
     std::vector<int32_t>().swap(hp.scat_src);

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
+#include <numeric>
 
 namespace napspmv {
 
@@ -23,6 +25,52 @@ void row_blocks(const int32_t *rowptr, int64_t n, int cap, int max_rows,
     }
     rowblk.push_back((int32_t)n);
     blkptr.push_back(rowptr[n]);
+}
+
+void row_blocks_per_process(const int32_t *rowptr, const std::vector<int64_t> &starts, int cap,
+                            int max_rows, std::vector<int32_t> &rowblk,
+                            std::vector<int32_t> &blkptr) {
+    rowblk.clear();
+    blkptr.clear();
+    const int64_t n_p = (int64_t)starts.size() - 1;
+    std::vector<int32_t> rb, bp;
+    for (int64_t t = 0; t < n_p; ++t) {
+        const int64_t r0 = starts[t], r1 = starts[t + 1];
+        row_blocks(rowptr + r0, r1 - r0, cap, max_rows, rb, bp);
+        for (size_t b = 0; b + 1 < rb.size(); ++b) {
+            rowblk.push_back(rb[b] + (int32_t)r0);
+            blkptr.push_back(bp[b]);
+        }
+    }
+    rowblk.push_back((int32_t)starts[n_p]);
+    blkptr.push_back(rowptr[starts[n_p]]);
+}
+
+void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col,
+                 const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
+                 uint16_t *slot_out) {
+    const int64_t nb = (int64_t)blkptr.size() - 1;
+#pragma omp parallel
+    {
+        std::vector<int32_t> ord;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t k0 = blkptr[b], len = blkptr[b + 1] - k0;
+            ord.resize((size_t)len);
+            std::iota(ord.begin(), ord.end(), 0);
+            const bool sorted = len <= cap;
+            if (sorted)
+                std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+                    return col[k0 + x] < col[k0 + y];
+                });
+            for (int64_t q = 0; q < len; ++q) {
+                const int64_t from = k0 + ord[q];
+                col_out[k0 + q] = col[from];
+                std::memcpy(val_out + (k0 + q) * vs, val + from * vs, (size_t)vs);
+                slot_out[k0 + q] = (uint16_t)(sorted ? ord[q] : 0);
+            }
+        }
+    }
 }
 
 void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int32_t> &on_lo,

@@ -13,6 +13,22 @@ namespace napspmv {
 void row_blocks(const int32_t *rowptr, int64_t n, int cap, int max_rows,
                 std::vector<int32_t> &rowblk, std::vector<int32_t> &blkptr);
 
+// Row blocks of each process's rows [starts[t], starts[t+1]) in turn, so no
+// block holds rows of two processes (the per-process launches of a
+// partition use exactly these blocks).  Same encoding as row_blocks.
+void row_blocks_per_process(const int32_t *rowptr, const std::vector<int64_t> &starts, int cap,
+                            int max_rows, std::vector<int32_t> &rowblk,
+                            std::vector<int32_t> &blkptr);
+
+// Gather order of a block's entries: each block [blkptr[b], blkptr[b+1]) of
+// at most `cap` entries is reordered by ascending column (stable), so the
+// lanes of a wave read nearby ghost values; slot_out[k] = the stored
+// position, inside its block, of the entry now at k.  Longer blocks (a
+// single long row) keep stored order (slot 0).  `vs` = bytes of one value.
+void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col,
+                 const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
+                 uint16_t *slot_out);
+
 // The window of v (first column, length <= `window`) each row block stages
 // in LDS, as interleaved pairs: the block's whole on-process column range if
 // it fits, otherwise `window` columns centred on the block's rows inside that
