@@ -273,7 +273,7 @@ NAPSPMV_API int napspmv_graph_create(napspmv_plan_t plan, const void *v, void *w
 NAPSPMV_API int napspmv_graph_launch(void *graph, void *stream);
 NAPSPMV_API int napspmv_graph_destroy(void *graph);
 
-/* Autotuner: times every (BLOCK_NNZ, VWINDOW, GATHER_BANDS) candidate on
+/* Autotuner: times every (BLOCK_NNZ, VWINDOW, GATHER_ITEM) candidate on
  * this plan with `reps` applies each (HIP events on `stream`; w is
  * overwritten) and keeps the fastest.  With cache_path (may be NULL), a
  * result already cached for the same device and workload shape is used
@@ -349,16 +349,18 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
  * device plan rebuilds and re-uploads the launch schedules (it allocates and
  * synchronizes the device): do not call it while an apply of the plan is in
  * flight.
- *   BLOCK_NNZ     entries per row block of both products: 1024, 2048, 4096
+ *   BLOCK_NNZ     entries per row block of both products, and columns of v
+ *                 per band of the exchange buffers: 1024, 2048, 4096
  *                 (automatic: 4096)
- *   GATHER_BANDS  standard exchange: column bands of v that order the ghost
- *                 gather, 1..4096 (automatic: about 2 MiB of v per band)
+ *   GATHER_ITEM   most entries of one exchange work item (a slice of one
+ *                 band of the ghost or send buffer), 256 .. 2^24
+ *                 (automatic: 65536)
  *   VWINDOW       on-process product: most elements of v a row block stages
  *                 in LDS, 0 (none), 1024, 2048, 4096 (automatic: 1024)
 
  * get_param returns the value in effect, or a negative error code. */
 #define NAPSPMV_PARAM_BLOCK_NNZ    0
-#define NAPSPMV_PARAM_GATHER_BANDS 1
+#define NAPSPMV_PARAM_GATHER_ITEM  1
 #define NAPSPMV_PARAM_VWINDOW      2
 
 NAPSPMV_API int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value);

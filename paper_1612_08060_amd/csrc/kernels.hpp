@@ -48,28 +48,6 @@ __device__ __forceinline__ float load_val(const uint16_t *p, int32_t k) {
     return __uint_as_float((uint32_t)b << 16);   // bfloat16 -> float32 is exact
 }
 
-// Two indexed copies in one launch, XCD-aware: ghost[d1[k]] = s1v[s1[k]]
-// (received inter-node values, to their users on the node) in the first nb1
-// logical blocks, ghost[d2[k]] = s2v[s2[k]] (fully local on-node values) in
-// the rest.  Each ghost slot appears in exactly one of the two lists, once.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_scatter2(
-    int32_t n1, const int32_t *__restrict__ s1, const int32_t *__restrict__ d1,
-    const T *__restrict__ s1v, int32_t n2, const int32_t *__restrict__ s2,
-    const int32_t *__restrict__ d2, const T *__restrict__ s2v, T *__restrict__ ghost,
-    uint32_t nb1) {
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    if (b < nb1) {
-        const uint32_t k = b * kBlock + threadIdx.x;
-        if (k < (uint32_t)n1)
-            ghost[__builtin_nontemporal_load(d1 + k)] = s1v[__builtin_nontemporal_load(s1 + k)];
-    } else {
-        const uint32_t k = (b - nb1) * kBlock + threadIdx.x;
-        if (k < (uint32_t)n2)
-            ghost[__builtin_nontemporal_load(d2 + k)] = s2v[__builtin_nontemporal_load(s2 + k)];
-    }
-}
-
 // dst[k] = src[k]: the explicit inter-node hop (send buffer -> receive buffer).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const T *__restrict__ src,
@@ -78,25 +56,101 @@ __global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const T *__restrict_
     if (k < (uint32_t)n) dst[k] = src[k];
 }
 
-// dst[k] = src[idx[k]] for k in [start, start + len): one work item of a
-// phase's concatenated messages (the standard ghost gather, or the NAP pack
-// of the inter-node send buffer).  Four independent loads per lane in flight.
-template <typename T>
-__device__ __forceinline__ void gather_item(int2 it, const int32_t *__restrict__ idx,
-                                            const T *__restrict__ src, T *__restrict__ dst) {
-    const int32_t end = it.x + it.y;
-    int32_t k = it.x + (int32_t)threadIdx.x;
-    for (; k + 3 * kBlock < end; k += 4 * kBlock) {
-        int32_t j[4];
+// Exchange buffers (the ghost buffer, the NAP send buffer) are laid out band
+// by band: band b holds, in order, the entries whose source column of v lies
+// in [b*CAP, (b+1)*CAP), grouped by message (each process's ghosts, or each
+// inter-node message) in ascending column.  A band item (x = b >= 0, entries
+// [y, y+z)) stages that slice of the source vector in LDS with coalesced
+// loads and then writes its entries in order: dst[k] = lds[off[k]], a
+// streaming write fed by LDS reads, instead of one scattered L2 read per
+// entry.  An indexed item (x = -1) is the plain form, dst[dpos[k]] =
+// src[idx[k]] over entries [y, y+z), used by the per-process launches.
+template <typename T, int CAP>
+__device__ __forceinline__ void stage_band(int32_t band, int32_t n, const T *__restrict__ src,
+                                           T *lds) {
+    const int64_t c0 = (int64_t)band * CAP;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) j[u] = __builtin_nontemporal_load(idx + k + u * kBlock);
+    for (int u = 0; u < CAP / kBlock; ++u) {
+        const int64_t c = c0 + u * kBlock + threadIdx.x;
+        if (c < n) lds[u * kBlock + threadIdx.x] = src[c];
+    }
+    __syncthreads();
+}
+
+template <typename T, int CAP>
+__device__ __forceinline__ void exchange_item(int4 it, int32_t n, const uint16_t *__restrict__ off,
+                                              const int32_t *__restrict__ idx,
+                                              const int32_t *__restrict__ dpos,
+                                              const T *__restrict__ src, T *__restrict__ dst,
+                                              T *lds) {
+    const int32_t end = it.y + it.z;
+    int32_t k = it.y + (int32_t)threadIdx.x;
+    if (it.x >= 0) {
+        stage_band<T, CAP>(it.x, n, src, lds);
+        for (; k + 7 * kBlock < end; k += 8 * kBlock) {
+            uint16_t o[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) o[u] = __builtin_nontemporal_load(off + k + u * kBlock);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dst[k + u * kBlock] = lds[o[u]];
+        }
+        for (; k < end; k += kBlock) dst[k] = lds[__builtin_nontemporal_load(off + k)];
+        return;
+    }
+    for (; k + 3 * kBlock < end; k += 4 * kBlock) {
+        int32_t j[4], d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            j[u] = __builtin_nontemporal_load(idx + k + u * kBlock);
+            d[u] = __builtin_nontemporal_load(dpos + k + u * kBlock);
+        }
         T x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) x[u] = src[j[u]];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dst[k + u * kBlock] = x[u];
+        for (int u = 0; u < 4; ++u) dst[d[u]] = x[u];
     }
-    for (; k < end; k += kBlock) dst[k] = src[__builtin_nontemporal_load(idx + k)];
+    for (; k < end; k += kBlock)
+        dst[__builtin_nontemporal_load(dpos + k)] = src[__builtin_nontemporal_load(idx + k)];
+}
+
+// NAP scatter of one band of the ghost buffer (band-ordered like the
+// exchange buffers): each ghost position's code says where its value comes
+// from: bit 31 set, the fully local step, column offset code & 0x7fffffff
+// inside the band of v (staged in LDS); clear, the received inter-node
+// buffer at position code.  `which` = 0 fills every position, 1 only
+// received values, 2 only fully local values.
+constexpr uint32_t kFromV = 0x80000000u;
+
+template <typename T, int CAP>
+__device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
+                                             const uint32_t *__restrict__ code,
+                                             const T *__restrict__ v, const T *__restrict__ recv,
+                                             T *__restrict__ ghost, T *lds) {
+    if (which != 1) stage_band<T, CAP>(it.x, n, v, lds);
+    const int32_t end = it.y + it.z;
+    int32_t k = it.y + (int32_t)threadIdx.x;
+    for (; k + 3 * kBlock < end; k += 4 * kBlock) {
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = __builtin_nontemporal_load(code + k + u * kBlock);
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool fv = (c[u] & kFromV) != 0;
+            if (fv ? which != 1 : which != 2) x[u] = fv ? lds[c[u] & ~kFromV] : recv[c[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool fv = (c[u] & kFromV) != 0;
+            if (fv ? which != 1 : which != 2) ghost[k + u * kBlock] = x[u];
+        }
+    }
+    for (; k < end; k += kBlock) {
+        const uint32_t c = __builtin_nontemporal_load(code + k);
+        const bool fv = (c & kFromV) != 0;
+        if (fv ? which != 1 : which != 2) ghost[k] = fv ? lds[c & ~kFromV] : recv[c];
+    }
 }
 
 // One row block of a split CSR product.  The block owns rows [r0, r1) (at
@@ -222,9 +276,11 @@ template <typename VT, typename XT>
 struct LocalView {
     const int32_t *tasks;      // task list: ~i exchange item, b >= 0 on-process block
     int32_t n_tasks;
-    const int2 *items;         // exchange items (start, len)
-    const int32_t *idx;        // exchange source indices (columns of v)
+    const int4 *items;         // exchange items (band or indexed; see exchange_item)
+    const uint16_t *off;       // band items: column offset in the band of every entry
+    const int32_t *idx, *dpos; // indexed items: source column, destination position
     XT *xdst;                  // exchange destination (ghost buffer or NAP send buffer)
+    int32_t n;                 // length of v
     const int32_t *rowblk, *blkptr;
     const int2 *win;           // v windows of the on-process blocks (or null)
     const int32_t *rowptr, *col;
@@ -245,13 +301,12 @@ struct RemoteView {
 
 template <typename XT>
 struct ScatterView {
-    int32_t n1;                // received values -> ghost slots
-    const int32_t *s1, *d1;
-    const XT *s1v;
-    int32_t n2;                // fully local values -> ghost slots
-    const int32_t *s2, *d2;
-    const XT *s2v;
+    const int4 *items;         // band items over the ghost buffer
+    int32_t n_items;
+    const uint32_t *code;      // per ghost position, see scatter_item
+    const XT *v, *recv;
     XT *ghost;
+    int32_t n, which;
 };
 
 template <typename VT, typename XT, int CAP, int W>
@@ -259,7 +314,7 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
                                            XT *wbuf) {
     const int32_t task = L.tasks[t];
     if (task < 0) {
-        gather_item(L.items[~task], L.idx, L.v, L.xdst);
+        exchange_item<XT, CAP>(L.items[~task], L.n, L.off, L.idx, L.dpos, L.v, L.xdst, prod);
         return;
     }
     const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
@@ -327,27 +382,25 @@ __global__ __launch_bounds__(kBlock) void k_remote_batch(const RemoteView<VT, XT
     remote_block<VT, XT, CAP>(views[i], b - prefix[i], prod);
 }
 
-// Batched NAP scatter: views[i] owns blocks [prefix[i], prefix[i+1]); each
-// view's first ceil(n1/256) blocks copy received values, the rest fully
-// local values.
-template <typename XT>
+// NAP scatter: one band item per block.
+template <typename XT, int CAP>
+__global__ __launch_bounds__(kBlock) void k_scatter(ScatterView<XT> S) {
+    __shared__ XT lds[CAP];
+    scatter_item<XT, CAP>(S.items[xcd_block(blockIdx.x, gridDim.x)], S.n, S.which, S.code, S.v,
+                          S.recv, S.ghost, lds);
+}
+
+// Batched NAP scatter: views[i] owns blocks [prefix[i], prefix[i+1]), one
+// band item each.
+template <typename XT, int CAP>
 __global__ __launch_bounds__(kBlock) void k_scatter_batch(const ScatterView<XT> *__restrict__ views,
                                                           const int32_t *__restrict__ prefix,
                                                           int32_t count) {
+    __shared__ XT lds[CAP];
     const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
     const int32_t i = find_range(prefix, count, b);
     const ScatterView<XT> &S = views[i];
-    const uint32_t lb = (uint32_t)(b - prefix[i]);
-    const uint32_t nb1 = ((uint32_t)S.n1 + kBlock - 1) / kBlock;
-    if (lb < nb1) {
-        const uint32_t k = lb * kBlock + threadIdx.x;
-        if (k < (uint32_t)S.n1)
-            S.ghost[__builtin_nontemporal_load(S.d1 + k)] = S.s1v[__builtin_nontemporal_load(S.s1 + k)];
-    } else {
-        const uint32_t k = (lb - nb1) * kBlock + threadIdx.x;
-        if (k < (uint32_t)S.n2)
-            S.ghost[__builtin_nontemporal_load(S.d2 + k)] = S.s2v[__builtin_nontemporal_load(S.s2 + k)];
-    }
+    scatter_item<XT, CAP>(S.items[b - prefix[i]], S.n, S.which, S.code, S.v, S.recv, S.ghost, lds);
 }
 
 }  // namespace napspmv

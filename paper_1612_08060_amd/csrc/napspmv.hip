@@ -24,7 +24,8 @@ using napspmv::Error;
 using napspmv::HostPlan;
 
 namespace {
-constexpr int kMaxItem = 4096;                      // exchange work item length
+constexpr int kIndexedItem = 4096;                  // entries of an indexed exchange item
+constexpr int kMinItem = 256, kMaxItem = 1 << 24;   // entries of a band exchange item
 constexpr int kMaxRowsPerBlock = napspmv::kMaxRows;  // rows of a product block
 constexpr int64_t kAlign = 256;
 
@@ -36,7 +37,8 @@ struct Schedules {
     int32_t *onblk = nullptr, *onptr = nullptr, *win = nullptr;
     int32_t *offblk = nullptr, *offptr = nullptr, *items = nullptr, *tasks = nullptr;
     int32_t *ndblk = nullptr, *ndptr = nullptr;     // three-way: on_node row blocks
-    int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, n_nd = 0, bytes = 0;
+    int32_t *sitems = nullptr;                      // NAP: band items of the ghost scatter
+    int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, n_nd = 0, n_sitems = 0, bytes = 0;
     // per-partition schedules only: each process's range of tasks and of
     // off-process blocks
     std::vector<int64_t> task_ptr, off_ptr;
@@ -48,21 +50,29 @@ struct napspmv_plan_s {
     bool on_device = false;
     int device = 0;
     // tuning (-1 = automatic)
-    int block_nnz = -1, bands = -1, window = -1;
-    int auto_block_nnz = 4096, auto_bands = 1, auto_window = 1024;
-    int cur_block_nnz = 0, cur_bands = 0, cur_window = -1;   // schedules on the device
+    int block_nnz = -1, item = -1, window = -1;
+    int auto_block_nnz = 4096, auto_item = 65536, auto_window = 1024;
+    int cur_block_nnz = 0, cur_item = 0, cur_window = -1;   // schedules on the device
     int64_t G = 0, E = 0, H = 0, Gon = 0;
     int32_t *d_rp_on = nullptr, *d_col_on = nullptr, *d_rp_off = nullptr, *d_col_off = nullptr;
     void *d_val_on = nullptr, *d_val_off = nullptr;
-    int32_t *d_gather = nullptr, *d_pack = nullptr;
-    int32_t *d_ssrc = nullptr, *d_sdst = nullptr, *d_lsrc = nullptr, *d_ldst = nullptr;
+    // Band-ordered exchange buffers (see exchange_item), laid out for bands of
+    // `layout_cap` columns: gpos[k] = device position of ghost k of the
+    // plan's process-ordered ghost list; d_off = column offset inside its
+    // band of every ghost (standard) or send-buffer entry (NAP); d_code = the
+    // source of every ghost position for the NAP scatter.
+    int layout_cap = 0;
+    std::vector<int32_t> gpos;
+    std::vector<int64_t> gband, sband;   // band boundaries of the ghost / send buffers
+    uint16_t *d_off = nullptr;
+    uint32_t *d_code = nullptr;
+    int32_t *d_pgcol = nullptr, *d_pgpos = nullptr;   // per-process indexed gathers
     // three-way plans: the on_node block, and the helper stream and events
     // that run the inter-node hop and scatter beside the on_node product
     int32_t *d_rp_nd = nullptr, *d_col_nd = nullptr;
     void *d_val_nd = nullptr;
     // gather order of the off-process (and on_node) blocks; see sort_blocks
     uint16_t *d_slot_off = nullptr, *d_slot_nd = nullptr;
-    int sorted_cap = 0;              // block size the device entry order was sorted for
     hipStream_t helper = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void *d_ws = nullptr;            // the plan's own workspace (ghost, send, receive)
@@ -130,11 +140,6 @@ int guarded(F &&f) {
 
 int64_t vec_bytes(int dtype) { return dtype == NAPSPMV_F64 ? 8 : 4; }
 
-// Column bands of the standard gather: about 2 MiB of v per band.
-int pick_bands(int64_t n, int64_t vb) {
-    const int64_t b = (n * vb + (2 << 20) - 1) / (2 << 20);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(64, b));
-}
 
 // Workspace layout: ghost buffer, then the NAP send buffer, then the NAP
 // receive buffer (explicit hop only), each 256-byte aligned.
@@ -184,7 +189,8 @@ void charge(napspmv_plan_s *p, int64_t bytes) {
 }
 
 void free_schedules(napspmv_plan_s *p, Schedules &s) {
-    void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks, s.ndblk, s.ndptr};
+    void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks, s.ndblk, s.ndptr,
+                    s.sitems};
     for (void *q : ptrs) free_ptr(q);
     charge(p, -s.bytes);
     s = Schedules();
@@ -195,14 +201,12 @@ void free_device(napspmv_plan_s *p) {
     free_schedules(p, p->part);
     p->part_ready = false;
     void *ptrs[] = {p->d_rp_on, p->d_col_on, p->d_rp_off, p->d_col_off, p->d_val_on,
-                    p->d_val_off, p->d_gather, p->d_pack, p->d_ssrc, p->d_sdst, p->d_lsrc,
-                    p->d_ldst, p->d_ws, p->d_rp_nd, p->d_col_nd, p->d_val_nd,
-                    p->d_slot_off, p->d_slot_nd};
+                    p->d_val_off, p->d_off, p->d_code, p->d_pgcol, p->d_pgpos, p->d_ws,
+                    p->d_rp_nd, p->d_col_nd, p->d_val_nd, p->d_slot_off, p->d_slot_nd};
     for (void *q : ptrs) free_ptr(q);
     p->d_rp_nd = p->d_col_nd = nullptr;
     p->d_val_nd = nullptr;
     p->d_slot_off = p->d_slot_nd = nullptr;
-    p->sorted_cap = 0;
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->helper) (void)hipStreamDestroy(p->helper);
@@ -210,7 +214,10 @@ void free_device(napspmv_plan_s *p) {
     p->helper = nullptr;
     p->d_rp_on = p->d_col_on = p->d_rp_off = p->d_col_off = nullptr;
     p->d_val_on = p->d_val_off = p->d_ws = nullptr;
-    p->d_gather = p->d_pack = p->d_ssrc = p->d_sdst = p->d_lsrc = p->d_ldst = nullptr;
+    p->d_off = nullptr;
+    p->d_code = nullptr;
+    p->d_pgcol = p->d_pgpos = nullptr;
+    p->layout_cap = 0;
     g_in_use -= p->device_bytes;
     p->device_bytes = 0;
     p->on_device = false;
@@ -222,8 +229,8 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
                           hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
     b += (int64_t)(hp.rowptr_nd.size() + hp.col_nd.size()) * 4 + (int64_t)hp.val_nd.size();
     b += (int64_t)(hp.col_off.size() + hp.col_nd.size()) * 2;   // gather-order slots
-    b += (int64_t)(hp.gather_idx.size() + hp.pack_idx.size() + hp.scat_src.size() +
-                   hp.scat_dst.size() + hp.l2_src.size() + hp.l2_dst.size()) * 4;
+    // band offsets (ghosts or send entries) and, for NAP, the scatter codes
+    b += hp.mode == NAPSPMV_NAP ? p->E * 2 + p->G * 4 : p->G * 2;
     return b + ws_layout(p).total;
 }
 
@@ -231,7 +238,8 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
                       const std::vector<int32_t> &onptr, const std::vector<int32_t> &wins,
                       const std::vector<int32_t> &offblk, const std::vector<int32_t> &offptr,
                       const std::vector<int32_t> &items, const std::vector<int32_t> &tasks,
-                      const std::vector<int32_t> &ndblk = {}, const std::vector<int32_t> &ndptr = {}) {
+                      const std::vector<int32_t> &ndblk = {}, const std::vector<int32_t> &ndptr = {},
+                      const std::vector<int32_t> &sitems = {}) {
     free_schedules(p, s);
     int64_t total = 0;
     try {
@@ -244,6 +252,7 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
         upload(s.offptr, offptr, total);
         upload(s.items, items, total);
         upload(s.tasks, tasks, total);
+        upload(s.sitems, sitems, total);
     } catch (...) {
         s.bytes = total;
         charge(p, total);
@@ -253,14 +262,15 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
     charge(p, total);
     s.n_on = (int64_t)onblk.size() - 1;
     s.n_off = (int64_t)offblk.size() - 1;
-    s.n_items = (int64_t)items.size() / 2;
+    s.n_items = (int64_t)items.size() / 4;
+    s.n_sitems = (int64_t)sitems.size() / 4;
     s.n_tasks = (int64_t)tasks.size();
     s.n_nd = ndblk.empty() ? 0 : (int64_t)ndblk.size() - 1;
 }
 
 int cur_cap(const napspmv_plan_s *p) { return p->block_nnz >= 0 ? p->block_nnz : p->auto_block_nnz; }
 int cur_win(const napspmv_plan_s *p) { return p->window >= 0 ? p->window : p->auto_window; }
-int cur_bands(const napspmv_plan_s *p) { return p->bands >= 0 ? p->bands : p->auto_bands; }
+int cur_item(const napspmv_plan_s *p) { return p->item >= 0 ? p->item : p->auto_item; }
 
 // Per-partition schedules (standard mode): each process's row blocks and its
 // own ghost gather items, contiguous per process, so one process's product
@@ -268,6 +278,17 @@ int cur_bands(const napspmv_plan_s *p) { return p->bands >= 0 ? p->bands : p->au
 void build_partitions(napspmv_plan_s *p) {
     const HostPlan &hp = p->hp;
     const int cap = cur_cap(p), win = cur_win(p);
+    {
+        // indexed gathers: source column and device position of every ghost
+        int64_t total = 0;
+        if (!p->d_pgcol) upload(p->d_pgcol, hp.ghost_col, total);
+        if (p->d_pgpos) {
+            HIP_OK(hipMemcpy(p->d_pgpos, p->gpos.data(), p->gpos.size() * 4, hipMemcpyHostToDevice));
+        } else {
+            upload(p->d_pgpos, p->gpos, total);
+        }
+        charge(p, total);
+    }
     std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks;
     std::vector<int64_t> task_ptr(hp.n_p + 1, 0), off_ptr(hp.n_p + 1, 0);
     for (int64_t t = 0; t < hp.n_p; ++t) {
@@ -278,11 +299,15 @@ void build_partitions(napspmv_plan_s *p) {
         for (auto &x : ob) x += (int32_t)r0;
         for (auto &x : fb) x += (int32_t)r0;
         if (win > 0) napspmv::row_block_windows(ob, hp.on_lo, hp.on_hi, hp.n, win, wn);
-        napspmv::flat_items(hp.ghost_ptr[t + 1] - hp.ghost_ptr[t], kMaxItem, it);
-        for (size_t k = 0; k < it.size(); k += 2) it[k] += (int32_t)hp.ghost_ptr[t];
+        std::vector<int32_t> flat;
+        napspmv::flat_items(hp.ghost_ptr[t + 1] - hp.ghost_ptr[t], kIndexedItem, flat);
+        for (size_t k = 0; k < flat.size(); k += 2) {
+            const int32_t q[4] = {-1, flat[k] + (int32_t)hp.ghost_ptr[t], flat[k + 1], 0};
+            it.insert(it.end(), q, q + 4);
+        }
         const int32_t blk_base = (int32_t)onblk.size();
-        const int32_t item_base = (int32_t)(items.size() / 2);
-        napspmv::merge_tasks((int64_t)it.size() / 2, (int64_t)ob.size() - 1, ts);
+        const int32_t item_base = (int32_t)(items.size() / 4);
+        napspmv::merge_tasks((int64_t)it.size() / 4, (int64_t)ob.size() - 1, ts);
         for (auto &x : ts) x = x < 0 ? ~(~x + item_base) : x + blk_base;
         // concatenate; a process's closing boundary is the next one's first
         onblk.insert(onblk.end(), ob.begin(), ob.end() - 1);
@@ -306,19 +331,72 @@ void build_partitions(napspmv_plan_s *p) {
     p->part_ready = true;
 }
 
-// Reorder the entries of every block into gather order (sort_blocks) and
+// Map the ghost positions of a block list to device positions (`map`),
+// reorder the entries of every block into gather order (sort_blocks) and
 // copy them, with their slots, over the device arrays (already allocated).
-void sort_upload(const std::vector<int32_t> &col, const std::vector<uint8_t> &val, int vs,
-                 const std::vector<int32_t> &blkptr, int cap, int32_t *d_col, void *d_val,
-                 uint16_t *d_slot) {
+void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &map,
+                 const std::vector<uint8_t> &val, int vs, const std::vector<int32_t> &blkptr, int cap,
+                 int32_t *d_col, void *d_val, uint16_t *d_slot) {
     if (col.empty()) return;
-    std::vector<int32_t> c2(col.size());
+    std::vector<int32_t> cm(col.size()), c2(col.size());
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)col.size(); ++k) cm[k] = map[col[k]];
     std::vector<uint8_t> v2(val.size());
     std::vector<uint16_t> s2(col.size());
-    napspmv::sort_blocks(blkptr, cap, col.data(), val.data(), vs, c2.data(), v2.data(), s2.data());
+    napspmv::sort_blocks(blkptr, cap, cm.data(), val.data(), vs, c2.data(), v2.data(), s2.data());
     HIP_OK(hipMemcpy(d_col, c2.data(), c2.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_val, v2.data(), v2.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_slot, s2.data(), s2.size() * 2, hipMemcpyHostToDevice));
+}
+
+// Stable counting sort of entries by the band of their column: pos[k] = the
+// device position of entry k, bstart = band boundaries (nb + 1).
+void band_order(const int32_t *cols, int64_t m, int cap, int64_t nb, std::vector<int32_t> &pos,
+                std::vector<int64_t> &bstart) {
+    bstart.assign(nb + 1, 0);
+    for (int64_t k = 0; k < m; ++k) ++bstart[cols[k] / cap + 1];
+    for (int64_t b = 0; b < nb; ++b) bstart[b + 1] += bstart[b];
+    std::vector<int64_t> next(bstart.begin(), bstart.end() - 1);
+    pos.resize(m);
+    for (int64_t k = 0; k < m; ++k) pos[k] = (int32_t)next[cols[k] / cap]++;
+}
+
+// Band layout of the exchange buffers for bands of `cap` columns (the LDS
+// tile of the exchange kernels): ghost positions, band offsets, NAP send
+// positions and scatter codes; uploaded over the plan's device arrays.
+void build_layout(napspmv_plan_s *p, int cap) {
+    const HostPlan &hp = p->hp;
+    const int64_t nb = (hp.n + cap - 1) / cap, G = p->G, E = p->E;
+    band_order(hp.ghost_col.data(), G, cap, nb, p->gpos, p->gband);
+    const std::vector<int32_t> &gpos = p->gpos;
+    if (hp.mode == NAPSPMV_STANDARD) {
+        std::vector<uint16_t> off(G);
+        for (int64_t k = 0; k < G; ++k) off[gpos[k]] = (uint16_t)(hp.ghost_col[k] % cap);
+        if (G) HIP_OK(hipMemcpy(p->d_off, off.data(), G * 2, hipMemcpyHostToDevice));
+    } else {
+        std::vector<int32_t> spos;
+        band_order(hp.pack_idx.data(), E, cap, nb, spos, p->sband);
+        std::vector<uint16_t> off(E);
+        for (int64_t e = 0; e < E; ++e) off[spos[e]] = (uint16_t)(hp.pack_idx[e] % cap);
+        std::vector<uint32_t> code(G, 0);
+        for (int64_t h = 0; h < p->H; ++h) code[gpos[hp.scat_dst[h]]] = (uint32_t)spos[hp.scat_src[h]];
+        for (int64_t k = 0; k < p->Gon; ++k)
+            code[gpos[hp.l2_dst[k]]] = napspmv::kFromV | (uint32_t)(hp.l2_src[k] % cap);
+        if (E) HIP_OK(hipMemcpy(p->d_off, off.data(), E * 2, hipMemcpyHostToDevice));
+        if (G) HIP_OK(hipMemcpy(p->d_code, code.data(), G * 4, hipMemcpyHostToDevice));
+    }
+    p->layout_cap = cap;
+}
+
+// Band items (band, first, count, 0) over a band-ordered buffer, at most
+// `item` entries each.
+void band_items(const std::vector<int64_t> &bstart, int item, std::vector<int32_t> &items) {
+    items.clear();
+    for (int64_t b = 0; b + 1 < (int64_t)bstart.size(); ++b)
+        for (int64_t k = bstart[b]; k < bstart[b + 1]; k += item) {
+            const int32_t q[4] = {(int32_t)b, (int32_t)k, (int32_t)std::min<int64_t>(item, bstart[b + 1] - k), 0};
+            items.insert(items.end(), q, q + 4);
+        }
 }
 
 // (Re)build the launch schedules for the current tuning: on-process row
@@ -326,38 +404,42 @@ void sort_upload(const std::vector<int32_t> &col, const std::vector<uint8_t> &va
 // (standard: ghost gather by column band; NAP: pack in order) and the task
 // list of the first launch.  Per-partition schedules follow.
 void refresh_schedules(napspmv_plan_s *p) {
-    const int cap = cur_cap(p), win = cur_win(p), bands = cur_bands(p);
-    if (p->sched.onblk && cap == p->cur_block_nnz && win == p->cur_window && bands == p->cur_bands)
+    const int cap = cur_cap(p), win = cur_win(p), item = cur_item(p);
+    if (p->sched.onblk && cap == p->cur_block_nnz && win == p->cur_window && item == p->cur_item)
         return;
     const HostPlan &hp = p->hp;
-    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks;
+    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems;
     napspmv::row_blocks(hp.rowptr_on.data(), hp.n, cap, kMaxRowsPerBlock, onblk, onptr);
     if (win > 0) napspmv::row_block_windows(onblk, hp.on_lo, hp.on_hi, hp.n, win, wins);
     napspmv::row_blocks_per_process(hp.rowptr_off.data(), hp.starts, cap, kMaxRowsPerBlock, offblk,
                                     offptr);
-    if (hp.mode == NAPSPMV_STANDARD)
-        napspmv::gather_items(hp.ghost_ptr, hp.ghost_col, hp.n, bands, kMaxItem, items);
-    else
-        napspmv::flat_items(p->E, kMaxItem, items);
-    napspmv::merge_tasks((int64_t)items.size() / 2, (int64_t)onblk.size() - 1, tasks);
     std::vector<int32_t> ndblk, ndptr;
     if (hp.three_way)
         napspmv::row_blocks_per_process(hp.rowptr_nd.data(), hp.starts, cap, kMaxRowsPerBlock,
                                         ndblk, ndptr);
-    if (cap != p->sorted_cap) {
-        // entry order of the off-process blocks follows the block cuts
+    if (cap != p->layout_cap) {
+        // the exchange layout and the entry order of the off-process blocks
+        // follow the band width and the block cuts
         HIP_OK(hipDeviceSynchronize());
-        sort_upload(hp.col_off, hp.val_off, (int)hp.value_size, offptr, cap, p->d_col_off,
-                    p->d_val_off, p->d_slot_off);
+        build_layout(p, cap);
+        sort_upload(hp.col_off, p->gpos, hp.val_off, (int)hp.value_size, offptr, cap,
+                    p->d_col_off, p->d_val_off, p->d_slot_off);
         if (hp.three_way)
-            sort_upload(hp.col_nd, hp.val_nd, (int)hp.value_size, ndptr, cap, p->d_col_nd,
-                        p->d_val_nd, p->d_slot_nd);
-        p->sorted_cap = cap;
+            sort_upload(hp.col_nd, p->gpos, hp.val_nd, (int)hp.value_size, ndptr, cap,
+                        p->d_col_nd, p->d_val_nd, p->d_slot_nd);
     }
-    upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr);
+    if (hp.mode == NAPSPMV_STANDARD) {
+        band_items(p->gband, item, items);
+    } else {
+        band_items(p->sband, item, items);
+        band_items(p->gband, item, sitems);
+    }
+    napspmv::merge_tasks((int64_t)items.size() / 4, (int64_t)onblk.size() - 1, tasks);
+    upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr,
+                     sitems);
     p->cur_block_nnz = cap;
     p->cur_window = win;
-    p->cur_bands = bands;
+    p->cur_item = item;
     if (p->part_ready) build_partitions(p);
 }
 
@@ -401,12 +483,13 @@ void to_device(napspmv_plan_s *p) {
             HIP_OK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
             HIP_OK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
         }
-        upload(p->d_gather, hp.gather_idx, total);
-        upload(p->d_pack, hp.pack_idx, total);
-        upload(p->d_ssrc, hp.scat_src, total);
-        upload(p->d_sdst, hp.scat_dst, total);
-        upload(p->d_lsrc, hp.l2_src, total);
-        upload(p->d_ldst, hp.l2_dst, total);
+        // band layout arrays: filled by refresh_schedules
+        if (hp.mode == NAPSPMV_STANDARD) {
+            alloc(p->d_off, (size_t)p->G * 2);
+        } else {
+            alloc(p->d_off, (size_t)p->E * 2);
+            alloc(p->d_code, (size_t)p->G * 4);
+        }
         const int64_t wsb = ws_layout(p).total;
         if (wsb > 0) {
             HIP_OK(hipMalloc(&p->d_ws, (size_t)wsb));
@@ -435,9 +518,12 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
     napspmv::LocalView<VT, XT> L;
     L.tasks = s.tasks + task0;
     L.n_tasks = (int32_t)n_tasks;
-    L.items = reinterpret_cast<const int2 *>(s.items);
-    L.idx = std_mode ? p->d_gather : p->d_pack;
+    L.items = reinterpret_cast<const int4 *>(s.items);
+    L.off = p->d_off;
+    L.idx = p->d_pgcol;
+    L.dpos = p->d_pgpos;
     L.xdst = static_cast<XT *>(std_mode ? ws.ghost : ws.send);
+    L.n = (int32_t)p->hp.n;
     L.rowblk = s.onblk;
     L.blkptr = s.onptr;
     L.win = reinterpret_cast<const int2 *>(s.win);
@@ -468,17 +554,17 @@ napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules
 }
 
 template <typename XT>
-napspmv::ScatterView<XT> scatter_view(const napspmv_plan_s *p, const Ws &ws, const XT *v) {
+napspmv::ScatterView<XT> scatter_view(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws,
+                                      const XT *v, int which) {
     napspmv::ScatterView<XT> S;
-    S.n1 = (int32_t)p->H;
-    S.s1 = p->d_ssrc;
-    S.d1 = p->d_sdst;
-    S.s1v = static_cast<const XT *>(ws.recv);
-    S.n2 = (int32_t)p->Gon;
-    S.s2 = p->d_lsrc;
-    S.d2 = p->d_ldst;
-    S.s2v = v;
+    S.items = reinterpret_cast<const int4 *>(sc.sitems);
+    S.n_items = (int32_t)sc.n_sitems;
+    S.code = p->d_code;
+    S.v = v;
+    S.recv = static_cast<const XT *>(ws.recv);
     S.ghost = static_cast<XT *>(ws.ghost);
+    S.n = (int32_t)p->hp.n;
+    S.which = which;
     return S;
 }
 
@@ -500,20 +586,18 @@ void launch_local(int win, const napspmv::LocalView<VT, XT> &L, hipStream_t s) {
     }
 }
 
-// The inter-node hop (explicit copy, if any) and the scatter of received
-// values (`hop`), and the fully local gathers (`local`), into the ghost buffer.
-template <typename XT>
-void launch_hop_scatter(const napspmv_plan_s *p, const Ws &ws, const XT *v, hipStream_t s,
-                        bool hop = true, bool local = true) {
+// The inter-node hop (explicit copy, if any) and the ghost scatter: every
+// position (which = 0), only received values (1, with the hop) or only the
+// fully local values (2).
+template <typename XT, int CAP>
+void launch_scatter(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, const XT *v,
+                    hipStream_t s, int which) {
     using namespace napspmv;
-    if (hop && p->E > 0 && ws.recv != ws.send)
+    if (which != 2 && p->E > 0 && ws.recv != ws.send)
         k_copy<XT><<<blocks_for(p->E), kBlock, 0, s>>>((int32_t)p->E, static_cast<const XT *>(ws.send),
                                                      static_cast<XT *>(ws.recv));
-    const uint32_t nb1 = hop ? blocks_for(p->H) : 0, nb2 = local ? blocks_for(p->Gon) : 0;
-    if (nb1 + nb2 > 0)
-        k_scatter2<XT><<<nb1 + nb2, kBlock, 0, s>>>(
-            hop ? (int32_t)p->H : 0, p->d_ssrc, p->d_sdst, static_cast<const XT *>(ws.recv),
-            local ? (int32_t)p->Gon : 0, p->d_lsrc, p->d_ldst, v, static_cast<XT *>(ws.ghost), nb1);
+    if (sc.n_sitems > 0)
+        k_scatter<XT, CAP><<<(uint32_t)sc.n_sitems, kBlock, 0, s>>>(scatter_view<XT>(p, sc, ws, v, which));
 }
 
 // REMOTE stage of a three-way plan (algorithm NAPSpMV): on the caller's
@@ -525,9 +609,9 @@ void launch_three_way(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws
                       XT *w, hipStream_t s) {
     HIP_OK(hipEventRecord(p->ev_fork, s));
     HIP_OK(hipStreamWaitEvent(p->helper, p->ev_fork, 0));
-    launch_hop_scatter<XT>(p, ws, v, p->helper, true, false);
+    launch_scatter<XT, CAP>(p, sc, ws, v, p->helper, 1);
     HIP_OK(hipEventRecord(p->ev_join, p->helper));
-    launch_hop_scatter<XT>(p, ws, v, s, false, true);
+    launch_scatter<XT, CAP>(p, sc, ws, v, s, 2);
     if (sc.n_nd > 0 && p->hp.nnz_nd > 0)
         napspmv::k_remote<VT, XT, CAP><<<(uint32_t)sc.n_nd, napspmv::kBlock, 0, s>>>(
             remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_nd, true));
@@ -549,7 +633,7 @@ void launch_cap(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, int 
         launch_three_way<VT, XT, CAP>(p, sc, ws, v, w, s);
         return;
     }
-    if (p->hp.mode == NAPSPMV_NAP) launch_hop_scatter<XT>(p, ws, v, s);
+    if (p->hp.mode == NAPSPMV_NAP) launch_scatter<XT, CAP>(p, sc, ws, v, s, 0);
     if (p->hp.nnz_off > 0 && n_blk > 0)
         napspmv::k_remote<VT, XT, CAP><<<(uint32_t)n_blk, napspmv::kBlock, 0, s>>>(
             remote_view<VT, XT>(p, sc, ws, w, blk0, n_blk));
@@ -690,13 +774,13 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
         const Ws wp = ws_ptrs(p, ws && ws[i] ? ws[i] : p->d_ws);
         lv[i] = local_view<VT, XT>(p, p->sched, wp, static_cast<const XT *>(v[i]),
                                    static_cast<XT *>(w[i]), 0, p->sched.n_tasks);
-        sv[i] = scatter_view<XT>(p, wp, static_cast<const XT *>(v[i]));
+        sv[i] = scatter_view<XT>(p, p->sched, wp, static_cast<const XT *>(v[i]), 0);
         rv[i] = remote_view<VT, XT>(p, p->sched, wp, static_cast<XT *>(w[i]), 0,
                                     p->hp.nnz_off > 0 ? p->sched.n_off : 0);
         const bool nap = p->hp.mode == NAPSPMV_NAP;
         any_nap = any_nap || nap;
         pl[i + 1] = pl[i] + lv[i].n_tasks;
-        ps[i + 1] = ps[i] + (nap ? (int32_t)(blocks_for(p->H) + blocks_for(p->Gon)) : 0);
+        ps[i + 1] = ps[i] + (nap ? (int32_t)p->sched.n_sitems : 0);
         pr[i + 1] = pr[i] + rv[i].n_blocks;
     }
     HIP_OK(hipMemcpyAsync(d, h, t.total, hipMemcpyHostToDevice, s));
@@ -705,7 +789,7 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
             reinterpret_cast<const LocalView<VT, XT> *>(d + t.local),
             reinterpret_cast<const int32_t *>(d + t.pre_local), count);
     if (any_nap && ps[count] > 0)
-        k_scatter_batch<XT><<<(uint32_t)ps[count], kBlock, 0, s>>>(
+        k_scatter_batch<XT, CAP><<<(uint32_t)ps[count], kBlock, 0, s>>>(
             reinterpret_cast<const ScatterView<XT> *>(d + t.scatter),
             reinterpret_cast<const int32_t *>(d + t.pre_scatter), count);
     if (pr[count] > 0)
@@ -783,7 +867,8 @@ void cache_store(const char *path, const std::string &key, const int v[3], doubl
 
 bool valid_cfg(const int c[3]) {
     return (c[0] == 1024 || c[0] == 2048 || c[0] == 4096) &&
-           (c[1] == 0 || c[1] == 1024 || c[1] == 2048 || c[1] == 4096) && c[2] >= 1 && c[2] <= 4096;
+           (c[1] == 0 || c[1] == 1024 || c[1] == 2048 || c[1] == 4096) && c[2] >= kMinItem &&
+           c[2] <= kMaxItem;
 }
 
 }  // namespace
@@ -814,7 +899,6 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         p->E = (int64_t)p->hp.pack_idx.size();
         p->H = (int64_t)p->hp.scat_src.size();
         p->Gon = (int64_t)p->hp.l2_src.size();
-        p->auto_bands = pick_bands(n, vec_bytes(dtype));
         if (!(flags & NAPSPMV_HOST_ONLY)) {
             to_device(p);
             napspmv::release_device_arrays(p->hp);
@@ -1036,7 +1120,7 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
         if (cache_lookup(cache_path, key, cfg) && valid_cfg(cfg)) {
             plan->block_nnz = cfg[0];
             plan->window = cfg[1];
-            plan->bands = cfg[2];
+            plan->item = cfg[2];
             refresh_schedules(plan);
             HIP_OK(hipDeviceSynchronize());
             if (best_ms) *best_ms = -1.0;
@@ -1045,21 +1129,15 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
         hipEvent_t e0 = nullptr, e1 = nullptr;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
-        const int ab = plan->auto_bands;
-        std::vector<int> band_opts = {ab};
-        if (plan->hp.mode == NAPSPMV_STANDARD) {
-            if (ab > 1) band_opts.push_back(std::max(1, ab / 2));
-            band_opts.push_back(std::min(4096, ab * 2));
-        }
         double best = 1e30;
-        int best_cfg[3] = {cur_cap(plan), cur_win(plan), cur_bands(plan)};
+        int best_cfg[3] = {cur_cap(plan), cur_win(plan), cur_item(plan)};
         try {
             for (int cap : {1024, 2048, 4096})
                 for (int win : {0, 1024, 2048, 4096})
-                    for (int bands : band_opts) {
+                    for (int item : {16384, 65536}) {
                         plan->block_nnz = cap;
                         plan->window = win;
-                        plan->bands = bands;
+                        plan->item = item;
                         refresh_schedules(plan);
                         const Ws wp = ws_ptrs(plan, plan->d_ws);
                         run_apply(plan, wp, v, w, s);            // warm-up
@@ -1074,7 +1152,7 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
                             best = per;
                             best_cfg[0] = cap;
                             best_cfg[1] = win;
-                            best_cfg[2] = bands;
+                            best_cfg[2] = item;
                         }
                     }
         } catch (...) {
@@ -1086,7 +1164,7 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
         (void)hipEventDestroy(e1);
         plan->block_nnz = best_cfg[0];
         plan->window = best_cfg[1];
-        plan->bands = best_cfg[2];
+        plan->item = best_cfg[2];
         refresh_schedules(plan);
         HIP_OK(hipDeviceSynchronize());
         cache_store(cache_path, key, best_cfg, best);
@@ -1155,9 +1233,15 @@ int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *ws, void *ou
         DeviceGuard g(plan->device);
         HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
         const Ws wp = ws_ptrs(plan, ws ? const_cast<void *>(ws) : plan->d_ws);
-        if (plan->G > 0)
-            HIP_OK(hipMemcpy(out, wp.ghost, (size_t)(plan->G * vec_bytes(plan->hp.dtype)),
-                             hipMemcpyDeviceToHost));
+        if (plan->G > 0) {
+            // device positions are band-ordered: return the plan's ghost order
+            const int64_t vb = vec_bytes(plan->hp.dtype);
+            std::vector<uint8_t> dev((size_t)(plan->G * vb));
+            HIP_OK(hipMemcpy(dev.data(), wp.ghost, dev.size(), hipMemcpyDeviceToHost));
+            uint8_t *o = static_cast<uint8_t *>(out);
+            for (int64_t k = 0; k < plan->G; ++k)
+                std::memcpy(o + k * vb, dev.data() + (int64_t)plan->gpos[k] * vb, (size_t)vb);
+        }
         return NAPSPMV_OK;
     });
 }
@@ -1170,10 +1254,10 @@ int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value) {
                 return fail(NAPSPMV_EINVAL, "block entries must be -1, 1024, 2048 or 4096");
             plan->block_nnz = value;
             break;
-        case NAPSPMV_PARAM_GATHER_BANDS:
-            if (value != -1 && (value < 1 || value > 4096))
-                return fail(NAPSPMV_EINVAL, "bands must be -1 or in [1, 4096]");
-            plan->bands = value;
+        case NAPSPMV_PARAM_GATHER_ITEM:
+            if (value != -1 && (value < kMinItem || value > kMaxItem))
+                return fail(NAPSPMV_EINVAL, "gather item must be -1 or in [256, 2^24]");
+            plan->item = value;
             break;
         case NAPSPMV_PARAM_VWINDOW:
             if (value != -1 && value != 0 && value != 1024 && value != 2048 && value != 4096)
@@ -1197,7 +1281,7 @@ int napspmv_plan_get_param(napspmv_plan_t plan, int param) {
     if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
     switch (param) {
         case NAPSPMV_PARAM_BLOCK_NNZ: return cur_cap(plan);
-        case NAPSPMV_PARAM_GATHER_BANDS: return cur_bands(plan);
+        case NAPSPMV_PARAM_GATHER_ITEM: return cur_item(plan);
         case NAPSPMV_PARAM_VWINDOW: return cur_win(plan);
         default: return fail(NAPSPMV_EINVAL, "unknown parameter");
     }

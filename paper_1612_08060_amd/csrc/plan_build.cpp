@@ -160,11 +160,6 @@ void release_device_arrays(HostPlan &hp) {
     std::vector<int32_t>().swap(hp.col_on);
     std::vector<uint8_t>().swap(hp.val_on);
     std::vector<int32_t>().swap(hp.gather_idx);
-    std::vector<int32_t>().swap(hp.pack_idx);
-    std::vector<int32_t>().swap(hp.scat_src);
-    std::vector<int32_t>().swap(hp.scat_dst);
-    std::vector<int32_t>().swap(hp.l2_src);
-    std::vector<int32_t>().swap(hp.l2_dst);
 }
 
 namespace {

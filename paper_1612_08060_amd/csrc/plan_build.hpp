@@ -89,10 +89,11 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
 // destination share a socket, out[2 ph + 1] = the others.
 void level_stats(const HostPlan &hp, int64_t pps, PhaseStats out[8]);
 
-// Frees the host copies of the on-process block and of the device index
-// lists after upload.  Row pointers, row windows and the off-process (and
-// on_node) entries stay: launch schedules, and the gather order of the
-// off-process blocks, are rebuilt from them when the block size changes.
+// Frees the host copy of the on-process block after upload.  Row pointers,
+// row windows, the off-process (and on_node) entries and the exchange index
+// lists stay: launch schedules, the band layout of the exchange buffers and
+// the gather order of the off-process blocks are rebuilt from them when the
+// block size changes.
 void release_device_arrays(HostPlan &hp);
 
 }  // namespace napspmv

@@ -116,35 +116,6 @@ void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks)
     }
 }
 
-void gather_items(const std::vector<int64_t> &ghost_ptr, const std::vector<int32_t> &ghost_col,
-                  int64_t n, int bands, int max_len, std::vector<int32_t> &items) {
-    items.clear();
-    const int64_t n_p = (int64_t)ghost_ptr.size() - 1;
-    if (bands < 1) bands = 1;
-    // cut[t * (bands + 1) + b]: first position of gh(t) in band b
-    std::vector<int64_t> cut((size_t)(n_p * (bands + 1)));
-    for (int64_t t = 0; t < n_p; ++t) {
-        const int32_t *g0 = ghost_col.data() + ghost_ptr[t];
-        const int32_t *g1 = ghost_col.data() + ghost_ptr[t + 1];
-        for (int b = 0; b <= bands; ++b) {
-            const int64_t lo = (n * b) / bands;
-            cut[t * (bands + 1) + b] =
-                b == bands ? ghost_ptr[t + 1] : ghost_ptr[t] + (std::lower_bound(g0, g1, lo) - g0);
-        }
-    }
-    for (int b = 0; b < bands; ++b)
-        for (int64_t t = 0; t < n_p; ++t) {
-            int64_t a = cut[t * (bands + 1) + b];
-            const int64_t e = cut[t * (bands + 1) + b + 1];
-            while (a < e) {
-                const int64_t len = std::min<int64_t>(max_len, e - a);
-                items.push_back((int32_t)a);
-                items.push_back((int32_t)len);
-                a += len;
-            }
-        }
-}
-
 void flat_items(int64_t total, int max_len, std::vector<int32_t> &items) {
     items.clear();
     for (int64_t a = 0; a < total; a += max_len) {

@@ -43,13 +43,6 @@ void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int
 // XCD's share) holds a proportional slice of both.
 void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks);
 
-// Work items (start, len) over the ghost buffer for the standard gather:
-// each process's ascending ghost list cut at `bands` equal column bands of v
-// and into pieces of at most `max_len`, ordered by (band, process).
-// Returned as interleaved pairs.
-void gather_items(const std::vector<int64_t> &ghost_ptr, const std::vector<int32_t> &ghost_col,
-                  int64_t n, int bands, int max_len, std::vector<int32_t> &items);
-
 // Work items covering [0, total) in order, pieces of at most `max_len`.
 void flat_items(int64_t total, int max_len, std::vector<int32_t> &items);
 

@@ -188,12 +188,13 @@ def test_tuning_parameters():
     a = kkt_like(1 << 10, 2)
     p = lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, host_only=True)
     assert p.get_param("block_nnz") == 4096 and p.get_param("window") == 1024
-    assert p.get_param("bands") >= 1
+    assert p.get_param("gather_item") == 65536
     p.set_param("block_nnz", 1024)
     p.set_param("window", 0)
-    p.set_param("bands", 7)
-    assert (p.get_param("block_nnz"), p.get_param("window"), p.get_param("bands")) == (1024, 0, 7)
-    for name, bad in (("block_nnz", 3000), ("window", 512), ("bands", 0)):
+    p.set_param("gather_item", 700)
+    assert (p.get_param("block_nnz"), p.get_param("window"), p.get_param("gather_item")) == (1024, 0, 700)
+    for name, bad in (("block_nnz", 3000), ("window", 512), ("gather_item", 255),
+                      ("gather_item", (1 << 24) + 1)):
         with pytest.raises(lib.NapspmvError):
             p.set_param(name, bad)
     p.set_param("block_nnz", -1)
