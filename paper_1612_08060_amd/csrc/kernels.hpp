@@ -205,42 +205,44 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
         if (tid == 0) w[r0] = s;
         return;
     }
+    // Every load below is unconditional, on an index clamped into the block
+    // (an empty block reads its predecessor's last entry; no array is empty),
+    // so all of them can be in flight at once: a load under a per-lane
+    // condition makes the compiler wait for the loads before it.  Clamped
+    // lanes' values are discarded.
+    const int32_t klast = k1 > 0 ? k1 - 1 : 0;
     int32_t c[U];
     XT a[U];
     int32_t sl[REMOTE ? U : 1];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int32_t k = k0 + u * kBlock + tid;
-        if (k < k1) {
-            c[u] = __builtin_nontemporal_load(col + k);
-            a[u] = (XT)load_val(val, k);
-            if (REMOTE) sl[REMOTE ? u : 0] = __builtin_nontemporal_load(slot + k);
-        }
+        const int32_t k = min(k0 + u * kBlock + tid, klast);
+        c[u] = __builtin_nontemporal_load(col + k);
+        a[u] = (XT)load_val(val, k);
+        if (REMOTE) sl[REMOTE ? u : 0] = __builtin_nontemporal_load(slot + k);
     }
     XT t[W > 0 ? W / kBlock : 1];
     if (W > 0) {
+        const int32_t qlast = win.y > 0 ? win.y - 1 : 0;
 #pragma unroll
-        for (int u = 0; u < W / kBlock; ++u) {
-            const int32_t q = u * kBlock + tid;
-            if (q < win.y) t[u] = xsrc[win.x + q];
-        }
+        for (int u = 0; u < W / kBlock; ++u) t[u] = xsrc[win.x + min(u * kBlock + tid, qlast)];
     }
     int32_t rb[R], re[R];
     XT s[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const int32_t r = r0 + i * kBlock + tid;
-        if (r < r1) {
-            rb[i] = rowptr[r];
-            re[i] = rowptr[r + 1];
-            s[i] = REMOTE ? w[r] : (XT)0;
-        }
+        const int32_t r = min(r0 + i * kBlock + tid, r1 - 1);
+        rb[i] = rowptr[r];
+        re[i] = rowptr[r + 1];
+        s[i] = REMOTE ? w[r] : (XT)0;
     }
+    // operands: columns inside the staged window read one shared address
+    // (a single cache line per wave) and take the LDS copy below
     XT x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int32_t k = k0 + u * kBlock + tid;
-        if (k < k1 && !(W > 0 && (uint32_t)(c[u] - win.x) < (uint32_t)win.y)) x[u] = xsrc[c[u]];
+        const bool inwin = W > 0 && (uint32_t)(c[u] - win.x) < (uint32_t)win.y;
+        x[u] = xsrc[inwin ? win.x : c[u]];
     }
     if (W > 0) {
 #pragma unroll

@@ -11,6 +11,7 @@
 #include <fstream>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -170,13 +171,17 @@ Ws ws_ptrs(const napspmv_plan_s *p, void *base) {
     return Ws{b + l.ghost, b + l.send, b + l.recv};
 }
 
+// Device arrays are never empty and start zeroed: the product kernels read
+// clamped dummy entries (index 0 of an empty part) whose values they discard.
+constexpr size_t kMinAlloc = 256;
+
 template <typename T>
 void upload(T *&dst, const std::vector<T> &src, int64_t &total) {
-    if (src.empty()) return;
-    const size_t bytes = src.size() * sizeof(T);
-    HIP_OK(hipMalloc(reinterpret_cast<void **>(&dst), bytes));
-    total += (int64_t)bytes;
-    HIP_OK(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
+    const size_t bytes = src.size() * sizeof(T), cap = std::max(bytes, kMinAlloc);
+    HIP_OK(hipMalloc(reinterpret_cast<void **>(&dst), cap));
+    total += (int64_t)cap;
+    HIP_OK(hipMemset(dst, 0, cap));
+    if (bytes) HIP_OK(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
 }
 
 void free_ptr(void *p) {
@@ -349,16 +354,29 @@ void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &ma
     HIP_OK(hipMemcpy(d_slot, s2.data(), s2.size() * 2, hipMemcpyHostToDevice));
 }
 
-// Stable counting sort of entries by the band of their column: pos[k] = the
-// device position of entry k, bstart = band boundaries (nb + 1).
-void band_order(const int32_t *cols, int64_t m, int cap, int64_t nb, std::vector<int32_t> &pos,
-                std::vector<int64_t> &bstart) {
+// Stable sort of entries by the band of their column and then by `group`
+// (NULL: none): pos[k] = the device position of entry k, bstart = band
+// boundaries (nb + 1).  A counting sort when the key space is small.
+void band_order(const int32_t *cols, int64_t m, int cap, int64_t nb, const int32_t *group,
+                int64_t ngroups, std::vector<int32_t> &pos, std::vector<int64_t> &bstart) {
+    if (!group) ngroups = 1;
+    auto key = [&](int64_t k) { return (int64_t)(cols[k] / cap) * ngroups + (group ? group[k] : 0); };
+    pos.resize(m);
     bstart.assign(nb + 1, 0);
     for (int64_t k = 0; k < m; ++k) ++bstart[cols[k] / cap + 1];
     for (int64_t b = 0; b < nb; ++b) bstart[b + 1] += bstart[b];
-    std::vector<int64_t> next(bstart.begin(), bstart.end() - 1);
-    pos.resize(m);
-    for (int64_t k = 0; k < m; ++k) pos[k] = (int32_t)next[cols[k] / cap]++;
+    const int64_t nk = nb * ngroups;
+    if (nk <= (int64_t)1 << 26) {
+        std::vector<int64_t> next(nk + 1, 0);
+        for (int64_t k = 0; k < m; ++k) ++next[key(k) + 1];
+        for (int64_t q = 0; q < nk; ++q) next[q + 1] += next[q];
+        for (int64_t k = 0; k < m; ++k) pos[k] = (int32_t)next[key(k)]++;
+    } else {
+        std::vector<int32_t> ord(m);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
+        for (int64_t q = 0; q < m; ++q) pos[ord[q]] = (int32_t)q;
+    }
 }
 
 // Band layout of the exchange buffers for bands of `cap` columns (the LDS
@@ -367,15 +385,21 @@ void band_order(const int32_t *cols, int64_t m, int cap, int64_t nb, std::vector
 void build_layout(napspmv_plan_s *p, int cap) {
     const HostPlan &hp = p->hp;
     const int64_t nb = (hp.n + cap - 1) / cap, G = p->G, E = p->E;
-    band_order(hp.ghost_col.data(), G, cap, nb, p->gpos, p->gband);
+    band_order(hp.ghost_col.data(), G, cap, nb, nullptr, 1, p->gpos, p->gband);
     const std::vector<int32_t> &gpos = p->gpos;
     if (hp.mode == NAPSPMV_STANDARD) {
         std::vector<uint16_t> off(G);
         for (int64_t k = 0; k < G; ++k) off[gpos[k]] = (uint16_t)(hp.ghost_col[k] % cap);
         if (G) HIP_OK(hipMemcpy(p->d_off, off.data(), G * 2, hipMemcpyHostToDevice));
     } else {
+        // inside a band, the send buffer is grouped by receiving node, so the
+        // values one node's ghosts take from a band lie together
+        const napspmv::Phase &I = hp.phase[NAPSPMV_PHASE_INTER];
+        std::vector<int32_t> dst_node(E);
+        for (size_t k = 0; k < I.src.size(); ++k)
+            for (int64_t e = I.ptr[k]; e < I.ptr[k + 1]; ++e) dst_node[e] = (int32_t)(I.dst[k] / hp.ppn);
         std::vector<int32_t> spos;
-        band_order(hp.pack_idx.data(), E, cap, nb, spos, p->sband);
+        band_order(hp.pack_idx.data(), E, cap, nb, dst_node.data(), hp.n_nodes, spos, p->sband);
         std::vector<uint16_t> off(E);
         for (int64_t e = 0; e < E; ++e) off[spos[e]] = (uint16_t)(hp.pack_idx[e] % cap);
         std::vector<uint32_t> code(G, 0);
@@ -458,9 +482,10 @@ void to_device(napspmv_plan_s *p) {
         upload(p->d_col_on, hp.col_on, total);
         upload(p->d_rp_off, hp.rowptr_off, total);
         auto alloc = [&](auto *&dst, size_t bytes) {
-            if (!bytes) return;
-            HIP_OK(hipMalloc(reinterpret_cast<void **>(&dst), bytes));
-            total += (int64_t)bytes;
+            const size_t cap = std::max(bytes, kMinAlloc);
+            HIP_OK(hipMalloc(reinterpret_cast<void **>(&dst), cap));
+            total += (int64_t)cap;
+            HIP_OK(hipMemset(dst, 0, cap));
         };
         // entry arrays of the off-process blocks: filled in gather order by
         // refresh_schedules
@@ -468,10 +493,11 @@ void to_device(napspmv_plan_s *p) {
         alloc(p->d_val_off, hp.val_off.size());
         alloc(p->d_slot_off, hp.col_off.size() * 2);
         auto upload_bytes = [&](void *&dst, const std::vector<uint8_t> &src) {
-            if (src.empty()) return;
-            HIP_OK(hipMalloc(&dst, src.size()));
-            total += (int64_t)src.size();
-            HIP_OK(hipMemcpy(dst, src.data(), src.size(), hipMemcpyHostToDevice));
+            const size_t cap = std::max(src.size(), kMinAlloc);
+            HIP_OK(hipMalloc(&dst, cap));
+            total += (int64_t)cap;
+            HIP_OK(hipMemset(dst, 0, cap));
+            if (!src.empty()) HIP_OK(hipMemcpy(dst, src.data(), src.size(), hipMemcpyHostToDevice));
         };
         upload_bytes(p->d_val_on, hp.val_on);
         if (hp.three_way) {
