@@ -77,10 +77,16 @@ def rows_with_off_entries(a, n_p, row_starts):
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources with comments and blank lines removed, so a
+    recorded counter summary stays valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hpp", "napspmv.hip"):
-        with open(os.path.join(ROOT, "paper_1612_08060_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1612_08060_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

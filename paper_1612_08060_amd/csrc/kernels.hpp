@@ -1,24 +1,23 @@
-// gfx950 kernels of the apply path: index gathers and scatters that carry
-// the plan's messages, and the split CSR product.
+// gfx950 kernels of the apply path: the exchanges that carry the plan's
+// messages, and the split CSR product.
 //
 // An apply is two product launches, as algorithm standard_spmv (section 2.1)
 // and NAPSpMV (section 4.3) order the work: the first launch runs the
 // exchange that fills the ghost buffer (or the NAP send buffer) together
 // with the on-process product local_spmv(A_on, v), which needs no received
 // value; the second adds the off-process product local_spmv(A_off, ghost)
-// into w.  The first launch interleaves its two kinds of blocks on every CU,
-// so the exchange, bound by random L2 requests, overlaps the on-process
-// product, bound by HBM streaming: the overlap of local work with
-// communication the paper's algorithms make, on one GPU.
+// into w (for NAP after the hop and the scatter of received values).  The
+// first launch interleaves its two kinds of blocks on every CU, the overlap
+// of local work with communication that the paper's algorithms make.
 //
 // Every kernel is HBM-bound (the product does 2 flops per 12-16 bytes), so
 // the design is about bytes and latency, not arithmetic: 256-thread blocks of
-// four wave64s; matrix streams (values, column tags) read once with
-// non-temporal loads so they do not evict the vector and the ghost buffer
-// from L2; many independent loads in flight per lane; and an XCD-aware block
-// order, so that each of the eight L2 caches sees one contiguous range of the
-// work (the vector window and the ghost segments of the processes an XCD is
-// working on stay in that XCD's L2).
+// four wave64s; matrix streams (values, columns) read once with non-temporal
+// loads so they do not evict the vector and the ghost buffer from L2;
+// exchange buffers laid out by column band so every exchange writes in order
+// from a slice of v staged in LDS; all loads of a block issued at once; and
+// an XCD-aware block order, so that each of the eight L2 caches sees one
+// contiguous range of the work.
 #pragma once
 
 #include <hip/hip_runtime.h>
