@@ -157,7 +157,7 @@ def bench_batched(torch, nap, dev, reps=20):
     w = torch.empty_like(v)
     default_ms = _time_ms(torch, lambda: p.apply(v, w), reps)
     tune_ms = p.autotune(v, w, reps=3)
-    tuning = {k: p.get_param(k) for k in ("block_nnz", "window", "gather_item")}
+    tuning = {k: p.get_param(k) for k in ("block_nnz", "window", "gather_item", "remote_nnz")}
     g = p.graph(v, w)
     batched_ms = _time_ms(torch, g.launch, reps)
     torch.cuda.synchronize()
@@ -297,6 +297,7 @@ def main():
     ap.add_argument("--block-nnz", type=int, default=-1)
     ap.add_argument("--window", type=int, default=-1)
     ap.add_argument("--gather-item", type=int, default=-1)
+    ap.add_argument("--remote-nnz", type=int, default=-1)
     ap.add_argument("--extras", type=int, default=1, help="also time NAP mode and reduced precision")
     ap.add_argument("--batched", type=int, default=1, help="also run the batched 256-block workload")
     ap.add_argument("--serving", type=int, default=1, help="also run the serving workload")
@@ -326,7 +327,8 @@ def main():
     t = time.perf_counter()
     plan = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="standard", dtype="f64",
                     row_starts=wl.row_starts)
-    tuning = {"block_nnz": args.block_nnz, "window": args.window, "gather_item": args.gather_item}
+    tuning = {"block_nnz": args.block_nnz, "window": args.window, "gather_item": args.gather_item,
+              "remote_nnz": args.remote_nnz}
     for k, x in tuning.items():
         plan.set_param(k, x)
     tuning = {k: plan.get_param(k) for k in tuning}

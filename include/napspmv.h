@@ -273,7 +273,8 @@ NAPSPMV_API int napspmv_graph_create(napspmv_plan_t plan, const void *v, void *w
 NAPSPMV_API int napspmv_graph_launch(void *graph, void *stream);
 NAPSPMV_API int napspmv_graph_destroy(void *graph);
 
-/* Autotuner: times every (BLOCK_NNZ, VWINDOW, GATHER_ITEM) candidate on
+/* Autotuner: times every (BLOCK_NNZ, VWINDOW, GATHER_ITEM) candidate, then
+ * every REMOTE_NNZ with the best of those, on
  * this plan with `reps` applies each (HIP events on `stream`; w is
  * overwritten) and keeps the fastest.  With cache_path (may be NULL), a
  * result already cached for the same device and workload shape is used
@@ -289,7 +290,7 @@ NAPSPMV_API int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *
  * their workspace fits in `workspace_budget` bytes (0 = no cap; idle
  * workspaces of other plans are released to make room), and each free slot
  * then runs up to `max_batch` queued requests of one kernel group (value
- * type, BLOCK_NNZ, VWINDOW; oldest request first) as one batched launch
+ * type, BLOCK_NNZ, VWINDOW, REMOTE_NNZ; oldest request first) as one batched launch
  * sequence (a NAP plan with NAPSPMV_EXCHANGE_COPY or NAPSPMV_NAP_THREE_WAY
  * always runs alone, by napspmv_apply_ws).  Requests that arrive while slots are busy are admitted as slots
  * free up, so their work overlaps the work already on the device.
@@ -349,9 +350,11 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
  * device plan rebuilds and re-uploads the launch schedules (it allocates and
  * synchronizes the device): do not call it while an apply of the plan is in
  * flight.
- *   BLOCK_NNZ     entries per row block of both products, and columns of v
- *                 per band of the exchange buffers: 1024, 2048, 4096
- *                 (automatic: 4096)
+ *   BLOCK_NNZ     entries per row block of the on-process product, and
+ *                 columns of v per band of the exchange buffers: 1024, 2048,
+ *                 4096, 8192 (automatic: 4096)
+ *   REMOTE_NNZ    entries per row block of the off-process product: 1024,
+ *                 2048, 4096, 8192 (automatic: 8192)
  *   GATHER_ITEM   most entries of one exchange work item (a slice of one
  *                 band of the ghost or send buffer), 256 .. 2^24
  *                 (automatic: 65536)
@@ -362,6 +365,7 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
 #define NAPSPMV_PARAM_BLOCK_NNZ    0
 #define NAPSPMV_PARAM_GATHER_ITEM  1
 #define NAPSPMV_PARAM_VWINDOW      2
+#define NAPSPMV_PARAM_REMOTE_NNZ   3
 
 NAPSPMV_API int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value);
 NAPSPMV_API int napspmv_plan_get_param(napspmv_plan_t plan, int param);

@@ -26,7 +26,7 @@ STAGE_LOCAL, STAGE_REMOTE = 0, 1
 HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
 VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20}
 PARTITION_STRIDED = 0x40
-PARAMS = {"block_nnz": 0, "gather_item": 1, "window": 2}
+PARAMS = {"block_nnz": 0, "gather_item": 1, "window": 2, "remote_nnz": 3}
 _VAL_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
 

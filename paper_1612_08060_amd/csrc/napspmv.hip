@@ -51,9 +51,10 @@ struct napspmv_plan_s {
     bool on_device = false;
     int device = 0;
     // tuning (-1 = automatic)
-    int block_nnz = -1, item = -1, window = -1;
-    int auto_block_nnz = 4096, auto_item = 65536, auto_window = 1024;
-    int cur_block_nnz = 0, cur_item = 0, cur_window = -1;   // schedules on the device
+    int block_nnz = -1, item = -1, window = -1, remote_nnz = -1;
+    int auto_block_nnz = 4096, auto_item = 65536, auto_window = 1024, auto_remote_nnz = 8192;
+    int cur_block_nnz = 0, cur_item = 0, cur_window = -1, cur_remote_nnz = 0;   // on the device
+    int sorted_remote_nnz = 0;       // block size the off-process entry order was sorted for
     int64_t G = 0, E = 0, H = 0, Gon = 0;
     int32_t *d_rp_on = nullptr, *d_col_on = nullptr, *d_rp_off = nullptr, *d_col_off = nullptr;
     void *d_val_on = nullptr, *d_val_off = nullptr;
@@ -223,6 +224,7 @@ void free_device(napspmv_plan_s *p) {
     p->d_code = nullptr;
     p->d_pgcol = p->d_pgpos = nullptr;
     p->layout_cap = 0;
+    p->sorted_remote_nnz = 0;
     g_in_use -= p->device_bytes;
     p->device_bytes = 0;
     p->on_device = false;
@@ -274,6 +276,10 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
 }
 
 int cur_cap(const napspmv_plan_s *p) { return p->block_nnz >= 0 ? p->block_nnz : p->auto_block_nnz; }
+int cur_rcap(const napspmv_plan_s *p) {
+    return p->remote_nnz >= 0 ? p->remote_nnz : p->auto_remote_nnz;
+}
+bool valid_block(int v) { return v == 1024 || v == 2048 || v == 4096 || v == 8192; }
 int cur_win(const napspmv_plan_s *p) { return p->window >= 0 ? p->window : p->auto_window; }
 int cur_item(const napspmv_plan_s *p) { return p->item >= 0 ? p->item : p->auto_item; }
 
@@ -300,7 +306,7 @@ void build_partitions(napspmv_plan_s *p) {
         const int64_t r0 = hp.starts[t], r1 = hp.starts[t + 1];
         std::vector<int32_t> ob, op, fb, fp, it, ts, wn;
         napspmv::row_blocks(hp.rowptr_on.data() + r0, r1 - r0, cap, kMaxRowsPerBlock, ob, op);
-        napspmv::row_blocks(hp.rowptr_off.data() + r0, r1 - r0, cap, kMaxRowsPerBlock, fb, fp);
+        napspmv::row_blocks(hp.rowptr_off.data() + r0, r1 - r0, cur_rcap(p), kMaxRowsPerBlock, fb, fp);
         for (auto &x : ob) x += (int32_t)r0;
         for (auto &x : fb) x += (int32_t)r0;
         if (win > 0) napspmv::row_block_windows(ob, hp.on_lo, hp.on_hi, hp.n, win, wn);
@@ -428,29 +434,32 @@ void band_items(const std::vector<int64_t> &bstart, int item, std::vector<int32_
 // (standard: ghost gather by column band; NAP: pack in order) and the task
 // list of the first launch.  Per-partition schedules follow.
 void refresh_schedules(napspmv_plan_s *p) {
-    const int cap = cur_cap(p), win = cur_win(p), item = cur_item(p);
-    if (p->sched.onblk && cap == p->cur_block_nnz && win == p->cur_window && item == p->cur_item)
+    const int cap = cur_cap(p), win = cur_win(p), item = cur_item(p), rcap = cur_rcap(p);
+    if (p->sched.onblk && cap == p->cur_block_nnz && win == p->cur_window && item == p->cur_item &&
+        rcap == p->cur_remote_nnz)
         return;
     const HostPlan &hp = p->hp;
     std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems;
     napspmv::row_blocks(hp.rowptr_on.data(), hp.n, cap, kMaxRowsPerBlock, onblk, onptr);
     if (win > 0) napspmv::row_block_windows(onblk, hp.on_lo, hp.on_hi, hp.n, win, wins);
-    napspmv::row_blocks_per_process(hp.rowptr_off.data(), hp.starts, cap, kMaxRowsPerBlock, offblk,
+    napspmv::row_blocks_per_process(hp.rowptr_off.data(), hp.starts, rcap, kMaxRowsPerBlock, offblk,
                                     offptr);
     std::vector<int32_t> ndblk, ndptr;
     if (hp.three_way)
-        napspmv::row_blocks_per_process(hp.rowptr_nd.data(), hp.starts, cap, kMaxRowsPerBlock,
+        napspmv::row_blocks_per_process(hp.rowptr_nd.data(), hp.starts, rcap, kMaxRowsPerBlock,
                                         ndblk, ndptr);
-    if (cap != p->layout_cap) {
-        // the exchange layout and the entry order of the off-process blocks
-        // follow the band width and the block cuts
+    const bool relayout = cap != p->layout_cap;
+    if (relayout || rcap != p->sorted_remote_nnz) {
+        // the exchange layout follows the band width; the entry order of the
+        // off-process blocks follows the layout and the block cuts
         HIP_OK(hipDeviceSynchronize());
-        build_layout(p, cap);
-        sort_upload(hp.col_off, p->gpos, hp.val_off, (int)hp.value_size, offptr, cap,
+        if (relayout) build_layout(p, cap);
+        sort_upload(hp.col_off, p->gpos, hp.val_off, (int)hp.value_size, offptr, rcap,
                     p->d_col_off, p->d_val_off, p->d_slot_off);
         if (hp.three_way)
-            sort_upload(hp.col_nd, p->gpos, hp.val_nd, (int)hp.value_size, ndptr, cap,
+            sort_upload(hp.col_nd, p->gpos, hp.val_nd, (int)hp.value_size, ndptr, rcap,
                         p->d_col_nd, p->d_val_nd, p->d_slot_nd);
+        p->sorted_remote_nnz = rcap;
     }
     if (hp.mode == NAPSPMV_STANDARD) {
         band_items(p->gband, item, items);
@@ -464,6 +473,7 @@ void refresh_schedules(napspmv_plan_s *p) {
     p->cur_block_nnz = cap;
     p->cur_window = win;
     p->cur_item = item;
+    p->cur_remote_nnz = rcap;
     if (p->part_ready) build_partitions(p);
 }
 
@@ -626,6 +636,21 @@ void launch_scatter(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, 
         k_scatter<XT, CAP><<<(uint32_t)sc.n_sitems, kBlock, 0, s>>>(scatter_view<XT>(p, sc, ws, v, which));
 }
 
+// The off-process product over blocks [blk0, blk0 + n_blk), for the plan's
+// remote block size.
+template <typename VT, typename XT>
+void launch_remote(const napspmv_plan_s *p, const napspmv::RemoteView<VT, XT> &R, hipStream_t s) {
+    using namespace napspmv;
+    if (R.n_blocks <= 0) return;
+    const uint32_t nb = (uint32_t)R.n_blocks;
+    switch (p->cur_remote_nnz) {
+        case 1024: k_remote<VT, XT, 1024><<<nb, kBlock, 0, s>>>(R); break;
+        case 2048: k_remote<VT, XT, 2048><<<nb, kBlock, 0, s>>>(R); break;
+        case 4096: k_remote<VT, XT, 4096><<<nb, kBlock, 0, s>>>(R); break;
+        default: k_remote<VT, XT, 8192><<<nb, kBlock, 0, s>>>(R); break;
+    }
+}
+
 // REMOTE stage of a three-way plan (algorithm NAPSpMV): on the caller's
 // stream the fully local gathers and the on_node product; meanwhile on the
 // helper stream the inter-node hop and the scatter of received values; then,
@@ -639,12 +664,10 @@ void launch_three_way(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws
     HIP_OK(hipEventRecord(p->ev_join, p->helper));
     launch_scatter<XT, CAP>(p, sc, ws, v, s, 2);
     if (sc.n_nd > 0 && p->hp.nnz_nd > 0)
-        napspmv::k_remote<VT, XT, CAP><<<(uint32_t)sc.n_nd, napspmv::kBlock, 0, s>>>(
-            remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_nd, true));
+        launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_nd, true), s);
     HIP_OK(hipStreamWaitEvent(s, p->ev_join, 0));
     if (p->hp.nnz_off - p->hp.nnz_nd > 0 && sc.n_off > 0)
-        napspmv::k_remote<VT, XT, CAP><<<(uint32_t)sc.n_off, napspmv::kBlock, 0, s>>>(
-            remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_off));
+        launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_off), s);
 }
 
 template <typename VT, typename XT, int CAP>
@@ -660,9 +683,7 @@ void launch_cap(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, int 
         return;
     }
     if (p->hp.mode == NAPSPMV_NAP) launch_scatter<XT, CAP>(p, sc, ws, v, s, 0);
-    if (p->hp.nnz_off > 0 && n_blk > 0)
-        napspmv::k_remote<VT, XT, CAP><<<(uint32_t)n_blk, napspmv::kBlock, 0, s>>>(
-            remote_view<VT, XT>(p, sc, ws, w, blk0, n_blk));
+    if (p->hp.nnz_off > 0 && n_blk > 0) launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, w, blk0, n_blk), s);
 }
 
 template <typename VT, typename XT>
@@ -672,6 +693,7 @@ void launch_stage(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, in
     switch (p->cur_block_nnz) {
         case 1024: launch_cap<VT, XT, 1024>(p, sc, ws, stage, v, w, s, task0, n_tasks, blk0, n_blk); break;
         case 2048: launch_cap<VT, XT, 2048>(p, sc, ws, stage, v, w, s, task0, n_tasks, blk0, n_blk); break;
+        case 8192: launch_cap<VT, XT, 8192>(p, sc, ws, stage, v, w, s, task0, n_tasks, blk0, n_blk); break;
         default: launch_cap<VT, XT, 4096>(p, sc, ws, stage, v, w, s, task0, n_tasks, blk0, n_blk); break;
     }
 }
@@ -818,10 +840,17 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
         k_scatter_batch<XT, CAP><<<(uint32_t)ps[count], kBlock, 0, s>>>(
             reinterpret_cast<const ScatterView<XT> *>(d + t.scatter),
             reinterpret_cast<const int32_t *>(d + t.pre_scatter), count);
-    if (pr[count] > 0)
-        k_remote_batch<VT, XT, CAP><<<(uint32_t)pr[count], kBlock, 0, s>>>(
-            reinterpret_cast<const RemoteView<VT, XT> *>(d + t.remote),
-            reinterpret_cast<const int32_t *>(d + t.pre_remote), count);
+    if (pr[count] > 0) {
+        const auto *rvd = reinterpret_cast<const RemoteView<VT, XT> *>(d + t.remote);
+        const auto *prd = reinterpret_cast<const int32_t *>(d + t.pre_remote);
+        const uint32_t nb = (uint32_t)pr[count];
+        switch (plans[0]->cur_remote_nnz) {
+            case 1024: k_remote_batch<VT, XT, 1024><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
+            case 2048: k_remote_batch<VT, XT, 2048><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
+            case 4096: k_remote_batch<VT, XT, 4096><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
+            default: k_remote_batch<VT, XT, 8192><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
+        }
+    }
     HIP_OK(hipGetLastError());
 }
 
@@ -842,6 +871,7 @@ void batch_launch_t(int cap, int win, napspmv_batch_s *B, int count, const napsp
     switch (cap) {
         case 1024: batch_launch_cap<VT, XT, 1024>(win, B, count, plans, ws, v, w, s); break;
         case 2048: batch_launch_cap<VT, XT, 2048>(win, B, count, plans, ws, v, w, s); break;
+        case 8192: batch_launch_cap<VT, XT, 8192>(win, B, count, plans, ws, v, w, s); break;
         default: batch_launch_cap<VT, XT, 4096>(win, B, count, plans, ws, v, w, s); break;
     }
 }
@@ -858,13 +888,14 @@ std::string tune_key(const napspmv_plan_s *p) {
     std::ostringstream k;
     k << dev << ";n=" << p->hp.n << ";nnz=" << p->hp.nnz << ";np=" << p->hp.n_p << ";ppn="
       << p->hp.ppn << ";mode=" << p->hp.mode << ";dtype=" << p->hp.dtype << ";G=" << p->G
-      << ";on=" << p->hp.nnz_on << ";three_way=" << (p->hp.three_way ? 1 : 0);
+      << ";on=" << p->hp.nnz_on << ";three_way=" << (p->hp.three_way ? 1 : 0) << ";v=2";
     std::string s = k.str();
     std::replace(s.begin(), s.end(), ' ', '_');
     return s;
 }
 
-bool cache_lookup(const char *path, const std::string &key, int out[3]) {
+// Cache lines: key, BLOCK_NNZ, VWINDOW, GATHER_ITEM, REMOTE_NNZ, best ms.
+bool cache_lookup(const char *path, const std::string &key, int out[4]) {
     if (!path || !*path) return false;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     std::ifstream f(path);
@@ -873,26 +904,27 @@ bool cache_lookup(const char *path, const std::string &key, int out[3]) {
     while (std::getline(f, line)) {
         std::istringstream in(line);
         std::string k;
-        int a, b, c;
-        if (in >> k >> a >> b >> c && k == key) {
+        int a, b, c, d;
+        if (in >> k >> a >> b >> c >> d && k == key) {
             out[0] = a;
             out[1] = b;
             out[2] = c;
+            out[3] = d;
             found = true;       // the last entry of a key wins
         }
     }
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, const int v[3], double ms) {
+void cache_store(const char *path, const std::string &key, const int v[4], double ms) {
     if (!path || !*path) return;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     std::ofstream f(path, std::ios::app);
-    f << key << ' ' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << ms << '\n';
+    f << key << ' ' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << v[3] << ' ' << ms << '\n';
 }
 
-bool valid_cfg(const int c[3]) {
-    return (c[0] == 1024 || c[0] == 2048 || c[0] == 4096) &&
+bool valid_cfg(const int c[4]) {
+    return valid_block(c[0]) && valid_block(c[3]) &&
            (c[1] == 0 || c[1] == 1024 || c[1] == 2048 || c[1] == 4096) && c[2] >= kMinItem &&
            c[2] <= kMaxItem;
 }
@@ -1041,8 +1073,9 @@ int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *
         const napspmv_plan_s *p = plans[i];
         if (p->device != batch->device) return fail(NAPSPMV_EINVAL, "plans on different devices");
         if (p->hp.dtype != p0->hp.dtype || p->cur_block_nnz != p0->cur_block_nnz ||
-            p->cur_window != p0->cur_window)
-            return fail(NAPSPMV_EINVAL, "a batch needs one value type, BLOCK_NNZ and VWINDOW");
+            p->cur_window != p0->cur_window || p->cur_remote_nnz != p0->cur_remote_nnz)
+            return fail(NAPSPMV_EINVAL,
+                        "a batch needs one value type, BLOCK_NNZ, VWINDOW and REMOTE_NNZ");
         if (p->hp.mode == NAPSPMV_NAP && (p->flags & NAPSPMV_EXCHANGE_COPY))
             return fail(NAPSPMV_EUNSUPPORTED, "batched applies receive NAP messages in place");
         if (p->hp.three_way)
@@ -1142,11 +1175,12 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
         DeviceGuard g(plan->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
         const std::string key = tune_key(plan);
-        int cfg[3];
+        int cfg[4];
         if (cache_lookup(cache_path, key, cfg) && valid_cfg(cfg)) {
             plan->block_nnz = cfg[0];
             plan->window = cfg[1];
             plan->item = cfg[2];
+            plan->remote_nnz = cfg[3];
             refresh_schedules(plan);
             HIP_OK(hipDeviceSynchronize());
             if (best_ms) *best_ms = -1.0;
@@ -1156,31 +1190,40 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
         double best = 1e30;
-        int best_cfg[3] = {cur_cap(plan), cur_win(plan), cur_item(plan)};
+        int best_cfg[4] = {cur_cap(plan), cur_win(plan), cur_item(plan), cur_rcap(plan)};
+        auto trial = [&](int cap, int win, int item, int rcap) {
+            plan->block_nnz = cap;
+            plan->window = win;
+            plan->item = item;
+            plan->remote_nnz = rcap;
+            refresh_schedules(plan);
+            const Ws wp = ws_ptrs(plan, plan->d_ws);
+            run_apply(plan, wp, v, w, s);            // warm-up
+            HIP_OK(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) run_apply(plan, wp, v, w, s);
+            HIP_OK(hipEventRecord(e1, s));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            const double per = ms / reps;
+            if (per < best) {
+                best = per;
+                best_cfg[0] = cap;
+                best_cfg[1] = win;
+                best_cfg[2] = item;
+                best_cfg[3] = rcap;
+            }
+        };
         try {
-            for (int cap : {1024, 2048, 4096})
+            // the first launch's parameters with the remote block size held,
+            // then the remote block size alone
+            const int rcap0 = best_cfg[3];
+            for (int cap : {1024, 2048, 4096, 8192})
                 for (int win : {0, 1024, 2048, 4096})
-                    for (int item : {16384, 65536}) {
-                        plan->block_nnz = cap;
-                        plan->window = win;
-                        plan->item = item;
-                        refresh_schedules(plan);
-                        const Ws wp = ws_ptrs(plan, plan->d_ws);
-                        run_apply(plan, wp, v, w, s);            // warm-up
-                        HIP_OK(hipEventRecord(e0, s));
-                        for (int r = 0; r < reps; ++r) run_apply(plan, wp, v, w, s);
-                        HIP_OK(hipEventRecord(e1, s));
-                        HIP_OK(hipEventSynchronize(e1));
-                        float ms = 0;
-                        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-                        const double per = ms / reps;
-                        if (per < best) {
-                            best = per;
-                            best_cfg[0] = cap;
-                            best_cfg[1] = win;
-                            best_cfg[2] = item;
-                        }
-                    }
+                    for (int item : {16384, 65536}) trial(cap, win, item, rcap0);
+            const int c0 = best_cfg[0], w0 = best_cfg[1], i0 = best_cfg[2];
+            for (int rcap : {1024, 2048, 4096, 8192})
+                if (rcap != rcap0) trial(c0, w0, i0, rcap);
         } catch (...) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
@@ -1191,6 +1234,7 @@ int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *w, void *str
         plan->block_nnz = best_cfg[0];
         plan->window = best_cfg[1];
         plan->item = best_cfg[2];
+        plan->remote_nnz = best_cfg[3];
         refresh_schedules(plan);
         HIP_OK(hipDeviceSynchronize());
         cache_store(cache_path, key, best_cfg, best);
@@ -1276,9 +1320,14 @@ int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value) {
     if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
     switch (param) {
         case NAPSPMV_PARAM_BLOCK_NNZ:
-            if (value != -1 && value != 1024 && value != 2048 && value != 4096)
-                return fail(NAPSPMV_EINVAL, "block entries must be -1, 1024, 2048 or 4096");
+            if (value != -1 && !valid_block(value))
+                return fail(NAPSPMV_EINVAL, "block entries must be -1, 1024, 2048, 4096 or 8192");
             plan->block_nnz = value;
+            break;
+        case NAPSPMV_PARAM_REMOTE_NNZ:
+            if (value != -1 && !valid_block(value))
+                return fail(NAPSPMV_EINVAL, "remote block entries must be -1, 1024, 2048, 4096 or 8192");
+            plan->remote_nnz = value;
             break;
         case NAPSPMV_PARAM_GATHER_ITEM:
             if (value != -1 && (value < kMinItem || value > kMaxItem))
@@ -1307,6 +1356,7 @@ int napspmv_plan_get_param(napspmv_plan_t plan, int param) {
     if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
     switch (param) {
         case NAPSPMV_PARAM_BLOCK_NNZ: return cur_cap(plan);
+        case NAPSPMV_PARAM_REMOTE_NNZ: return cur_rcap(plan);
         case NAPSPMV_PARAM_GATHER_ITEM: return cur_item(plan);
         case NAPSPMV_PARAM_VWINDOW: return cur_win(plan);
         default: return fail(NAPSPMV_EINVAL, "unknown parameter");

@@ -188,12 +188,14 @@ def test_tuning_parameters():
     a = kkt_like(1 << 10, 2)
     p = lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, host_only=True)
     assert p.get_param("block_nnz") == 4096 and p.get_param("window") == 1024
-    assert p.get_param("gather_item") == 65536
+    assert p.get_param("gather_item") == 65536 and p.get_param("remote_nnz") == 8192
+    p.set_param("remote_nnz", 2048)
+    assert p.get_param("remote_nnz") == 2048
     p.set_param("block_nnz", 1024)
     p.set_param("window", 0)
     p.set_param("gather_item", 700)
     assert (p.get_param("block_nnz"), p.get_param("window"), p.get_param("gather_item")) == (1024, 0, 700)
-    for name, bad in (("block_nnz", 3000), ("window", 512), ("gather_item", 255),
+    for name, bad in (("block_nnz", 3000), ("window", 512), ("gather_item", 255), ("remote_nnz", 512),
                       ("gather_item", (1 << 24) + 1)):
         with pytest.raises(lib.NapspmvError):
             p.set_param(name, bad)

@@ -162,16 +162,17 @@ def test_kkt_full_nap_bitwise(kkt):
     assert np.array_equal(ws, wn)
 
 
-@pytest.mark.parametrize("block_nnz,item,window", [(1024, 256, 0), (2048, 3000, 1024),
-                                                   (4096, 65536, 4096), (-1, -1, -1),
-                                                   (2048, 1 << 20, 2048), (1024, 777, 4096)])
-def test_stream_schedules_bitwise(block_nnz, item, window):
+@pytest.mark.parametrize("block_nnz,item,window,remote", [(1024, 256, 0, 1024), (2048, 3000, 1024, 8192),
+                                                          (4096, 65536, 4096, 2048), (-1, -1, -1, -1),
+                                                          (2048, 1 << 20, 2048, 4096),
+                                                          (8192, 777, 4096, 8192), (8192, 4096, 0, 1024)])
+def test_stream_schedules_bitwise(block_nnz, item, window, remote):
     a = kkt_like(1 << 15, 11)
     v = vec_normal(a.n, 12)
     ref = _split(a, v, 64)
     for mode in ("standard", "nap"):
         w, g, gc = _run(a, v, 64, 16, mode, params={"block_nnz": block_nnz, "gather_item": item,
-                                                    "window": window})
+                                                    "window": window, "remote_nnz": remote})
         _check_ghosts(g, gc, v, "f64")
         assert np.array_equal(w, ref)
 

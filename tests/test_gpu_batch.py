@@ -170,13 +170,14 @@ def test_autotune_keeps_results_and_caches():
             w = torch.zeros_like(v)
             best = p.autotune(v, w, reps=2, cache_path=cache)
             assert best > 0
-            cfg = (p.get_param("block_nnz"), p.get_param("window"), p.get_param("gather_item"))
+            cfg = (p.get_param("block_nnz"), p.get_param("window"), p.get_param("gather_item"),
+                   p.get_param("remote_nnz"))
             assert torch.equal(_solo(p, v), ref)
             p.close()
             p2 = _plan(a, 64, 16, mode=mode)
             assert p2.autotune(v, w, reps=2, cache_path=cache) == -1.0      # from the cache
             assert (p2.get_param("block_nnz"), p2.get_param("window"),
-                    p2.get_param("gather_item")) == cfg
+                    p2.get_param("gather_item"), p2.get_param("remote_nnz")) == cfg
             assert torch.equal(_solo(p2, v), ref)
             p2.close()
         assert len(open(cache).read().splitlines()) == 2

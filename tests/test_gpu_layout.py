@@ -32,10 +32,12 @@ def test_relayout_between_applies(mode, variant):
     tv = torch.from_numpy(v).to(DEV)
     with nap.Plan(a.rowptr, a.col, a.val, a.n, n_p, ppn, mode=mode, variant=variant) as p:
         _, gc = p.ghosts()
-        for cap, item in ((4096, -1), (1024, 300), (2048, 1 << 20), (4096, 256), (-1, -1)):
-            print(f"mode={mode} variant={variant} block_nnz={cap} item={item}", flush=True)
+        for cap, item, rcap in ((4096, -1, -1), (1024, 300, 1024), (2048, 1 << 20, 4096),
+                                (8192, 256, 2048), (4096, 1000, 1024), (-1, -1, -1)):
+            print(f"mode={mode} variant={variant} block_nnz={cap} item={item} remote={rcap}", flush=True)
             p.set_param("block_nnz", cap)
             p.set_param("gather_item", item)
+            p.set_param("remote_nnz", rcap)
             assert np.array_equal(_apply(p, tv), ref)
             assert np.array_equal(p.read_ghosts(), v[gc])
 
@@ -48,9 +50,10 @@ def test_partitions_follow_relayout():
     tv = torch.from_numpy(v).to(DEV)
     with nap.Plan(a.rowptr, a.col, a.val, a.n, n_p, 2, mode="standard") as p:
         p.prepare_partitions()
-        for cap in (4096, 1024, 2048):
-            print(f"partitions block_nnz={cap}", flush=True)
+        for cap, rcap in ((4096, 8192), (1024, 1024), (2048, 4096), (8192, 2048)):
+            print(f"partitions block_nnz={cap} remote={rcap}", flush=True)
             p.set_param("block_nnz", cap)
+            p.set_param("remote_nnz", rcap)
             w = torch.full_like(tv, float("nan"))
             for t in range(n_p):
                 p.apply_partition(t, tv, w)
