@@ -170,6 +170,10 @@ __device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
 // off-process part), or, for on-process columns inside the block's window
 // win = (first, length) of v, from a copy of that window staged in LDS.
 //
+// Columns come as CT (int32, or uint16 offsets from `cbase`, the first row
+// of the block's process, when every process holds at most 65536 rows: two
+// bytes instead of four per on-process entry).
+//
 // Off-process blocks of at most CAP entries are stored in gather order
 // (ascending ghost position, so a wave's lanes read nearby ghost values and
 // share cache lines); slot[k] is the stored position of entry k inside its
@@ -177,10 +181,10 @@ __device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
 // stored order.
 constexpr int kMaxRows = 1024;
 
-template <typename VT, typename XT, int CAP, int W, bool REMOTE>
+template <typename VT, typename XT, typename CT, int CAP, int W, bool REMOTE>
 __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                               int2 win, const int32_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col,
+                                              const CT *__restrict__ col, int32_t cbase,
                                               const VT *__restrict__ val,
                                               const uint16_t *__restrict__ slot,
                                               const XT *__restrict__ xsrc, XT *__restrict__ w,
@@ -194,7 +198,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
             const int32_t lim = (k1 - base) < CAP ? (k1 - base) : CAP;
             for (int32_t q = tid; q < lim; q += kBlock) {
                 const int32_t k = base + q;
-                prod[q] = (XT)load_val(val, k) * xsrc[__builtin_nontemporal_load(col + k)];
+                prod[q] = (XT)load_val(val, k) * xsrc[cbase + (int32_t)__builtin_nontemporal_load(col + k)];
             }
             __syncthreads();
             if (tid == 0)
@@ -216,7 +220,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t k = min(k0 + u * kBlock + tid, klast);
-        c[u] = __builtin_nontemporal_load(col + k);
+        c[u] = cbase + (int32_t)__builtin_nontemporal_load(col + k);
         a[u] = (XT)load_val(val, k);
         if (REMOTE) sl[REMOTE ? u : 0] = __builtin_nontemporal_load(slot + k);
     }
@@ -285,6 +289,8 @@ struct LocalView {
     const int32_t *rowblk, *blkptr;
     const int2 *win;           // v windows of the on-process blocks (or null)
     const int32_t *rowptr, *col;
+    const uint16_t *col16;     // or, when not null, uint16 columns offset by base[block]
+    const int32_t *base;
     const VT *val;
     const XT *v;
     XT *w;
@@ -319,16 +325,21 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
         return;
     }
     const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
-    product_block<VT, XT, CAP, W, false>(L.rowblk[task], L.rowblk[task + 1], L.blkptr[task],
-                                         L.blkptr[task + 1], wn, L.rowptr, L.col, L.val, nullptr,
-                                         L.v, L.w, prod, wbuf);
+    if (L.col16)
+        product_block<VT, XT, uint16_t, CAP, W, false>(
+            L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
+            L.col16, L.base[task], L.val, nullptr, L.v, L.w, prod, wbuf);
+    else
+        product_block<VT, XT, int32_t, CAP, W, false>(
+            L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
+            L.col, 0, L.val, nullptr, L.v, L.w, prod, wbuf);
 }
 
 template <typename VT, typename XT, int CAP>
 __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
-    product_block<VT, XT, CAP, 0, true>(R.rowblk[b], R.rowblk[b + 1], R.blkptr[b],
-                                        R.blkptr[b + 1], make_int2(0, 0), R.rowptr, R.col, R.val,
-                                        R.slot, R.ghost, R.w, prod, nullptr);
+    product_block<VT, XT, int32_t, CAP, 0, true>(R.rowblk[b], R.rowblk[b + 1], R.blkptr[b],
+                                                 R.blkptr[b + 1], make_int2(0, 0), R.rowptr, R.col,
+                                                 0, R.val, R.slot, R.ghost, R.w, prod, nullptr);
 }
 
 // Index of the entry of prefix[0..count] (ascending, prefix[0] = 0) whose

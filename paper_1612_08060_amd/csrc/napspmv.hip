@@ -38,6 +38,7 @@ struct Schedules {
     int32_t *onblk = nullptr, *onptr = nullptr, *win = nullptr;
     int32_t *offblk = nullptr, *offptr = nullptr, *items = nullptr, *tasks = nullptr;
     int32_t *ndblk = nullptr, *ndptr = nullptr;     // three-way: on_node row blocks
+    int32_t *onbase = nullptr;                      // first row of each on-process block's process
     int32_t *sitems = nullptr;                      // NAP: band items of the ghost scatter
     int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, n_nd = 0, n_sitems = 0, bytes = 0;
     // per-partition schedules only: each process's range of tasks and of
@@ -57,6 +58,7 @@ struct napspmv_plan_s {
     int sorted_remote_nnz = 0;       // block size the off-process entry order was sorted for
     int64_t G = 0, E = 0, H = 0, Gon = 0;
     int32_t *d_rp_on = nullptr, *d_col_on = nullptr, *d_rp_off = nullptr, *d_col_off = nullptr;
+    uint16_t *d_col16_on = nullptr;  // on-process columns as offsets from the process's first row
     void *d_val_on = nullptr, *d_val_off = nullptr;
     // Band-ordered exchange buffers (see exchange_item), laid out for bands of
     // `layout_cap` columns: gpos[k] = device position of ghost k of the
@@ -196,7 +198,7 @@ void charge(napspmv_plan_s *p, int64_t bytes) {
 
 void free_schedules(napspmv_plan_s *p, Schedules &s) {
     void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks, s.ndblk, s.ndptr,
-                    s.sitems};
+                    s.sitems, s.onbase};
     for (void *q : ptrs) free_ptr(q);
     charge(p, -s.bytes);
     s = Schedules();
@@ -208,11 +210,13 @@ void free_device(napspmv_plan_s *p) {
     p->part_ready = false;
     void *ptrs[] = {p->d_rp_on, p->d_col_on, p->d_rp_off, p->d_col_off, p->d_val_on,
                     p->d_val_off, p->d_off, p->d_code, p->d_pgcol, p->d_pgpos, p->d_ws,
-                    p->d_rp_nd, p->d_col_nd, p->d_val_nd, p->d_slot_off, p->d_slot_nd};
+                    p->d_rp_nd, p->d_col_nd, p->d_val_nd, p->d_slot_off, p->d_slot_nd,
+                    p->d_col16_on};
     for (void *q : ptrs) free_ptr(q);
     p->d_rp_nd = p->d_col_nd = nullptr;
     p->d_val_nd = nullptr;
     p->d_slot_off = p->d_slot_nd = nullptr;
+    p->d_col16_on = nullptr;
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->helper) (void)hipStreamDestroy(p->helper);
@@ -246,7 +250,7 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
                       const std::vector<int32_t> &offblk, const std::vector<int32_t> &offptr,
                       const std::vector<int32_t> &items, const std::vector<int32_t> &tasks,
                       const std::vector<int32_t> &ndblk = {}, const std::vector<int32_t> &ndptr = {},
-                      const std::vector<int32_t> &sitems = {}) {
+                      const std::vector<int32_t> &sitems = {}, const std::vector<int32_t> &onbase = {}) {
     free_schedules(p, s);
     int64_t total = 0;
     try {
@@ -260,6 +264,7 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
         upload(s.items, items, total);
         upload(s.tasks, tasks, total);
         upload(s.sitems, sitems, total);
+        upload(s.onbase, onbase, total);
     } catch (...) {
         s.bytes = total;
         charge(p, total);
@@ -300,7 +305,7 @@ void build_partitions(napspmv_plan_s *p) {
         }
         charge(p, total);
     }
-    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks;
+    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, onbase;
     std::vector<int64_t> task_ptr(hp.n_p + 1, 0), off_ptr(hp.n_p + 1, 0);
     for (int64_t t = 0; t < hp.n_p; ++t) {
         const int64_t r0 = hp.starts[t], r1 = hp.starts[t + 1];
@@ -323,6 +328,7 @@ void build_partitions(napspmv_plan_s *p) {
         // concatenate; a process's closing boundary is the next one's first
         onblk.insert(onblk.end(), ob.begin(), ob.end() - 1);
         onptr.insert(onptr.end(), op.begin(), op.end() - 1);
+        onbase.insert(onbase.end(), ob.size() - 1, (int32_t)r0);
         wins.insert(wins.end(), wn.begin(), wn.end());
         off_ptr[t] = (int64_t)offblk.size();
         offblk.insert(offblk.end(), fb.begin(), fb.end() - 1);
@@ -336,7 +342,7 @@ void build_partitions(napspmv_plan_s *p) {
     onptr.push_back(hp.rowptr_on[hp.n]);
     offblk.push_back((int32_t)hp.n);
     offptr.push_back(hp.rowptr_off[hp.n]);
-    upload_schedules(p, p->part, onblk, onptr, wins, offblk, offptr, items, tasks);
+    upload_schedules(p, p->part, onblk, onptr, wins, offblk, offptr, items, tasks, {}, {}, {}, onbase);
     p->part.task_ptr = task_ptr;
     p->part.off_ptr = off_ptr;
     p->part_ready = true;
@@ -439,8 +445,15 @@ void refresh_schedules(napspmv_plan_s *p) {
         rcap == p->cur_remote_nnz)
         return;
     const HostPlan &hp = p->hp;
-    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems;
-    napspmv::row_blocks(hp.rowptr_on.data(), hp.n, cap, kMaxRowsPerBlock, onblk, onptr);
+    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems, onbase;
+    // on-process blocks never span two processes: each block's columns are
+    // offsets from its process's first row
+    napspmv::row_blocks_per_process(hp.rowptr_on.data(), hp.starts, cap, kMaxRowsPerBlock, onblk,
+                                    onptr);
+    onbase.resize(onblk.size() - 1);
+    for (size_t b = 0; b + 1 < onblk.size(); ++b)
+        onbase[b] = (int32_t)hp.starts[(std::upper_bound(hp.starts.begin(), hp.starts.end(), onblk[b]) -
+                                        hp.starts.begin()) - 1];
     if (win > 0) napspmv::row_block_windows(onblk, hp.on_lo, hp.on_hi, hp.n, win, wins);
     napspmv::row_blocks_per_process(hp.rowptr_off.data(), hp.starts, rcap, kMaxRowsPerBlock, offblk,
                                     offptr);
@@ -469,7 +482,7 @@ void refresh_schedules(napspmv_plan_s *p) {
     }
     napspmv::merge_tasks((int64_t)items.size() / 4, (int64_t)onblk.size() - 1, tasks);
     upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr,
-                     sitems);
+                     sitems, onbase);
     p->cur_block_nnz = cap;
     p->cur_window = win;
     p->cur_item = item;
@@ -489,7 +502,19 @@ void to_device(napspmv_plan_s *p) {
     int64_t total = 0;
     try {
         upload(p->d_rp_on, hp.rowptr_on, total);
-        upload(p->d_col_on, hp.col_on, total);
+        int64_t most_rows = 0;
+        for (int64_t t = 0; t < hp.n_p; ++t) most_rows = std::max(most_rows, hp.starts[t + 1] - hp.starts[t]);
+        if (most_rows <= 65536) {
+            // on-process columns as 16-bit offsets from the process's first row
+            std::vector<uint16_t> c16(hp.col_on.size());
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t t = 0; t < hp.n_p; ++t)
+                for (int64_t k = hp.rowptr_on[hp.starts[t]]; k < hp.rowptr_on[hp.starts[t + 1]]; ++k)
+                    c16[k] = (uint16_t)(hp.col_on[k] - hp.starts[t]);
+            upload(p->d_col16_on, c16, total);
+        } else {
+            upload(p->d_col_on, hp.col_on, total);
+        }
         upload(p->d_rp_off, hp.rowptr_off, total);
         auto alloc = [&](auto *&dst, size_t bytes) {
             const size_t cap = std::max(bytes, kMinAlloc);
@@ -565,6 +590,8 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
     L.win = reinterpret_cast<const int2 *>(s.win);
     L.rowptr = p->d_rp_on;
     L.col = p->d_col_on;
+    L.col16 = p->d_col16_on;
+    L.base = s.onbase;
     L.val = static_cast<const VT *>(p->d_val_on);
     L.v = v;
     L.w = w;
