@@ -114,7 +114,7 @@ extern "C" {
  * the call order).  Batches refuse such plans (EUNSUPPORTED); servers run
  * them alone. */
 #define NAPSPMV_NAP_THREE_WAY 0x20u
-/* Strided partition (section 5.3): row r, and v_r, on process r mod n_p
+/* Strided partition (section 5): row r, and v_r, on process r mod n_p
  * (row_starts must be NULL; EINVAL with NAPSPMV_NAP_SPLIT, whose pieces
  * follow index order).  The plan, its exports and napspmv_apply work in the
  * process-major numbering that a distributed code stores: position

@@ -76,7 +76,7 @@ VARIANTS = frozenset({"owner_map", "dedup", "split", "three_way"})
 
 class Layout:
     """Processes, nodes and row blocks (section 2).  ``strided=True`` gives
-    the strided partition of section 5.3 instead: row r on process
+    the strided partition of section 5 instead: row r on process
     r mod n_p."""
 
     def __init__(self, n: int, n_p: int, ppn: int, row_starts=None, strided: bool = False):

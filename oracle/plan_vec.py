@@ -42,7 +42,7 @@ def owner(starts: np.ndarray, j: np.ndarray) -> np.ndarray:
 def owner_fn(starts, n_p: int):
     """The owner map of a partition: contiguous blocks given by ``starts``,
     or, when ``starts`` is None, the strided partition (row r on process
-    r mod n_p, section 5.3)."""
+    r mod n_p, section 5)."""
     if starts is None:
         return lambda j: np.asarray(j, dtype=np.int64) % n_p
     return lambda j: owner(starts, j)

@@ -145,7 +145,7 @@ class Plan:
     change the messages, not the result; "three_way" sums each row in the
     three parts of algorithm NAPSpMV (on_process, on_node, off_node) with the
     inter-node hop overlapped with the on_node product.  ``strided`` puts
-    row r on process r mod n_p (section 5.3); the plan, its exports and v, w
+    row r on process r mod n_p (section 5); the plan, its exports and v, w
     are then in process-major order (see ``rows``).
     """
 

@@ -183,8 +183,8 @@ void upload(T *&dst, const std::vector<T> &src, int64_t &total) {
     const size_t bytes = src.size() * sizeof(T), cap = std::max(bytes, kMinAlloc);
     HIP_OK(hipMalloc(reinterpret_cast<void **>(&dst), cap));
     total += (int64_t)cap;
-    HIP_OK(hipMemset(dst, 0, cap));
     if (bytes) HIP_OK(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
+    if (cap > bytes) HIP_OK(hipMemset(reinterpret_cast<char *>(dst) + bytes, 0, cap - bytes));
 }
 
 void free_ptr(void *p) {
@@ -531,8 +531,9 @@ void to_device(napspmv_plan_s *p) {
             const size_t cap = std::max(src.size(), kMinAlloc);
             HIP_OK(hipMalloc(&dst, cap));
             total += (int64_t)cap;
-            HIP_OK(hipMemset(dst, 0, cap));
             if (!src.empty()) HIP_OK(hipMemcpy(dst, src.data(), src.size(), hipMemcpyHostToDevice));
+            if (cap > src.size())
+                HIP_OK(hipMemset(static_cast<char *>(dst) + src.size(), 0, cap - src.size()));
         };
         upload_bytes(p->d_val_on, hp.val_on);
         if (hp.three_way) {

@@ -164,7 +164,7 @@ void release_device_arrays(HostPlan &hp) {
 
 namespace {
 
-// Strided partition (section 5.3: row r on process r mod n_p) as the
+// Strided partition (section 5: row r on process r mod n_p) as the
 // contiguous partition of the symmetrically permuted matrix P A P^T, with
 // row r at position starts[r mod n_p] + r div n_p: every set of the paper
 // depends only on which process owns which index, so the plan of the
