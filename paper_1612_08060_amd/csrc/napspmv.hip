@@ -288,9 +288,10 @@ bool valid_block(int v) { return v == 1024 || v == 2048 || v == 4096 || v == 819
 int cur_win(const napspmv_plan_s *p) { return p->window >= 0 ? p->window : p->auto_window; }
 int cur_item(const napspmv_plan_s *p) { return p->item >= 0 ? p->item : p->auto_item; }
 
-// Per-partition schedules (standard mode): each process's row blocks and its
-// own ghost gather items, contiguous per process, so one process's product
-// is one pair of launches.
+// Per-partition schedules (standard mode): each process's row blocks and
+// indexed gather items for its own ghosts (into their band-ordered
+// positions), contiguous per process, so one process's product is one pair
+// of launches.
 void build_partitions(napspmv_plan_s *p) {
     const HostPlan &hp = p->hp;
     const int cap = cur_cap(p), win = cur_win(p);
@@ -436,9 +437,11 @@ void band_items(const std::vector<int64_t> &bstart, int item, std::vector<int32_
 }
 
 // (Re)build the launch schedules for the current tuning: on-process row
-// blocks with their v windows, off-process row blocks, the exchange items
-// (standard: ghost gather by column band; NAP: pack in order) and the task
-// list of the first launch.  Per-partition schedules follow.
+// blocks with their v windows and process bases, off-process row blocks,
+// the band items of the exchange (standard: the ghost buffer; NAP: the send
+// buffer, plus the scatter items over the ghost buffer) and the task list of
+// the first launch; re-lay the bands and re-sort the off-process blocks when
+// the block sizes change.  Per-partition schedules follow.
 void refresh_schedules(napspmv_plan_s *p) {
     const int cap = cur_cap(p), win = cur_win(p), item = cur_item(p), rcap = cur_rcap(p);
     if (p->sched.onblk && cap == p->cur_block_nnz && win == p->cur_window && item == p->cur_item &&
