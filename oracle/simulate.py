@@ -8,9 +8,11 @@ buffer; nothing is shared between ranks except what a message carries.  The
 simulation asserts that every slot of every ghost list is written exactly
 once, with the owner's value, bit for bit.
 
-The split product sums, per row and in stored order, first the on-process
-block and then the off-process block (standard), or the on_process, on_node
-and off_node blocks in that order (NAPSpMV).
+The split product accumulates, per row, from 0 and in stored order within
+each block, first the on-process block and then the off-process block
+(standard_spmv, and NAPSpMV under the default two-part reading), or the
+on_process, on_node and off_node blocks in that order (NAPSpMV with the
+``three_way`` variant): one rounded product and one rounded add per entry.
 """
 from __future__ import annotations
 
@@ -136,7 +138,8 @@ def simulate_nap(csr, lay: Layout, plan: dict, v):
                     slots[j] = x
         _check(t, gh[t], counts, slots, v)
         ghost_vals.append(slots)
-    w = _split_product(csr, lay, v_loc, ghost_vals, three_way=True)
+    three = "three_way" in plan.get("variant", ())
+    w = _split_product(csr, lay, v_loc, ghost_vals, three_way=three)
     return ghost_vals, w
 
 
@@ -149,19 +152,25 @@ def _check(t, gh_t, counts, slots, v):
 
 
 def _split_product(csr, lay, v_loc, ghost_vals, three_way: bool):
-    """local_spmv on the split blocks of every rank."""
+    """local_spmv on the split blocks of every rank, accumulated into w."""
     w = np.zeros(csr.n)
     for t in range(lay.n_p):
         for i in lay.R(t):
-            parts = [0.0, 0.0, 0.0]
-            for k in range(int(csr.rowptr[i]), int(csr.rowptr[i + 1])):
-                j, a = int(csr.col[k]), float(csr.val[k])
+            entries = [(int(csr.col[k]), float(csr.val[k]))
+                       for k in range(int(csr.rowptr[i]), int(csr.rowptr[i + 1]))]
+
+            def part(j):
                 r = lay.owner(j)
                 if r == t:
-                    parts[0] += a * v_loc[t][j]
-                elif three_way and lay.node(r) == lay.node(t):
-                    parts[1] += a * ghost_vals[t][j]
-                else:
-                    parts[2] += a * ghost_vals[t][j]
-            w[i] = (parts[0] + parts[1]) + parts[2] if three_way else parts[0] + parts[2]
+                    return 0
+                return 1 if three_way and lay.node(r) == lay.node(t) else 2
+
+            acc = 0.0
+            for block in (0, 1, 2):
+                for j, a in entries:
+                    if part(j) != block:
+                        continue
+                    x = v_loc[t][j] if block == 0 else ghost_vals[t][j]
+                    acc = acc + a * x
+            w[i] = acc
     return w

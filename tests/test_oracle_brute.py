@@ -92,6 +92,13 @@ def test_every_ghost_delivered_once(n_p, ppn):
         ref = brute.matvec(a, v)
         assert np.allclose(w_s, ref, rtol=1e-13, atol=1e-13)
         assert np.allclose(w_n, ref, rtol=1e-13, atol=1e-13)
+        # the simulation's per-rank products, from delivered values, equal the
+        # C split-order routines bit for bit (two independent evaluations)
+        from oracle import spmv as ospmv
+        assert np.array_equal(w_s, ospmv.spmv_split(a, v, n_p))
+        assert np.array_equal(w_n, ospmv.spmv_split(a, v, n_p))
+        _, w_3 = simulate.simulate_nap(a, lay, plan_ref.nap_plan(a, lay, ("three_way",)), v)
+        assert np.array_equal(w_3, ospmv.spmv_split3(a, v, n_p, ppn))
 
 
 def test_mapping_invariants_many_partners():
