@@ -21,8 +21,9 @@
  *                     message per node pair, scattered on the destination
  *                     node; on-node ghosts go directly.
  *
- * Both modes fill the same ghost buffer (each process's ghosts in ascending
- * column order) and run the same split product
+ * Both modes fill the same ghost values (each process's ghosts, which the
+ * plan lists in ascending column order; on the device the buffer is laid
+ * out by column band) and run the same split product
  *     w_i = sum_on a_ij v_j + sum_off a_ij ghost_t(j),
  * so their results are bitwise identical.  Each row is summed as algorithm
  * standard_spmv does: sequentially from 0, its on-process entries in stored
@@ -242,8 +243,8 @@ NAPSPMV_API int napspmv_apply_ws(napspmv_plan_t plan, void *ws, const void *v, v
  * in one launch sequence -- one first launch over every product's exchange
  * and on-process work, one NAP scatter launch if any plan is NAP, one second
  * launch over every off-process product.  All plans must share the value
- * type, BLOCK_NNZ and VWINDOW, be on the batch's device and receive NAP
- * messages in place.  ws may be NULL (every plan's own workspace) or hold
+ * type, BLOCK_NNZ, VWINDOW and REMOTE_NNZ, be on the batch's device, receive
+ * NAP messages in place and use the two-part product (no NAPSPMV_NAP_THREE_WAY).  ws may be NULL (every plan's own workspace) or hold
  * per-product workspaces (NULL entries = the plan's own).  The batch object
  * owns a device descriptor table (and a pinned host copy) for up to
  * max_count products; a call waits until the previous call's launches have
