@@ -464,6 +464,23 @@ def main():
                        "speedup_vs_f64": round(ms / ms_r, 3),
                        "rel_err_vs_f64_apply": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
             pr.close()
+        # the 3D 7-point Laplacian, 128^3, n_p = 1024 at ppn = 16 (float64)
+        wl2 = config(2)
+        a2 = wl2.csr
+        v2 = torch.from_numpy(wl2.v).to(dev)
+        lap = {}
+        for mode in ("standard", "nap"):
+            p2 = nap.Plan(a2.rowptr, a2.col, a2.val, a2.n, wl2.n_p, wl2.ppn, mode=mode, dtype="f64")
+            w2 = torch.empty_like(v2)
+            ms2, ex2, sp2 = time_apply(p2, v2, w2, max(10, args.steps // 2), 2, torch, nap)
+            s2 = p2.stats
+            b2 = spmv_bytes(s2, 8, 8) + exchange_bytes(s2, 8)
+            lap[mode] = {"ms": round(ms2, 5), "gbs": round(b2 / (ms2 * 1e-3) / 1e9, 1),
+                         "local_ms": round(ex2, 5), "remote_ms": round(sp2, 5)}
+            p2.close()
+            del w2
+        ext["laplace3d_128cube_np1024_ppn16_f64"] = lap
+        del v2
         result["extras"] = ext
 
     if args.batched:
