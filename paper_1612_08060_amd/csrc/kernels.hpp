@@ -47,6 +47,16 @@ __device__ __forceinline__ float load_val(const uint16_t *p, int32_t k) {
     return __uint_as_float((uint32_t)b << 16);   // bfloat16 -> float32 is exact
 }
 
+// dst[dpos[k]] = src[sidx[k]] for k < n: a short indexed copy (the fully
+// local step of a three-way apply).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_put(int32_t n, const int32_t *__restrict__ dpos,
+                                                const int32_t *__restrict__ sidx,
+                                                const T *__restrict__ src, T *__restrict__ dst) {
+    const uint32_t k = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (k < (uint32_t)n) dst[__builtin_nontemporal_load(dpos + k)] = src[__builtin_nontemporal_load(sidx + k)];
+}
+
 // dst[k] = src[k]: the explicit inter-node hop (send buffer -> receive buffer).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const T *__restrict__ src,

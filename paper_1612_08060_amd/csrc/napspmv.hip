@@ -71,6 +71,9 @@ struct napspmv_plan_s {
     uint16_t *d_off = nullptr;
     uint32_t *d_code = nullptr;
     int32_t *d_pgcol = nullptr, *d_pgpos = nullptr;   // per-process indexed gathers
+    // three-way plans: the fully local step as an indexed list (device
+    // position, column of v) so that it does not walk every ghost position
+    int32_t *d_l2pos = nullptr, *d_l2col = nullptr;
     // three-way plans: the on_node block, and the helper stream and events
     // that run the inter-node hop and scatter beside the on_node product
     int32_t *d_rp_nd = nullptr, *d_col_nd = nullptr;
@@ -210,6 +213,7 @@ void free_device(napspmv_plan_s *p) {
     p->part_ready = false;
     void *ptrs[] = {p->d_rp_on, p->d_col_on, p->d_rp_off, p->d_col_off, p->d_val_on,
                     p->d_val_off, p->d_off, p->d_code, p->d_pgcol, p->d_pgpos, p->d_ws,
+                    p->d_l2pos, p->d_l2col,
                     p->d_rp_nd, p->d_col_nd, p->d_val_nd, p->d_slot_off, p->d_slot_nd,
                     p->d_col16_on};
     for (void *q : ptrs) free_ptr(q);
@@ -227,6 +231,7 @@ void free_device(napspmv_plan_s *p) {
     p->d_off = nullptr;
     p->d_code = nullptr;
     p->d_pgcol = p->d_pgpos = nullptr;
+    p->d_l2pos = p->d_l2col = nullptr;
     p->layout_cap = 0;
     p->sorted_remote_nnz = 0;
     g_in_use -= p->device_bytes;
@@ -421,6 +426,11 @@ void build_layout(napspmv_plan_s *p, int cap) {
             code[gpos[hp.l2_dst[k]]] = napspmv::kFromV | (uint32_t)(hp.l2_src[k] % cap);
         if (E) HIP_OK(hipMemcpy(p->d_off, off.data(), E * 2, hipMemcpyHostToDevice));
         if (G) HIP_OK(hipMemcpy(p->d_code, code.data(), G * 4, hipMemcpyHostToDevice));
+        if (hp.three_way && p->Gon > 0) {
+            std::vector<int32_t> l2pos(p->Gon);
+            for (int64_t k = 0; k < p->Gon; ++k) l2pos[k] = gpos[hp.l2_dst[k]];
+            HIP_OK(hipMemcpy(p->d_l2pos, l2pos.data(), p->Gon * 4, hipMemcpyHostToDevice));
+        }
     }
     p->layout_cap = cap;
 }
@@ -544,6 +554,8 @@ void to_device(napspmv_plan_s *p) {
             alloc(p->d_col_nd, hp.col_nd.size() * 4);
             alloc(p->d_val_nd, hp.val_nd.size());
             alloc(p->d_slot_nd, hp.col_nd.size() * 2);
+            alloc(p->d_l2pos, (size_t)p->Gon * 4);
+            upload(p->d_l2col, hp.l2_src, total);
             HIP_OK(hipStreamCreateWithFlags(&p->helper, hipStreamNonBlocking));
             HIP_OK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
             HIP_OK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
@@ -693,7 +705,9 @@ void launch_three_way(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws
     HIP_OK(hipStreamWaitEvent(p->helper, p->ev_fork, 0));
     launch_scatter<XT, CAP>(p, sc, ws, v, p->helper, 1);
     HIP_OK(hipEventRecord(p->ev_join, p->helper));
-    launch_scatter<XT, CAP>(p, sc, ws, v, s, 2);
+    if (p->Gon > 0)
+        napspmv::k_put<XT><<<blocks_for(p->Gon), napspmv::kBlock, 0, s>>>(
+            (int32_t)p->Gon, p->d_l2pos, p->d_l2col, v, static_cast<XT *>(ws.ghost));
     if (sc.n_nd > 0 && p->hp.nnz_nd > 0)
         launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_nd, true), s);
     HIP_OK(hipStreamWaitEvent(s, p->ev_join, 0));
