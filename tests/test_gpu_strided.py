@@ -66,3 +66,32 @@ def test_laplace3d_f32():
     assert np.array_equal(g, to_f32(wl.v)[gcol])
     ref = oracle_spmv.spmv(a, wl.v)
     assert np.linalg.norm(w - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+def test_strided_partitions_and_batch():
+    """Per-process launches and a batch of a strided plan give the plan's own
+    result bit for bit."""
+    a = random_pattern(3000, 0.01, seed=77, duplicates=2)
+    a = CSR(a.n, a.rowptr, a.col, vec_normal(a.nnz, 78))
+    v = vec_normal(a.n, 79)
+    with nap.Plan(a.rowptr, a.col, a.val, a.n, 12, 4, mode="standard", strided=True) as p:
+        rows = p.rows()
+        tv = torch.from_numpy(v[rows]).to(DEV)
+        w0 = torch.full_like(tv, float("nan"))
+        p.apply(tv, w0)
+        p.prepare_partitions()
+        w1 = torch.full_like(tv, float("nan"))
+        for t in range(12):
+            p.apply_partition(t, tv, w1)
+        b = nap.Batch(2)
+        ws2 = p.new_workspace()
+        w2 = torch.full_like(tv, float("nan"))
+        w3 = torch.full_like(tv, float("nan"))
+        b.apply([p, p], [tv, tv], [w2, w3], workspaces=[None, ws2])
+        torch.cuda.synchronize()
+        b.close()
+        out = np.empty(a.n)
+        out[rows] = w0.cpu().numpy()
+        assert np.array_equal(out, oracle_spmv.spmv_split(a, v, 12, strided=True))
+        for w in (w1, w2, w3):
+            assert torch.equal(w, w0)
