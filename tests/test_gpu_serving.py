@@ -105,3 +105,44 @@ def test_server_rejects_bad_arguments():
     with pytest.raises(nap.NapspmvError):
         srv.wait(5)
     srv.close()
+
+
+def test_mixed_kernel_groups_and_solo_plans():
+    """Plans that differ in REMOTE_NNZ form separate kernel groups; an
+    explicit-hop NAP plan, a three-way plan and a strided plan run alone or
+    in their groups; every result equals the apply done alone."""
+    a1, a2, a3 = kkt_like(7000, 11), kkt_like(5000, 12), laplacian_2d(70, 50)
+    plans = [nap.Plan(a1.rowptr, a1.col, a1.val, a1.n, 16, 4, mode="standard"),
+             nap.Plan(a1.rowptr, a1.col, a1.val, a1.n, 16, 4, mode="standard"),
+             nap.Plan(a2.rowptr, a2.col, a2.val, a2.n, 20, 4, mode="nap", exchange_copy=True),
+             nap.Plan(a2.rowptr, a2.col, a2.val, a2.n, 20, 4, mode="nap", variant=("three_way",)),
+             nap.Plan(a3.rowptr, a3.col, a3.val, a3.n, 14, 7, mode="nap", strided=True),
+             nap.Plan(a3.rowptr, a3.col, a3.val, a3.n, 14, 7, mode="nap",
+                      variant=("owner_map", "dedup"))]
+    plans[1].set_param("remote_nnz", 2048)
+    plans[5].set_param("block_nnz", 1024)
+    sizes = [p.n for p in plans]
+    rng = np.random.default_rng(3)
+    ids = rng.integers(0, len(plans), size=48)
+    vs = [_vec(vec_uniform(sizes[i], 900 + k), "f64") for k, i in enumerate(ids)]
+    ref = []
+    for i, v in zip(ids, vs):
+        w = torch.empty_like(v)
+        plans[i].apply(v, w)
+        ref.append(w)
+    torch.cuda.synchronize()
+    srv = nap.Server(slots=3, max_batch=6)
+    pids = [srv.add(p) for p in plans]
+    outs = [torch.full_like(v, float("nan")) for v in vs]
+    tickets = [srv.submit(pids[i], v, w) for i, v, w in zip(ids, vs, outs)]
+    for t in tickets:
+        srv.wait(t)
+    torch.cuda.synchronize()
+    for k, t in enumerate(tickets):
+        _, _, bs = srv.info(t)
+        if ids[k] in (2, 3):
+            assert bs == 1                      # never batched
+        assert torch.equal(outs[k], ref[k]), k
+    srv.close()
+    for p in plans:
+        p.close()
