@@ -410,6 +410,17 @@ def main():
                                     "local_ms": round(ex_3, 5), "remote_ms": round(sp_3, 5)}
         p3.close()
         del w3
+        # direct reads: off-node ghosts read in place from the received buffer
+        pd = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="nap", dtype="f64",
+                      row_starts=wl.row_starts, variant=("direct",))
+        wd = torch.empty_like(v)
+        ms_d, ex_d, sp_d = time_apply(pd, v, wd, max(10, args.steps // 2), 2, torch, nap)
+        torch.cuda.synchronize()
+        ext["nap_direct_f64"] = {"ms": round(ms_d, 5), "gbs": round(bn / (ms_d * 1e-3) / 1e9, 1),
+                                 "local_ms": round(ex_d, 5), "remote_ms": round(sp_d, 5),
+                                 "bitwise_equal_to_standard": bool(torch.equal(w, wd))}
+        pd.close()
+        del wd
         # message statistics of the mapping variants (host-only plans)
         var = {}
         for name in ("owner_map", "split", "dedup"):

@@ -115,6 +115,14 @@ extern "C" {
  * the call order).  Batches refuse such plans (EUNSUPPORTED); servers run
  * them alone. */
 #define NAPSPMV_NAP_THREE_WAY 0x20u
+/* NAP, direct reads: the off-process product reads every off-node ghost
+ * value in place from the received inter-node buffer and every on-node one
+ * from v, the way processes sharing a node's memory can read each other's
+ * buffers; the off_node -> on_node and fully local steps move no data and
+ * no ghost buffer is filled (napspmv_plan_read_ghost_values is then
+ * EUNSUPPORTED).  Same messages, statistics and w.  EINVAL with
+ * NAPSPMV_NAP_THREE_WAY. */
+#define NAPSPMV_NAP_DIRECT    0x80u
 /* Strided partition (section 5): row r, and v_r, on process r mod n_p
  * (row_starts must be NULL; EINVAL with NAPSPMV_NAP_SPLIT, whose pieces
  * follow index order).  The plan, its exports and napspmv_apply work in the

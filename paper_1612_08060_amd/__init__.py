@@ -24,7 +24,8 @@ DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 PHASES = ("INTER", "L0", "L1", "L2")
 STAGE_LOCAL, STAGE_REMOTE = 0, 1
 HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
-VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20}
+VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20,
+            "direct": 0x80}
 PARTITION_STRIDED = 0x40
 PARAMS = {"block_nnz": 0, "gather_item": 1, "window": 2, "remote_nnz": 3}
 _VAL_NP = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}

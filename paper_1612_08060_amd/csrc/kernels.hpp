@@ -191,14 +191,15 @@ __device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
 // stored order.
 constexpr int kMaxRows = 1024;
 
-template <typename VT, typename XT, typename CT, int CAP, int W, bool REMOTE>
+template <typename VT, typename XT, typename CT, int CAP, int W, bool REMOTE, bool DIRECT = false>
 __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                               int2 win, const int32_t *__restrict__ rowptr,
                                               const CT *__restrict__ col, int32_t cbase,
                                               const VT *__restrict__ val,
                                               const uint16_t *__restrict__ slot,
                                               const XT *__restrict__ xsrc, XT *__restrict__ w,
-                                              XT *prod, XT *wbuf) {
+                                              XT *prod, XT *wbuf,
+                                              const XT *__restrict__ vsrc = nullptr) {
     constexpr int U = CAP / kBlock;
     constexpr int R = kMaxRows / kBlock;
     const int tid = threadIdx.x;
@@ -208,7 +209,8 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
             const int32_t lim = (k1 - base) < CAP ? (k1 - base) : CAP;
             for (int32_t q = tid; q < lim; q += kBlock) {
                 const int32_t k = base + q;
-                prod[q] = (XT)load_val(val, k) * xsrc[cbase + (int32_t)__builtin_nontemporal_load(col + k)];
+                const int32_t c = cbase + (int32_t)__builtin_nontemporal_load(col + k);
+                prod[q] = (XT)load_val(val, k) * (DIRECT ? (c < 0 ? vsrc : xsrc)[c & 0x7fffffff] : xsrc[c]);
             }
             __syncthreads();
             if (tid == 0)
@@ -254,8 +256,14 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
     XT x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const bool inwin = W > 0 && (uint32_t)(c[u] - win.x) < (uint32_t)win.y;
-        x[u] = xsrc[inwin ? win.x : c[u]];
+        if (DIRECT) {
+            // direct reads: negative codes are columns of v, others positions
+            // in the received buffer
+            x[u] = (c[u] < 0 ? vsrc : xsrc)[c[u] & 0x7fffffff];
+        } else {
+            const bool inwin = W > 0 && (uint32_t)(c[u] - win.x) < (uint32_t)win.y;
+            x[u] = xsrc[inwin ? win.x : c[u]];
+        }
     }
     if (W > 0) {
 #pragma unroll
@@ -312,7 +320,8 @@ struct RemoteView {
     const int32_t *rowblk, *blkptr, *rowptr, *col;
     const VT *val;
     const uint16_t *slot;      // stored position of each entry inside its block
-    const XT *ghost;
+    const XT *ghost;           // ghost buffer, or the received buffer (direct reads)
+    const XT *v;               // direct reads only (else null): source of on-node values
     XT *w;
 };
 
@@ -347,9 +356,15 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
 
 template <typename VT, typename XT, int CAP>
 __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
-    product_block<VT, XT, int32_t, CAP, 0, true>(R.rowblk[b], R.rowblk[b + 1], R.blkptr[b],
-                                                 R.blkptr[b + 1], make_int2(0, 0), R.rowptr, R.col,
-                                                 0, R.val, R.slot, R.ghost, R.w, prod, nullptr);
+    if (R.v)
+        product_block<VT, XT, int32_t, CAP, 0, true, true>(
+            R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], make_int2(0, 0), R.rowptr,
+            R.col, 0, R.val, R.slot, R.ghost, R.w, prod, nullptr, R.v);
+    else
+        product_block<VT, XT, int32_t, CAP, 0, true>(R.rowblk[b], R.rowblk[b + 1], R.blkptr[b],
+                                                     R.blkptr[b + 1], make_int2(0, 0), R.rowptr,
+                                                     R.col, 0, R.val, R.slot, R.ghost, R.w, prod,
+                                                     nullptr);
 }
 
 // Index of the entry of prefix[0..count] (ascending, prefix[0] = 0) whose

@@ -67,6 +67,7 @@ struct napspmv_plan_s {
     // source of every ghost position for the NAP scatter.
     int layout_cap = 0;
     std::vector<int32_t> gpos;
+    std::vector<int32_t> dmap;           // direct reads: source code of every ghost
     std::vector<int64_t> gband, sband;   // band boundaries of the ghost / send buffers
     uint16_t *d_off = nullptr;
     uint32_t *d_code = nullptr;
@@ -159,7 +160,7 @@ WsLayout ws_layout(const napspmv_plan_s *p) {
     const bool nap = p->hp.mode == NAPSPMV_NAP;
     const bool copy = nap && (p->flags & NAPSPMV_EXCHANGE_COPY);
     WsLayout l;
-    l.send = align_up(p->G * vb);
+    l.send = p->hp.direct ? 0 : align_up(p->G * vb);     // direct reads fill no ghost buffer
     l.total = l.send + (nap ? align_up(p->E * vb) : 0);
     l.recv = copy ? l.total : l.send;
     if (copy) l.total += align_up(p->E * vb);
@@ -426,6 +427,13 @@ void build_layout(napspmv_plan_s *p, int cap) {
             code[gpos[hp.l2_dst[k]]] = napspmv::kFromV | (uint32_t)(hp.l2_src[k] % cap);
         if (E) HIP_OK(hipMemcpy(p->d_off, off.data(), E * 2, hipMemcpyHostToDevice));
         if (G) HIP_OK(hipMemcpy(p->d_code, code.data(), G * 4, hipMemcpyHostToDevice));
+        if (hp.direct) {
+            // off-node ghosts read the received buffer, on-node ones v (sign bit)
+            p->dmap.assign(G, 0);
+            for (int64_t h = 0; h < p->H; ++h) p->dmap[hp.scat_dst[h]] = spos[hp.scat_src[h]];
+            for (int64_t k = 0; k < p->Gon; ++k)
+                p->dmap[hp.l2_dst[k]] = (int32_t)(napspmv::kFromV | (uint32_t)hp.l2_src[k]);
+        }
         if (hp.three_way && p->Gon > 0) {
             std::vector<int32_t> l2pos(p->Gon);
             for (int64_t k = 0; k < p->Gon; ++k) l2pos[k] = gpos[hp.l2_dst[k]];
@@ -480,8 +488,8 @@ void refresh_schedules(napspmv_plan_s *p) {
         // off-process blocks follows the layout and the block cuts
         HIP_OK(hipDeviceSynchronize());
         if (relayout) build_layout(p, cap);
-        sort_upload(hp.col_off, p->gpos, hp.val_off, (int)hp.value_size, offptr, rcap,
-                    p->d_col_off, p->d_val_off, p->d_slot_off);
+        sort_upload(hp.col_off, hp.direct ? p->dmap : p->gpos, hp.val_off, (int)hp.value_size,
+                    offptr, rcap, p->d_col_off, p->d_val_off, p->d_slot_off);
         if (hp.three_way)
             sort_upload(hp.col_nd, p->gpos, hp.val_nd, (int)hp.value_size, ndptr, rcap,
                         p->d_col_nd, p->d_val_nd, p->d_slot_nd);
@@ -618,7 +626,8 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
 // block instead of the (off_node) off-process block.
 template <typename VT, typename XT>
 napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules &s, const Ws &ws,
-                                        XT *w, int64_t blk0, int64_t n_blk, bool on_node = false) {
+                                        const XT *v, XT *w, int64_t blk0, int64_t n_blk,
+                                        bool on_node = false) {
     napspmv::RemoteView<VT, XT> R;
     R.n_blocks = (int32_t)n_blk;
     R.rowblk = (on_node ? s.ndblk : s.offblk) + blk0;
@@ -627,7 +636,8 @@ napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules
     R.col = on_node ? p->d_col_nd : p->d_col_off;
     R.val = static_cast<const VT *>(on_node ? p->d_val_nd : p->d_val_off);
     R.slot = on_node ? p->d_slot_nd : p->d_slot_off;
-    R.ghost = static_cast<const XT *>(ws.ghost);
+    R.ghost = static_cast<const XT *>(p->hp.direct ? ws.recv : ws.ghost);
+    R.v = p->hp.direct ? v : nullptr;
     R.w = w;
     return R;
 }
@@ -709,10 +719,10 @@ void launch_three_way(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws
         napspmv::k_put<XT><<<blocks_for(p->Gon), napspmv::kBlock, 0, s>>>(
             (int32_t)p->Gon, p->d_l2pos, p->d_l2col, v, static_cast<XT *>(ws.ghost));
     if (sc.n_nd > 0 && p->hp.nnz_nd > 0)
-        launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_nd, true), s);
+        launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, v, w, 0, sc.n_nd, true), s);
     HIP_OK(hipStreamWaitEvent(s, p->ev_join, 0));
     if (p->hp.nnz_off - p->hp.nnz_nd > 0 && sc.n_off > 0)
-        launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, w, 0, sc.n_off), s);
+        launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, v, w, 0, sc.n_off), s);
 }
 
 template <typename VT, typename XT, int CAP>
@@ -727,8 +737,18 @@ void launch_cap(const napspmv_plan_s *p, const Schedules &sc, const Ws &ws, int 
         launch_three_way<VT, XT, CAP>(p, sc, ws, v, w, s);
         return;
     }
-    if (p->hp.mode == NAPSPMV_NAP) launch_scatter<XT, CAP>(p, sc, ws, v, s, 0);
-    if (p->hp.nnz_off > 0 && n_blk > 0) launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, w, blk0, n_blk), s);
+    if (p->hp.mode == NAPSPMV_NAP) {
+        if (p->hp.direct) {
+            // direct reads: only the explicit hop, if any; no ghost scatter
+            if (p->E > 0 && ws.recv != ws.send)
+                napspmv::k_copy<XT><<<blocks_for(p->E), napspmv::kBlock, 0, s>>>(
+                    (int32_t)p->E, static_cast<const XT *>(ws.send), static_cast<XT *>(ws.recv));
+        } else {
+            launch_scatter<XT, CAP>(p, sc, ws, v, s, 0);
+        }
+    }
+    if (p->hp.nnz_off > 0 && n_blk > 0)
+        launch_remote<VT, XT>(p, remote_view<VT, XT>(p, sc, ws, v, w, blk0, n_blk), s);
 }
 
 template <typename VT, typename XT>
@@ -868,12 +888,13 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
         lv[i] = local_view<VT, XT>(p, p->sched, wp, static_cast<const XT *>(v[i]),
                                    static_cast<XT *>(w[i]), 0, p->sched.n_tasks);
         sv[i] = scatter_view<XT>(p, p->sched, wp, static_cast<const XT *>(v[i]), 0);
-        rv[i] = remote_view<VT, XT>(p, p->sched, wp, static_cast<XT *>(w[i]), 0,
+        rv[i] = remote_view<VT, XT>(p, p->sched, wp, static_cast<const XT *>(v[i]),
+                                    static_cast<XT *>(w[i]), 0,
                                     p->hp.nnz_off > 0 ? p->sched.n_off : 0);
         const bool nap = p->hp.mode == NAPSPMV_NAP;
         any_nap = any_nap || nap;
         pl[i + 1] = pl[i] + lv[i].n_tasks;
-        ps[i + 1] = ps[i] + (nap ? (int32_t)p->sched.n_sitems : 0);
+        ps[i + 1] = ps[i] + (nap && !p->hp.direct ? (int32_t)p->sched.n_sitems : 0);
         pr[i + 1] = pr[i] + rv[i].n_blocks;
     }
     HIP_OK(hipMemcpyAsync(d, h, t.total, hipMemcpyHostToDevice, s));
@@ -933,7 +954,8 @@ std::string tune_key(const napspmv_plan_s *p) {
     std::ostringstream k;
     k << dev << ";n=" << p->hp.n << ";nnz=" << p->hp.nnz << ";np=" << p->hp.n_p << ";ppn="
       << p->hp.ppn << ";mode=" << p->hp.mode << ";dtype=" << p->hp.dtype << ";G=" << p->G
-      << ";on=" << p->hp.nnz_on << ";three_way=" << (p->hp.three_way ? 1 : 0) << ";v=2";
+      << ";on=" << p->hp.nnz_on << ";three_way=" << (p->hp.three_way ? 1 : 0)
+      << ";direct=" << (p->hp.direct ? 1 : 0) << ";v=2";
     std::string s = k.str();
     std::replace(s.begin(), s.end(), ' ', '_');
     return s;
@@ -985,7 +1007,7 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
     *plan_out = nullptr;
     if (flags & ~(NAPSPMV_HOST_ONLY | NAPSPMV_EXCHANGE_COPY | NAPSPMV_NAP_OWNER_MAP |
                   NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY |
-                  NAPSPMV_PARTITION_STRIDED))
+                  NAPSPMV_NAP_DIRECT | NAPSPMV_PARTITION_STRIDED))
         return fail(NAPSPMV_EINVAL, "unknown flag bits");
     napspmv_plan_s *p = nullptr;
     const int rc = guarded([&]() {
@@ -994,7 +1016,7 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         const auto t0 = std::chrono::steady_clock::now();
         napspmv::build_plan(p->hp, rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts,
                             flags & (NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP |
-                                     NAPSPMV_NAP_THREE_WAY),
+                                     NAPSPMV_NAP_THREE_WAY | NAPSPMV_NAP_DIRECT),
                             (flags & NAPSPMV_PARTITION_STRIDED) != 0);
         const auto t1 = std::chrono::steady_clock::now();
         p->build_s = std::chrono::duration<double>(t1 - t0).count();
@@ -1344,6 +1366,8 @@ int napspmv_plan_ghosts(napspmv_plan_t plan, int64_t *ghost_ptr, int32_t *ghost_
 int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *ws, void *out, void *stream) {
     if (!plan || !out) return fail(NAPSPMV_EINVAL, "plan or out is NULL");
     if (!plan->on_device) return fail(NAPSPMV_EINVAL, "plan was built with NAPSPMV_HOST_ONLY");
+    if (plan->hp.direct)
+        return fail(NAPSPMV_EUNSUPPORTED, "a direct-read plan fills no ghost buffer");
     return guarded([&]() {
         DeviceGuard g(plan->device);
         HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));

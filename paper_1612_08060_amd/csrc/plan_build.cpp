@@ -48,7 +48,8 @@ namespace {
 constexpr int64_t kInt32Max = 0x7fffffff - 0x10000;
 
 constexpr uint32_t kVariantFlags =
-    NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY;
+    NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY |
+    NAPSPMV_NAP_DIRECT;
 
 struct Owner {
     const std::vector<int64_t> &starts;
@@ -203,6 +204,9 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
     if (variant & ~kVariantFlags) throw Error(NAPSPMV_EINVAL, "unknown plan variant flag");
     if (variant && mode != NAPSPMV_NAP)
         throw Error(NAPSPMV_EINVAL, "plan variant flags apply to NAP plans only");
+    if ((variant & NAPSPMV_NAP_DIRECT) && (variant & NAPSPMV_NAP_THREE_WAY))
+        throw Error(NAPSPMV_EINVAL, "direct reads and the three-way product do not combine");
+    hp.direct = (variant & NAPSPMV_NAP_DIRECT) != 0;
     if (strided) {
         if (row_starts) throw Error(NAPSPMV_EINVAL, "a strided partition takes no row_starts");
         if (variant & NAPSPMV_NAP_SPLIT)

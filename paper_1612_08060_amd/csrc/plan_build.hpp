@@ -59,6 +59,7 @@ struct HostPlan {
     // rowptr_off/col_off/val_off, which then hold the off_node part.
     // nnz_off still counts both parts.
     bool three_way = false;
+    bool direct = false;       // NAP direct reads (no ghost buffer on the device)
     std::vector<int32_t> rowptr_nd, col_nd;      // n + 1, nnz_nd
     std::vector<uint8_t> val_nd;                 // nnz_nd * value_size
     int64_t nnz_nd = 0;

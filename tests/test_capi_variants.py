@@ -1,7 +1,9 @@
-"""NAP plan variants (NAPSPMV_NAP_OWNER_MAP / SPLIT / DEDUP) in the C-ABI
-host builder: every phase, every statistic and the ghost lists equal the
-oracle's bit for bit, on random patterns, paper-shaped matrices and the
-worked example."""
+"""NAP plan variants (NAPSPMV_NAP_OWNER_MAP / SPLIT / DEDUP / THREE_WAY /
+DIRECT) in the C-ABI host builder: every phase, every statistic and the
+ghost lists equal the oracle's bit for bit, on random patterns,
+paper-shaped matrices and the worked example.  Direct reads change only how
+the device reads ghosts, so their messages are those of the same plan
+without them."""
 import numpy as np
 import pytest
 
@@ -11,12 +13,14 @@ from tests.helpers import example_2_1
 from workloads import config, random_pattern
 
 VARIANTS = [("owner_map",), ("split",), ("dedup",), ("owner_map", "split"),
-            ("owner_map", "split", "dedup"), ("three_way",), ("split", "three_way")]
-FLAGS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20}
+            ("owner_map", "split", "dedup"), ("three_way",), ("split", "three_way"),
+            ("direct",), ("dedup", "direct"), ("owner_map", "split", "dedup", "direct")]
+FLAGS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20, "direct": 0x80}
 
 
 def _compare(a, n_p, ppn, variant, row_starts=None):
-    ref = plan_vec.plan(a, n_p, ppn, "nap", row_starts, variant)
+    ref = plan_vec.plan(a, n_p, ppn, "nap", row_starts,
+                        tuple(x for x in variant if x != "direct"))
     with lib.Plan(a.rowptr, a.col, a.val, a.n, n_p, ppn, mode="nap", row_starts=row_starts,
                   host_only=True, variant=variant) as p:
         assert p.variant == tuple(sorted(variant))
@@ -86,3 +90,12 @@ def test_variant_flags_rejected_for_standard_and_unknown():
     with pytest.raises(ValueError):
         lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, mode="nap", host_only=True,
                  variant=("nope",))
+
+
+def test_direct_rejected_with_three_way_and_standard():
+    a = random_pattern(20, 0.2, seed=4)
+    for mode, variant in (("nap", ("direct", "three_way")), ("standard", ("direct",))):
+        with pytest.raises(lib.NapspmvError) as e:
+            lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, mode=mode, host_only=True,
+                     variant=variant)
+        assert e.value.code == -1
