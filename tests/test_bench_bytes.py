@@ -46,3 +46,6 @@ def test_nap_exchange_terms():
     h = st["ghosts"] - g_on
     assert bench.exchange_bytes(st, 8) == e * 20 + h * 24 + g_on * 24
     assert bench.exchange_bytes(st, 8, exchange_copy=True) == e * 20 + h * 24 + g_on * 24 + 16 * e
+    # direct reads: the pack alone (index, read of v, write per sent value)
+    assert bench.exchange_bytes(st, 8, direct=True) == e * 20
+    assert bench.exchange_bytes(st, 8, exchange_copy=True, direct=True) == e * 36
