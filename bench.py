@@ -79,11 +79,12 @@ def rows_with_off_entries(a, n_p, row_starts):
 
 
 def source_hash() -> str:
-    """Hash of the kernel sources with comments and blank lines removed, so a
-    recorded counter summary stays valid across comment-only edits."""
+    """Hash of the kernel and launch-schedule sources with comments and blank
+    lines removed, so a recorded counter summary stays valid across
+    comment-only edits."""
     import re
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "napspmv.hip"):
+    for f in ("kernels.hpp", "napspmv.hip", "schedule.hpp", "schedule.cpp"):
         with open(os.path.join(ROOT, "paper_1612_08060_amd", "csrc", f)) as fh:
             for line in fh:
                 code = re.sub(r"//.*", "", line).rstrip()

@@ -291,6 +291,7 @@ int cur_rcap(const napspmv_plan_s *p) {
     return p->remote_nnz >= 0 ? p->remote_nnz : p->auto_remote_nnz;
 }
 bool valid_block(int v) { return v == 1024 || v == 2048 || v == 4096 || v == 8192; }
+bool valid_rblock(int v) { return valid_block(v) || v == 5120 || v == 6144; }
 int cur_win(const napspmv_plan_s *p) { return p->window >= 0 ? p->window : p->auto_window; }
 int cur_item(const napspmv_plan_s *p) { return p->item >= 0 ? p->item : p->auto_item; }
 
@@ -700,6 +701,8 @@ void launch_remote(const napspmv_plan_s *p, const napspmv::RemoteView<VT, XT> &R
         case 1024: k_remote<VT, XT, 1024><<<nb, kBlock, 0, s>>>(R); break;
         case 2048: k_remote<VT, XT, 2048><<<nb, kBlock, 0, s>>>(R); break;
         case 4096: k_remote<VT, XT, 4096><<<nb, kBlock, 0, s>>>(R); break;
+        case 5120: k_remote<VT, XT, 5120><<<nb, kBlock, 0, s>>>(R); break;
+        case 6144: k_remote<VT, XT, 6144><<<nb, kBlock, 0, s>>>(R); break;
         default: k_remote<VT, XT, 8192><<<nb, kBlock, 0, s>>>(R); break;
     }
 }
@@ -914,6 +917,8 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
             case 1024: k_remote_batch<VT, XT, 1024><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
             case 2048: k_remote_batch<VT, XT, 2048><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
             case 4096: k_remote_batch<VT, XT, 4096><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
+            case 5120: k_remote_batch<VT, XT, 5120><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
+            case 6144: k_remote_batch<VT, XT, 6144><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
             default: k_remote_batch<VT, XT, 8192><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
         }
     }
@@ -991,7 +996,7 @@ void cache_store(const char *path, const std::string &key, const int v[4], doubl
 }
 
 bool valid_cfg(const int c[4]) {
-    return valid_block(c[0]) && valid_block(c[3]) &&
+    return valid_block(c[0]) && valid_rblock(c[3]) &&
            (c[1] == 0 || c[1] == 1024 || c[1] == 2048 || c[1] == 4096) && c[2] >= kMinItem &&
            c[2] <= kMaxItem;
 }
@@ -1394,8 +1399,9 @@ int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value) {
             plan->block_nnz = value;
             break;
         case NAPSPMV_PARAM_REMOTE_NNZ:
-            if (value != -1 && !valid_block(value))
-                return fail(NAPSPMV_EINVAL, "remote block entries must be -1, 1024, 2048, 4096 or 8192");
+            if (value != -1 && !valid_rblock(value))
+                return fail(NAPSPMV_EINVAL,
+                            "remote block entries must be -1, 1024, 2048, 4096, 5120, 6144 or 8192");
             plan->remote_nnz = value;
             break;
         case NAPSPMV_PARAM_GATHER_ITEM:

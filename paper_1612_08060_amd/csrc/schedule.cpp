@@ -106,13 +106,27 @@ void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int
 void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks) {
     tasks.clear();
     tasks.reserve((size_t)(n_items + n_blocks));
-    int64_t i = 0, b = 0;
-    while (i < n_items || b < n_blocks) {
-        // take an item while items are behind their share of the sequence
-        if (b >= n_blocks || (i < n_items && i * n_blocks <= b * n_items))
-            tasks.push_back(~(int32_t)i++);
-        else
-            tasks.push_back((int32_t)b++);
+    // the launch's XCD ranges (see xcd_block): 8 contiguous stretches of the
+    // task list, each dispatched in order on one XCD
+    const int64_t n = n_items + n_blocks, q = n / 8, r = n % 8;
+    int64_t i = 0, b = 0, start = 0;
+    for (int64_t x = 0; x < 8 && n > 0; ++x) {
+        const int64_t len = q + (x < r ? 1 : 0);
+        const int64_t ni = n_items * (start + len) / n - i;     // this range's share of items
+        // items go in proportion over the range but the last kItemTail
+        // tasks, so that no item (several times a row block's bytes) is
+        // left running alone at the end of the launch
+        const int64_t span = std::max(ni, len - kItemTail), sb = span - ni;
+        int64_t il = 0, bl = 0;
+        for (int64_t s = 0; s < len; ++s) {
+            if (il < ni && (bl >= sb || il * sb <= bl * ni))
+                tasks.push_back(~(int32_t)(i + il++));
+            else
+                tasks.push_back((int32_t)(b + bl++));
+        }
+        i += ni;
+        b += bl;
+        start += len;
     }
 }
 

@@ -38,9 +38,12 @@ void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int
                        std::vector<int32_t> &win);
 
 // Launch order of the first apply launch: exchange items (encoded ~i) and
-// local row blocks (encoded b >= 0) interleaved in proportion, each list
-// kept in its own order, so that any contiguous stretch of the launch (an
-// XCD's share) holds a proportional slice of both.
+// local row blocks (encoded b >= 0), each list kept in its own order.  Each
+// XCD's contiguous share of the launch gets its proportional slice of both,
+// interleaved, except that its last kItemTail tasks are row blocks only: an
+// XCD holds about 128 of these blocks at once (32 CUs, 4 each), and an
+// item still running in the final rounds would leave the rest idle.
+constexpr int64_t kItemTail = 512;
 void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks);
 
 // Work items covering [0, total) in order, pieces of at most `max_len`.

@@ -1,0 +1,115 @@
+// Host checks of the launch schedules (paper_1612_08060_amd/csrc/schedule.cpp):
+// every task, row block and sorted entry is accounted for exactly once, and
+// each schedule keeps the properties the kernels rely on.  Prints "ok" and
+// returns 0, or prints the first failure and returns 1.
+#include "schedule.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <vector>
+
+static int fail(const char *what, long long a, long long b) {
+    std::printf("FAIL %s (%lld, %lld)\n", what, a, b);
+    return 1;
+}
+
+static int check_merge() {
+    for (int64_t ni = 0; ni < 400; ni += 13)
+        for (int64_t nb = 0; nb < 6000; nb += 41) {
+            std::vector<int32_t> t;
+            napspmv::merge_tasks(ni, nb, t);
+            if ((int64_t)t.size() != ni + nb) return fail("merge size", ni, nb);
+            int64_t ei = 0, eb = 0;
+            for (int32_t x : t) {
+                if (x < 0) {
+                    if (~x != ei++) return fail("item order", ni, nb);
+                } else if (x != eb++) {
+                    return fail("block order", ni, nb);
+                }
+            }
+            if (ei != ni || eb != nb) return fail("merge counts", ni, nb);
+            // the XCD ranges of the launch (xcd_block): proportional shares,
+            // and no item in a range's last kItemTail tasks unless the items
+            // do not fit before them (then they lead the range)
+            const int64_t n = ni + nb, q = n / 8, r = n % 8;
+            int64_t start = 0, seen = 0;
+            for (int64_t x = 0; x < 8; ++x) {
+                const int64_t len = q + (x < r ? 1 : 0);
+                const int64_t share = (n ? ni * (start + len) / n : 0) - seen;
+                int64_t cnt = 0, last = -1;
+                for (int64_t s = 0; s < len; ++s)
+                    if (t[start + s] < 0) { ++cnt; last = s; }
+                if (cnt != share) return fail("range share", x, cnt);
+                const int64_t limit = std::max(share, len - napspmv::kItemTail);
+                if (last >= limit) return fail("item in the tail", x, last);
+                seen += cnt;
+                start += len;
+            }
+        }
+    return 0;
+}
+
+static int check_blocks_and_sort() {
+    std::mt19937 rng(7);
+    for (int trial = 0; trial < 60; ++trial) {
+        const int n_p = 1 + trial % 9, n = n_p * (5 + trial * 3 % 40);
+        std::vector<int32_t> rowptr(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            // mostly short rows, a few longer than any block
+            const int len = (rng() % 17 == 0) ? 300 + rng() % 200 : rng() % 30;
+            rowptr[i + 1] = rowptr[i] + len;
+        }
+        std::vector<int64_t> starts(n_p + 1);
+        for (int t = 0; t <= n_p; ++t) starts[t] = (int64_t)n * t / n_p;
+        for (int cap : {64, 256}) {
+            const int max_rows = 8;
+            std::vector<int32_t> rb, bp;
+            napspmv::row_blocks_per_process(rowptr.data(), starts, cap, max_rows, rb, bp);
+            if (rb.front() != 0 || rb.back() != n) return fail("blocks cover", trial, cap);
+            for (size_t b = 0; b + 1 < rb.size(); ++b) {
+                const int32_t r0 = rb[b], r1 = rb[b + 1];
+                if (r1 <= r0) return fail("empty block", trial, (long long)b);
+                if (bp[b] != rowptr[r0]) return fail("block pointer", trial, (long long)b);
+                const int64_t t = std::upper_bound(starts.begin(), starts.end(), r0) - starts.begin() - 1;
+                if (r1 > starts[t + 1]) return fail("block spans processes", trial, (long long)b);
+                const bool single = r1 - r0 == 1;
+                if (!single && (rowptr[r1] - rowptr[r0] > cap || r1 - r0 > max_rows))
+                    return fail("block too large", trial, (long long)b);
+            }
+            // sort inside blocks by column; slots give the stored positions
+            const int nnz = rowptr[n];
+            std::vector<int32_t> col(nnz), col_out(nnz);
+            std::vector<double> val(nnz), val_out(nnz);
+            std::vector<uint16_t> slot(nnz);
+            for (int k = 0; k < nnz; ++k) { col[k] = (int32_t)(rng() % 1000); val[k] = k + 0.5; }
+            napspmv::sort_blocks(bp, cap, col.data(), reinterpret_cast<const uint8_t *>(val.data()),
+                                 8, col_out.data(), reinterpret_cast<uint8_t *>(val_out.data()),
+                                 slot.data());
+            for (size_t b = 0; b + 1 < bp.size(); ++b) {
+                const int32_t k0 = bp[b], len = bp[b + 1] - k0;
+                std::vector<char> hit(len, 0);
+                for (int32_t q = 0; q < len; ++q) {
+                    if (len <= cap) {
+                        if (q && col_out[k0 + q] < col_out[k0 + q - 1]) return fail("not sorted", trial, q);
+                        const int32_t from = slot[k0 + q];
+                        if (from >= len || hit[from]++) return fail("slot permutation", trial, q);
+                        if (col_out[k0 + q] != col[k0 + from] || val_out[k0 + q] != val[k0 + from])
+                            return fail("slot target", trial, q);
+                    } else if (slot[k0 + q] != 0 || col_out[k0 + q] != col[k0 + q] ||
+                               val_out[k0 + q] != val[k0 + q]) {
+                        return fail("long block moved", trial, q);
+                    }
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+int main() {
+    if (check_merge() || check_blocks_and_sort()) return 1;
+    std::printf("ok\n");
+    return 0;
+}
