@@ -250,8 +250,9 @@ NAPSPMV_API int napspmv_apply_ws(napspmv_plan_t plan, void *ws, const void *v, v
  * plans[i], different matrices or the same one with different workspaces)
  * in one launch sequence -- one first launch over every product's exchange
  * and on-process work, one NAP scatter launch if any plan is NAP, one second
- * launch over every off-process product.  All plans must share the value
- * type, BLOCK_NNZ, VWINDOW and REMOTE_NNZ, be on the batch's device, receive
+ * launch over every off-process product (one per REMOTE_NNZ among the
+ * plans).  All plans must share the value type, BLOCK_NNZ and VWINDOW (else
+ * EINVAL), be on the batch's device, receive
  * NAP messages in place and use the two-part product (no NAPSPMV_NAP_THREE_WAY).  ws may be NULL (every plan's own workspace) or hold
  * per-product workspaces (NULL entries = the plan's own).  The batch object
  * owns a device descriptor table (and a pinned host copy) for up to
@@ -299,7 +300,7 @@ NAPSPMV_API int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *
  * their workspace fits in `workspace_budget` bytes (0 = no cap; idle
  * workspaces of other plans are released to make room), and each free slot
  * then runs up to `max_batch` queued requests of one kernel group (value
- * type, BLOCK_NNZ, VWINDOW, REMOTE_NNZ; oldest request first) as one batched launch
+ * type, BLOCK_NNZ, VWINDOW; oldest request first) as one batched launch
  * sequence (a NAP plan with NAPSPMV_EXCHANGE_COPY or NAPSPMV_NAP_THREE_WAY
  * always runs alone, by napspmv_apply_ws).  Requests that arrive while slots are busy are admitted as slots
  * free up, so their work overlaps the work already on the device.
@@ -363,7 +364,8 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
  *                 columns of v per band of the exchange buffers: 1024, 2048,
  *                 4096, 8192 (automatic: 4096)
  *   REMOTE_NNZ    entries per row block of the off-process product: 1024,
- *                 2048, 4096, 8192 (automatic: 8192)
+ *                 2048, 4096, 8192 (automatic: 8192 when the plan has at
+ *                 least 8192 off-process entries per process, else 4096)
  *   GATHER_ITEM   most entries of one exchange work item (a slice of one
  *                 band of the ghost or send buffer), 256 .. 2^24
  *                 (automatic: 65536)

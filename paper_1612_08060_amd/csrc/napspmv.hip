@@ -291,7 +291,9 @@ int cur_rcap(const napspmv_plan_s *p) {
     return p->remote_nnz >= 0 ? p->remote_nnz : p->auto_remote_nnz;
 }
 bool valid_block(int v) { return v == 1024 || v == 2048 || v == 4096 || v == 8192; }
-bool valid_rblock(int v) { return valid_block(v) || v == 5120 || v == 6144; }
+// remote block sizes, in the order of the batched launch's groups
+constexpr int kRemoteSizes = 4;
+int remote_size_index(int rcap) { return rcap == 1024 ? 0 : rcap == 2048 ? 1 : rcap == 4096 ? 2 : 3; }
 int cur_win(const napspmv_plan_s *p) { return p->window >= 0 ? p->window : p->auto_window; }
 int cur_item(const napspmv_plan_s *p) { return p->item >= 0 ? p->item : p->auto_item; }
 
@@ -701,8 +703,6 @@ void launch_remote(const napspmv_plan_s *p, const napspmv::RemoteView<VT, XT> &R
         case 1024: k_remote<VT, XT, 1024><<<nb, kBlock, 0, s>>>(R); break;
         case 2048: k_remote<VT, XT, 2048><<<nb, kBlock, 0, s>>>(R); break;
         case 4096: k_remote<VT, XT, 4096><<<nb, kBlock, 0, s>>>(R); break;
-        case 5120: k_remote<VT, XT, 5120><<<nb, kBlock, 0, s>>>(R); break;
-        case 6144: k_remote<VT, XT, 6144><<<nb, kBlock, 0, s>>>(R); break;
         default: k_remote<VT, XT, 8192><<<nb, kBlock, 0, s>>>(R); break;
     }
 }
@@ -856,7 +856,8 @@ BatchTable batch_table(int count) {
     };
     t.pre_local = take(sizeof(int32_t) * (count + 1));
     t.pre_scatter = take(sizeof(int32_t) * (count + 1));
-    t.pre_remote = take(sizeof(int32_t) * (count + 1));
+    // the remote views are grouped by block size, one prefix list per group
+    t.pre_remote = take(sizeof(int32_t) * (count + kRemoteSizes));
     t.local = take(sizeof(napspmv::LocalView<VT, XT>) * count);
     t.scatter = take(sizeof(napspmv::ScatterView<XT>) * count);
     t.remote = take(sizeof(napspmv::RemoteView<VT, XT>) * count);
@@ -880,10 +881,20 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
     int32_t *pl = reinterpret_cast<int32_t *>(h + t.pre_local);
     int32_t *ps = reinterpret_cast<int32_t *>(h + t.pre_scatter);
     int32_t *pr = reinterpret_cast<int32_t *>(h + t.pre_remote);
+    // remote views grouped by block size: group g holds views [g0[g], g0[g+1])
+    // and its prefix list starts at pr[g0[g] + g]
+    int g0[kRemoteSizes + 1] = {0};
+    for (int i = 0; i < count; ++i) ++g0[remote_size_index(plans[i]->cur_remote_nnz) + 1];
+    for (int g = 0; g < kRemoteSizes; ++g) g0[g + 1] += g0[g];
+    int fill[kRemoteSizes];
+    for (int g = 0; g < kRemoteSizes; ++g) {
+        fill[g] = g0[g];
+        pr[g0[g] + g] = 0;
+    }
     auto *lv = reinterpret_cast<LocalView<VT, XT> *>(h + t.local);
     auto *sv = reinterpret_cast<ScatterView<XT> *>(h + t.scatter);
     auto *rv = reinterpret_cast<RemoteView<VT, XT> *>(h + t.remote);
-    pl[0] = ps[0] = pr[0] = 0;
+    pl[0] = ps[0] = 0;
     bool any_nap = false;
     for (int i = 0; i < count; ++i) {
         const napspmv_plan_s *p = plans[i];
@@ -891,14 +902,15 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
         lv[i] = local_view<VT, XT>(p, p->sched, wp, static_cast<const XT *>(v[i]),
                                    static_cast<XT *>(w[i]), 0, p->sched.n_tasks);
         sv[i] = scatter_view<XT>(p, p->sched, wp, static_cast<const XT *>(v[i]), 0);
-        rv[i] = remote_view<VT, XT>(p, p->sched, wp, static_cast<const XT *>(v[i]),
+        const int g = remote_size_index(p->cur_remote_nnz), j = fill[g]++;
+        rv[j] = remote_view<VT, XT>(p, p->sched, wp, static_cast<const XT *>(v[i]),
                                     static_cast<XT *>(w[i]), 0,
                                     p->hp.nnz_off > 0 ? p->sched.n_off : 0);
+        pr[j + g + 1] = pr[j + g] + rv[j].n_blocks;
         const bool nap = p->hp.mode == NAPSPMV_NAP;
         any_nap = any_nap || nap;
         pl[i + 1] = pl[i] + lv[i].n_tasks;
         ps[i + 1] = ps[i] + (nap && !p->hp.direct ? (int32_t)p->sched.n_sitems : 0);
-        pr[i + 1] = pr[i] + rv[i].n_blocks;
     }
     HIP_OK(hipMemcpyAsync(d, h, t.total, hipMemcpyHostToDevice, s));
     if (pl[count] > 0)
@@ -909,17 +921,17 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
         k_scatter_batch<XT, CAP><<<(uint32_t)ps[count], kBlock, 0, s>>>(
             reinterpret_cast<const ScatterView<XT> *>(d + t.scatter),
             reinterpret_cast<const int32_t *>(d + t.pre_scatter), count);
-    if (pr[count] > 0) {
-        const auto *rvd = reinterpret_cast<const RemoteView<VT, XT> *>(d + t.remote);
-        const auto *prd = reinterpret_cast<const int32_t *>(d + t.pre_remote);
-        const uint32_t nb = (uint32_t)pr[count];
-        switch (plans[0]->cur_remote_nnz) {
-            case 1024: k_remote_batch<VT, XT, 1024><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
-            case 2048: k_remote_batch<VT, XT, 2048><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
-            case 4096: k_remote_batch<VT, XT, 4096><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
-            case 5120: k_remote_batch<VT, XT, 5120><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
-            case 6144: k_remote_batch<VT, XT, 6144><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
-            default: k_remote_batch<VT, XT, 8192><<<nb, kBlock, 0, s>>>(rvd, prd, count); break;
+    for (int g = 0; g < kRemoteSizes; ++g) {
+        const int n_g = g0[g + 1] - g0[g];
+        if (n_g == 0 || pr[g0[g + 1] + g] == 0) continue;
+        const auto *rvd = reinterpret_cast<const RemoteView<VT, XT> *>(d + t.remote) + g0[g];
+        const auto *prd = reinterpret_cast<const int32_t *>(d + t.pre_remote) + g0[g] + g;
+        const uint32_t nb = (uint32_t)pr[g0[g + 1] + g];
+        switch (g) {
+            case 0: k_remote_batch<VT, XT, 1024><<<nb, kBlock, 0, s>>>(rvd, prd, n_g); break;
+            case 1: k_remote_batch<VT, XT, 2048><<<nb, kBlock, 0, s>>>(rvd, prd, n_g); break;
+            case 2: k_remote_batch<VT, XT, 4096><<<nb, kBlock, 0, s>>>(rvd, prd, n_g); break;
+            default: k_remote_batch<VT, XT, 8192><<<nb, kBlock, 0, s>>>(rvd, prd, n_g); break;
         }
     }
     HIP_OK(hipGetLastError());
@@ -996,7 +1008,7 @@ void cache_store(const char *path, const std::string &key, const int v[4], doubl
 }
 
 bool valid_cfg(const int c[4]) {
-    return valid_block(c[0]) && valid_rblock(c[3]) &&
+    return valid_block(c[0]) && valid_block(c[3]) &&
            (c[1] == 0 || c[1] == 1024 || c[1] == 2048 || c[1] == 4096) && c[2] >= kMinItem &&
            c[2] <= kMaxItem;
 }
@@ -1029,6 +1041,10 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         p->E = (int64_t)p->hp.pack_idx.size();
         p->H = (int64_t)p->hp.scat_src.size();
         p->Gon = (int64_t)p->hp.l2_src.size();
+        // automatic off-process block size: the larger block lets a
+        // process's blocks share more ghost lines, but a process with fewer
+        // off-process entries than it holds would leave half of its LDS idle
+        p->auto_remote_nnz = p->hp.nnz_off >= (int64_t)8192 * p->hp.n_p ? 8192 : 4096;
         if (!(flags & NAPSPMV_HOST_ONLY)) {
             to_device(p);
             napspmv::release_device_arrays(p->hp);
@@ -1145,9 +1161,8 @@ int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *
         const napspmv_plan_s *p = plans[i];
         if (p->device != batch->device) return fail(NAPSPMV_EINVAL, "plans on different devices");
         if (p->hp.dtype != p0->hp.dtype || p->cur_block_nnz != p0->cur_block_nnz ||
-            p->cur_window != p0->cur_window || p->cur_remote_nnz != p0->cur_remote_nnz)
-            return fail(NAPSPMV_EINVAL,
-                        "a batch needs one value type, BLOCK_NNZ, VWINDOW and REMOTE_NNZ");
+            p->cur_window != p0->cur_window)
+            return fail(NAPSPMV_EINVAL, "a batch needs one value type, BLOCK_NNZ and VWINDOW");
         if (p->hp.mode == NAPSPMV_NAP && (p->flags & NAPSPMV_EXCHANGE_COPY))
             return fail(NAPSPMV_EUNSUPPORTED, "batched applies receive NAP messages in place");
         if (p->hp.three_way)
@@ -1399,9 +1414,8 @@ int napspmv_plan_set_param(napspmv_plan_t plan, int param, int value) {
             plan->block_nnz = value;
             break;
         case NAPSPMV_PARAM_REMOTE_NNZ:
-            if (value != -1 && !valid_rblock(value))
-                return fail(NAPSPMV_EINVAL,
-                            "remote block entries must be -1, 1024, 2048, 4096, 5120, 6144 or 8192");
+            if (value != -1 && !valid_block(value))
+                return fail(NAPSPMV_EINVAL, "remote block entries must be -1, 1024, 2048, 4096 or 8192");
             plan->remote_nnz = value;
             break;
         case NAPSPMV_PARAM_GATHER_ITEM:

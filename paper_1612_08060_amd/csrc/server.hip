@@ -53,7 +53,7 @@ struct ServerSlot {
 struct ServerPlan {
     napspmv_plan_t plan = nullptr;
     int64_t ws_bytes = 0;
-    int key_dtype = 0, key_cap = 0, key_win = 0, key_rcap = 0;
+    int key_dtype = 0, key_cap = 0, key_win = 0;
     bool solo = false;      // never batched (explicit exchange copy, three-way product)
     std::vector<void *> free_ws, all_ws;
 };
@@ -163,12 +163,12 @@ void admit(napspmv_server_s *s) {
         if (sl.busy) continue;
         if (s->queue.empty()) return;
         std::vector<int64_t> take;
-        int key[4] = {-1, -1, -1, -1};
+        int key[3] = {-1, -1, -1};
         for (auto it = s->queue.begin(); it != s->queue.end() && (int)take.size() < s->max_batch;) {
             ServerRequest &R = s->reqs[*it];
             const ServerPlan &P = s->plans[R.plan];
             if (key[0] >= 0 && (P.solo || P.key_dtype != key[0] || P.key_cap != key[1] ||
-                                P.key_win != key[2] || P.key_rcap != key[3])) {
+                                P.key_win != key[2])) {
                 ++it;
                 continue;
             }
@@ -181,7 +181,6 @@ void admit(napspmv_server_s *s) {
             key[0] = P.key_dtype;
             key[1] = P.key_cap;
             key[2] = P.key_win;
-            key[3] = P.key_rcap;
             take.push_back(*it);
             it = s->queue.erase(it);
             if (P.solo) break;
@@ -253,7 +252,6 @@ int napspmv_server_add_plan(napspmv_server_t s, napspmv_plan_t plan, int *id_out
     P.key_dtype = st.dtype;
     P.key_cap = napspmv_plan_get_param(plan, NAPSPMV_PARAM_BLOCK_NNZ);
     P.key_win = napspmv_plan_get_param(plan, NAPSPMV_PARAM_VWINDOW);
-    P.key_rcap = napspmv_plan_get_param(plan, NAPSPMV_PARAM_REMOTE_NNZ);
     P.solo = st.mode == NAPSPMV_NAP &&
              (st.flags & (NAPSPMV_EXCHANGE_COPY | NAPSPMV_NAP_THREE_WAY)) != 0;
     s->plans.push_back(P);

@@ -188,7 +188,12 @@ def test_tuning_parameters():
     a = kkt_like(1 << 10, 2)
     p = lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, host_only=True)
     assert p.get_param("block_nnz") == 4096 and p.get_param("window") == 1024
-    assert p.get_param("gather_item") == 65536 and p.get_param("remote_nnz") == 8192
+    # automatic off-process block: 4096 entries below 8192 off-process
+    # entries per process (this small matrix), 8192 from there on
+    assert p.get_param("gather_item") == 65536 and p.get_param("remote_nnz") == 4096
+    big = kkt_like(1 << 16, 3)
+    with lib.Plan(big.rowptr, big.col, big.val, big.n, 2, 2, host_only=True) as q:
+        assert q.stats["nnz_off"] >= 2 * 8192 and q.get_param("remote_nnz") == 8192
     p.set_param("remote_nnz", 2048)
     assert p.get_param("remote_nnz") == 2048
     p.set_param("block_nnz", 1024)

@@ -96,6 +96,31 @@ def test_batch_mixed_plans_equal_solo(dtype):
         p.close()
 
 
+def test_batch_mixed_remote_block_sizes():
+    """Plans with different off-process block sizes in one batch: one second
+    launch per size, every product equal to its solo apply bit for bit."""
+    a, b2 = kkt_like(1 << 13, 21), laplacian_3d(14, 14, 14)
+    plans = []
+    for rn, mode in ((1024, "standard"), (8192, "nap"), (2048, "standard"), (4096, "nap"),
+                     (8192, "standard"), (1024, "nap")):
+        p = _plan(a, 16, 4, mode=mode)
+        p.set_param("remote_nnz", rn)
+        plans.append(p)
+    plans.append(_plan(b2, 8, 4, mode="nap"))
+    vs = [_vec(vec_normal(p.n, 30 + k), "f64") for k, p in enumerate(plans)]
+    ref = [_solo(p, v) for p, v in zip(plans, vs)]
+    outs = [torch.full_like(v, float("nan")) for v in vs]
+    bt = nap.Batch(len(plans))
+    print("batch of mixed remote block sizes", flush=True)
+    bt.apply(plans, vs, outs)
+    torch.cuda.synchronize()
+    bt.close()
+    for k in range(len(plans)):
+        assert torch.equal(outs[k], ref[k]), k
+    for p in plans:
+        p.close()
+
+
 def test_batch_rejects_mixed_types():
     a = laplacian_2d(16, 16)
     p1 = _plan(a, 4, 2, dtype="f64")

@@ -108,7 +108,8 @@ def test_server_rejects_bad_arguments():
 
 
 def test_mixed_kernel_groups_and_solo_plans():
-    """Plans that differ in REMOTE_NNZ form separate kernel groups; an
+    """Plans that differ in REMOTE_NNZ share a kernel group (one second
+    launch per block size), plans that differ in BLOCK_NNZ do not; an
     explicit-hop NAP plan, a three-way plan and a strided plan run alone or
     in their groups; every result equals the apply done alone."""
     a1, a2, a3 = kkt_like(7000, 11), kkt_like(5000, 12), laplacian_2d(70, 50)
