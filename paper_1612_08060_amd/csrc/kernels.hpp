@@ -86,24 +86,43 @@ __device__ __forceinline__ void stage_band(int32_t band, int32_t n, const T *__r
     __syncthreads();
 }
 
+// NT: a non-temporal store (past the caches).  A compile-time choice: with a
+// run-time one the compiler merges the two stores and keeps neither hint.
+template <bool NT, typename T>
+__device__ __forceinline__ void store_out(T x, T *p) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(x, p);
+    else
+        *p = x;
+}
+
+template <typename T, bool NT>
+__device__ __forceinline__ void band_copy(int32_t k, int32_t end, const uint16_t *__restrict__ off,
+                                          T *__restrict__ dst, const T *lds) {
+    for (; k + 7 * kBlock < end; k += 8 * kBlock) {
+        uint16_t o[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) o[u] = __builtin_nontemporal_load(off + k + u * kBlock);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) store_out<NT>(lds[o[u]], dst + k + u * kBlock);
+    }
+    for (; k < end; k += kBlock) store_out<NT>(lds[__builtin_nontemporal_load(off + k)], dst + k);
+}
+
 template <typename T, int CAP>
 __device__ __forceinline__ void exchange_item(int4 it, int32_t n, const uint16_t *__restrict__ off,
                                               const int32_t *__restrict__ idx,
                                               const int32_t *__restrict__ dpos,
                                               const T *__restrict__ src, T *__restrict__ dst,
-                                              T *lds) {
+                                              T *lds, bool nt) {
     const int32_t end = it.y + it.z;
     int32_t k = it.y + (int32_t)threadIdx.x;
     if (it.x >= 0) {
         stage_band<T, CAP>(it.x, n, src, lds);
-        for (; k + 7 * kBlock < end; k += 8 * kBlock) {
-            uint16_t o[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) o[u] = __builtin_nontemporal_load(off + k + u * kBlock);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) dst[k + u * kBlock] = lds[o[u]];
-        }
-        for (; k < end; k += kBlock) dst[k] = lds[__builtin_nontemporal_load(off + k)];
+        if (nt)
+            band_copy<T, true>(k, end, off, dst, lds);
+        else
+            band_copy<T, false>(k, end, off, dst, lds);
         return;
     }
     for (; k + 3 * kBlock < end; k += 4 * kBlock) {
@@ -191,7 +210,8 @@ __device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
 // stored order.
 constexpr int kMaxRows = 1024;
 
-template <typename VT, typename XT, typename CT, int CAP, int W, bool REMOTE, bool DIRECT = false>
+template <typename VT, typename XT, typename CT, int CAP, int W, bool REMOTE, bool DIRECT = false,
+          bool NTW = false>
 __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                               int2 win, const int32_t *__restrict__ rowptr,
                                               const CT *__restrict__ col, int32_t cbase,
@@ -288,7 +308,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
         if (r < r1 && !(REMOTE && rb[i] == re[i])) {
             XT acc = s[i];
             for (int32_t q = rb[i] - k0; q < re[i] - k0; ++q) acc = acc + prod[q];
-            w[r] = acc;
+            store_out<NTW>(acc, w + r);
         }
     }
 }
@@ -312,6 +332,7 @@ struct LocalView {
     const VT *val;
     const XT *v;
     XT *w;
+    int32_t nt;                // stores past the caches (see stream_out)
 };
 
 template <typename VT, typename XT>
@@ -323,6 +344,7 @@ struct RemoteView {
     const XT *ghost;           // ghost buffer, or the received buffer (direct reads)
     const XT *v;               // direct reads only (else null): source of on-node values
     XT *w;
+    int32_t nt;                // stores of w past the caches (see stream_out)
 };
 
 template <typename XT>
@@ -335,36 +357,53 @@ struct ScatterView {
     int32_t n, which;
 };
 
+template <typename VT, typename XT, typename CT, int CAP, int W, bool NT>
+__device__ __forceinline__ void local_block(const LocalView<VT, XT> &L, int32_t task, const CT *col,
+                                            int32_t cbase, XT *prod, XT *wbuf) {
+    const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
+    product_block<VT, XT, CT, CAP, W, false, false, NT>(
+        L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr, col,
+        cbase, L.val, nullptr, L.v, L.w, prod, wbuf);
+}
+
 template <typename VT, typename XT, int CAP, int W>
 __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t, XT *prod,
                                            XT *wbuf) {
     const int32_t task = L.tasks[t];
     if (task < 0) {
-        exchange_item<XT, CAP>(L.items[~task], L.n, L.off, L.idx, L.dpos, L.v, L.xdst, prod);
+        exchange_item<XT, CAP>(L.items[~task], L.n, L.off, L.idx, L.dpos, L.v, L.xdst, prod,
+                               L.nt != 0);
         return;
     }
-    const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
-    if (L.col16)
-        product_block<VT, XT, uint16_t, CAP, W, false>(
-            L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
-            L.col16, L.base[task], L.val, nullptr, L.v, L.w, prod, wbuf);
-    else
-        product_block<VT, XT, int32_t, CAP, W, false>(
-            L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
-            L.col, 0, L.val, nullptr, L.v, L.w, prod, wbuf);
+    if (L.col16) {
+        if (L.nt)
+            local_block<VT, XT, uint16_t, CAP, W, true>(L, task, L.col16, L.base[task], prod, wbuf);
+        else
+            local_block<VT, XT, uint16_t, CAP, W, false>(L, task, L.col16, L.base[task], prod, wbuf);
+    } else {
+        if (L.nt)
+            local_block<VT, XT, int32_t, CAP, W, true>(L, task, L.col, 0, prod, wbuf);
+        else
+            local_block<VT, XT, int32_t, CAP, W, false>(L, task, L.col, 0, prod, wbuf);
+    }
+}
+
+template <typename VT, typename XT, int CAP, bool DIRECT, bool NT>
+__device__ __forceinline__ void remote_part(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
+    product_block<VT, XT, int32_t, CAP, 0, true, DIRECT, NT>(
+        R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], make_int2(0, 0), R.rowptr,
+        R.col, 0, R.val, R.slot, R.ghost, R.w, prod, nullptr, R.v);
 }
 
 template <typename VT, typename XT, int CAP>
 __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
-    if (R.v)
-        product_block<VT, XT, int32_t, CAP, 0, true, true>(
-            R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], make_int2(0, 0), R.rowptr,
-            R.col, 0, R.val, R.slot, R.ghost, R.w, prod, nullptr, R.v);
-    else
-        product_block<VT, XT, int32_t, CAP, 0, true>(R.rowblk[b], R.rowblk[b + 1], R.blkptr[b],
-                                                     R.blkptr[b + 1], make_int2(0, 0), R.rowptr,
-                                                     R.col, 0, R.val, R.slot, R.ghost, R.w, prod,
-                                                     nullptr);
+    if (R.v) {
+        if (R.nt) remote_part<VT, XT, CAP, true, true>(R, b, prod);
+        else remote_part<VT, XT, CAP, true, false>(R, b, prod);
+    } else {
+        if (R.nt) remote_part<VT, XT, CAP, false, true>(R, b, prod);
+        else remote_part<VT, XT, CAP, false, false>(R, b, prod);
+    }
 }
 
 // Index of the entry of prefix[0..count] (ascending, prefix[0] = 0) whose

@@ -599,6 +599,16 @@ inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + napspmv::kBlock -
 
 // ---- views -------------------------------------------------------------------
 
+// The first launch's exchange buffer and both launches' w are written with
+// non-temporal stores when that buffer is larger than the 256 MB Infinity
+// Cache: the second launch cannot find it there anyway, and lines left dirty
+// in L2 would be written back while the second launch runs.  (Smaller
+// buffers are read back from the cache, and plain stores are faster.)
+int32_t stream_out(const napspmv_plan_s *p) {
+    const int64_t x = (p->hp.mode == NAPSPMV_STANDARD ? p->G : p->E) * vec_bytes(p->hp.dtype);
+    return x > ((int64_t)256 << 20) ? 1 : 0;
+}
+
 template <typename VT, typename XT>
 napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &s, const Ws &ws,
                                       const XT *v, XT *w, int64_t task0, int64_t n_tasks) {
@@ -622,6 +632,7 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
     L.val = static_cast<const VT *>(p->d_val_on);
     L.v = v;
     L.w = w;
+    L.nt = stream_out(p);
     return L;
 }
 
@@ -642,6 +653,7 @@ napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules
     R.ghost = static_cast<const XT *>(p->hp.direct ? ws.recv : ws.ghost);
     R.v = p->hp.direct ? v : nullptr;
     R.w = w;
+    R.nt = stream_out(p);
     return R;
 }
 
