@@ -206,3 +206,40 @@ def test_autotune_keeps_results_and_caches():
             assert torch.equal(_solo(p2, v), ref)
             p2.close()
         assert len(open(cache).read().splitlines()) == 2
+
+
+def test_batched_workload_full_size():
+    """The 256-block 27-point workload at full size (N = 2,604,175, 69 M
+    entries), in the benchmark's launch configuration: autotuned, the whole
+    product as one graph-captured launch pair.  float32 values: w within 1e-5
+    of the float64 oracle (normwise), and the per-block launches equal to the
+    batched result bit for bit; float64 values: w equal to the oracle's
+    split-order product bit for bit."""
+    wl = config(4)
+    a = wl.csr
+    print("batched workload, full size, float32", flush=True)
+    p = _plan(a, wl.n_p, wl.ppn, dtype="f32", row_starts=wl.row_starts)
+    v = _vec(wl.v, "f32")
+    w = torch.full_like(v, float("nan"))
+    p.autotune(v, w, reps=2)
+    g = p.graph(v, w)
+    w.fill_(float("nan"))
+    g.launch()
+    torch.cuda.synchronize()
+    ref = oracle_spmv.spmv(a, wl.v)
+    got = w.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= 1e-5, err
+    p.prepare_partitions()
+    w2 = torch.full_like(v, float("nan"))
+    for t in range(wl.n_p):
+        p.apply_partition(t, v, w2)
+    torch.cuda.synchronize()
+    assert torch.equal(w, w2)
+    g.close()
+    p.close()
+    print("batched workload, full size, float64", flush=True)
+    p64 = _plan(a, wl.n_p, wl.ppn, dtype="f64", row_starts=wl.row_starts)
+    w64 = _solo(p64, _vec(wl.v, "f64"))
+    assert np.array_equal(w64.cpu().numpy(), oracle_spmv.spmv_split(a, wl.v, wl.n_p, wl.row_starts))
+    p64.close()
