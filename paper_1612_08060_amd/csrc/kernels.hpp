@@ -150,12 +150,11 @@ __device__ __forceinline__ void exchange_item(int4 it, int32_t n, const uint16_t
 // received values, 2 only fully local values.
 constexpr uint32_t kFromV = 0x80000000u;
 
-template <typename T, int CAP>
-__device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
-                                             const uint32_t *__restrict__ code,
-                                             const T *__restrict__ v, const T *__restrict__ recv,
-                                             T *__restrict__ ghost, T *lds) {
-    if (which != 1) stage_band<T, CAP>(it.x, n, v, lds);
+template <typename T, bool NT>
+__device__ __forceinline__ void scatter_values(int4 it, int32_t which,
+                                               const uint32_t *__restrict__ code,
+                                               const T *recv, T *__restrict__ ghost,
+                                               const T *lds) {
     const int32_t end = it.y + it.z;
     int32_t k = it.y + (int32_t)threadIdx.x;
     for (; k + 3 * kBlock < end; k += 4 * kBlock) {
@@ -171,14 +170,50 @@ __device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const bool fv = (c[u] & kFromV) != 0;
-            if (fv ? which != 1 : which != 2) ghost[k + u * kBlock] = x[u];
+            if (fv ? which != 1 : which != 2) store_out<NT>(x[u], ghost + k + u * kBlock);
         }
     }
     for (; k < end; k += kBlock) {
         const uint32_t c = __builtin_nontemporal_load(code + k);
         const bool fv = (c & kFromV) != 0;
-        if (fv ? which != 1 : which != 2) ghost[k] = fv ? lds[c & ~kFromV] : recv[c];
+        if (fv ? which != 1 : which != 2) store_out<NT>(fv ? lds[c & ~kFromV] : recv[c], ghost + k);
     }
+}
+
+template <typename T, int CAP>
+__device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
+                                             const uint32_t *__restrict__ code,
+                                             const T *__restrict__ v, const T *__restrict__ recv,
+                                             T *__restrict__ ghost, T *lds) {
+    if (which != 1) stage_band<T, CAP>(it.x, n, v, lds);
+    scatter_values<T, false>(it, which, code, recv, ghost, lds);
+}
+
+// NAP pack and scatter of one column band b in one item, when the exchange
+// is received in place: every received value a ghost of band b takes was
+// packed from band b of v (the ghost's own column), so once this item has
+// packed band b's part of the send buffer, the same workgroup can scatter
+// band b of the ghost buffer from it (the off_node -> on_node step and the
+// receiver's own use), and the fully local positions from the band of v
+// still in LDS.  The pack uses plain stores: its values are read back at
+// once, from this CU's cache.  item = (b, first send entry, count, 1).
+template <typename T, int CAP>
+__device__ __forceinline__ void pack_scatter_item(int4 it, int32_t n, const uint16_t *__restrict__ off,
+                                                  const T *__restrict__ v, T *send,
+                                                  const int32_t *__restrict__ gband,
+                                                  const uint32_t *__restrict__ code,
+                                                  const T *recv, T *__restrict__ ghost, T *lds,
+                                                  bool nt) {
+    stage_band<T, CAP>(it.x, n, v, lds);
+    band_copy<T, false>(it.y + (int32_t)threadIdx.x, it.y + it.z, off, send, lds);
+    // the band's packed values are visible to the whole workgroup (recv and
+    // send are the same memory: no restrict on either)
+    __syncthreads();
+    const int4 sit = make_int4(it.x, gband[it.x], gband[it.x + 1] - gband[it.x], 1);
+    if (nt)
+        scatter_values<T, true>(sit, 0, code, recv, ghost, lds);
+    else
+        scatter_values<T, false>(sit, 0, code, recv, ghost, lds);
 }
 
 // One row block of a split CSR product.  The block owns rows [r0, r1) (at
@@ -333,6 +368,12 @@ struct LocalView {
     const XT *v;
     XT *w;
     int32_t nt;                // stores past the caches (see stream_out)
+    // NAP pack-and-scatter items (item.w = 1): ghost band boundaries, the
+    // scatter codes, the received buffer and the ghost buffer
+    const int32_t *gband;
+    const uint32_t *code;
+    const XT *recv;
+    XT *ghost;
 };
 
 template <typename VT, typename XT>
@@ -371,8 +412,13 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
                                            XT *wbuf) {
     const int32_t task = L.tasks[t];
     if (task < 0) {
-        exchange_item<XT, CAP>(L.items[~task], L.n, L.off, L.idx, L.dpos, L.v, L.xdst, prod,
-                               L.nt != 0);
+        const int4 it = L.items[~task];
+        if (it.w == 1) {
+            pack_scatter_item<XT, CAP>(it, L.n, L.off, L.v, L.xdst, L.gband, L.code, L.recv,
+                                       L.ghost, prod, L.nt != 0);
+            return;
+        }
+        exchange_item<XT, CAP>(it, L.n, L.off, L.idx, L.dpos, L.v, L.xdst, prod, L.nt != 0);
         return;
     }
     if (L.col16) {

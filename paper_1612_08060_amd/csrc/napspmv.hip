@@ -40,6 +40,7 @@ struct Schedules {
     int32_t *ndblk = nullptr, *ndptr = nullptr;     // three-way: on_node row blocks
     int32_t *onbase = nullptr;                      // first row of each on-process block's process
     int32_t *sitems = nullptr;                      // NAP: band items of the ghost scatter
+    int32_t *gband = nullptr;                       // NAP: ghost band boundaries (pack-and-scatter items)
     int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, n_nd = 0, n_sitems = 0, bytes = 0;
     // per-partition schedules only: each process's range of tasks and of
     // off-process blocks
@@ -202,7 +203,7 @@ void charge(napspmv_plan_s *p, int64_t bytes) {
 
 void free_schedules(napspmv_plan_s *p, Schedules &s) {
     void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks, s.ndblk, s.ndptr,
-                    s.sitems, s.onbase};
+                    s.sitems, s.onbase, s.gband};
     for (void *q : ptrs) free_ptr(q);
     charge(p, -s.bytes);
     s = Schedules();
@@ -256,7 +257,8 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
                       const std::vector<int32_t> &offblk, const std::vector<int32_t> &offptr,
                       const std::vector<int32_t> &items, const std::vector<int32_t> &tasks,
                       const std::vector<int32_t> &ndblk = {}, const std::vector<int32_t> &ndptr = {},
-                      const std::vector<int32_t> &sitems = {}, const std::vector<int32_t> &onbase = {}) {
+                      const std::vector<int32_t> &sitems = {}, const std::vector<int32_t> &onbase = {},
+                      const std::vector<int32_t> &gband = {}) {
     free_schedules(p, s);
     int64_t total = 0;
     try {
@@ -271,6 +273,7 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
         upload(s.tasks, tasks, total);
         upload(s.sitems, sitems, total);
         upload(s.onbase, onbase, total);
+        upload(s.gband, gband, total);
     } catch (...) {
         s.bytes = total;
         charge(p, total);
@@ -469,7 +472,7 @@ void refresh_schedules(napspmv_plan_s *p) {
         rcap == p->cur_remote_nnz)
         return;
     const HostPlan &hp = p->hp;
-    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems, onbase;
+    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems, onbase, gbv;
     // on-process blocks never span two processes: each block's columns are
     // offsets from its process's first row
     napspmv::row_blocks_per_process(hp.rowptr_on.data(), hp.starts, cap, kMaxRowsPerBlock, onblk,
@@ -501,12 +504,29 @@ void refresh_schedules(napspmv_plan_s *p) {
     if (hp.mode == NAPSPMV_STANDARD) {
         band_items(p->gband, item, items);
     } else {
-        band_items(p->sband, item, items);
-        band_items(p->gband, item, sitems);
+        // received in place, each band's send entries in one item: pack and
+        // scatter band by band in the first launch (pack_scatter_item)
+        int64_t widest = 0;
+        for (size_t b = 0; b + 1 < p->sband.size(); ++b)
+            widest = std::max(widest, p->sband[b + 1] - p->sband[b]);
+        const bool fuse = !hp.three_way && !hp.direct && !(p->flags & NAPSPMV_EXCHANGE_COPY) &&
+                          widest <= item;
+        if (fuse) {
+            for (size_t b = 0; b + 1 < p->sband.size(); ++b) {
+                const int64_t ns = p->sband[b + 1] - p->sband[b], ng = p->gband[b + 1] - p->gband[b];
+                if (ns == 0 && ng == 0) continue;
+                const int32_t q[4] = {(int32_t)b, (int32_t)p->sband[b], (int32_t)ns, 1};
+                items.insert(items.end(), q, q + 4);
+            }
+            gbv.assign(p->gband.begin(), p->gband.end());
+        } else {
+            band_items(p->sband, item, items);
+            band_items(p->gband, item, sitems);
+        }
     }
     napspmv::merge_tasks((int64_t)items.size() / 4, (int64_t)onblk.size() - 1, tasks);
     upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr,
-                     sitems, onbase);
+                     sitems, onbase, gbv);
     p->cur_block_nnz = cap;
     p->cur_window = win;
     p->cur_item = item;
@@ -633,6 +653,10 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
     L.v = v;
     L.w = w;
     L.nt = stream_out(p);
+    L.gband = s.gband;
+    L.code = p->d_code;
+    L.recv = static_cast<const XT *>(ws.recv);
+    L.ghost = static_cast<XT *>(ws.ghost);
     return L;
 }
 
