@@ -473,6 +473,7 @@ void refresh_schedules(napspmv_plan_s *p) {
         return;
     const HostPlan &hp = p->hp;
     std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems, onbase, gbv;
+    int64_t tail = napspmv::kItemTail;
     // on-process blocks never span two processes: each block's columns are
     // offsets from its process's first row
     napspmv::row_blocks_per_process(hp.rowptr_on.data(), hp.starts, cap, kMaxRowsPerBlock, onblk,
@@ -512,6 +513,7 @@ void refresh_schedules(napspmv_plan_s *p) {
         const bool fuse = !hp.three_way && !hp.direct && !(p->flags & NAPSPMV_EXCHANGE_COPY) &&
                           widest <= item;
         if (fuse) {
+            tail = napspmv::kPackScatterTail;
             for (size_t b = 0; b + 1 < p->sband.size(); ++b) {
                 const int64_t ns = p->sband[b + 1] - p->sband[b], ng = p->gband[b + 1] - p->gband[b];
                 if (ns == 0 && ng == 0) continue;
@@ -524,7 +526,7 @@ void refresh_schedules(napspmv_plan_s *p) {
             band_items(p->gband, item, sitems);
         }
     }
-    napspmv::merge_tasks((int64_t)items.size() / 4, (int64_t)onblk.size() - 1, tasks);
+    napspmv::merge_tasks((int64_t)items.size() / 4, (int64_t)onblk.size() - 1, tasks, tail);
     upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr,
                      sitems, onbase, gbv);
     p->cur_block_nnz = cap;

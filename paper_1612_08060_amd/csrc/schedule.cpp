@@ -103,7 +103,7 @@ void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int
     }
 }
 
-void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks) {
+void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks, int64_t tail) {
     tasks.clear();
     tasks.reserve((size_t)(n_items + n_blocks));
     // the launch's XCD ranges (see xcd_block): 8 contiguous stretches of the
@@ -113,10 +113,10 @@ void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks)
     for (int64_t x = 0; x < 8 && n > 0; ++x) {
         const int64_t len = q + (x < r ? 1 : 0);
         const int64_t ni = n_items * (start + len) / n - i;     // this range's share of items
-        // items go in proportion over the range but the last kItemTail
-        // tasks, so that no item (several times a row block's bytes) is
-        // left running alone at the end of the launch
-        const int64_t span = std::max(ni, len - kItemTail), sb = span - ni;
+        // items go in proportion over the range but the last `tail` tasks,
+        // so that no item (several times a row block's bytes) is left
+        // running alone at the end of the launch
+        const int64_t span = std::max(ni, len - tail), sb = span - ni;
         int64_t il = 0, bl = 0;
         for (int64_t s = 0; s < len; ++s) {
             if (il < ni && (bl >= sb || il * sb <= bl * ni))

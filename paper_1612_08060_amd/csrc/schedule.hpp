@@ -40,11 +40,15 @@ void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int
 // Launch order of the first apply launch: exchange items (encoded ~i) and
 // local row blocks (encoded b >= 0), each list kept in its own order.  Each
 // XCD's contiguous share of the launch gets its proportional slice of both,
-// interleaved, except that its last kItemTail tasks are row blocks only: an
+// interleaved, except that its last `tail` tasks are row blocks only: an
 // XCD holds about 128 of these blocks at once (32 CUs, 4 each), and an
-// item still running in the final rounds would leave the rest idle.
+// item still running in the final rounds would leave the rest idle.  NAP
+// pack-and-scatter items carry about twice an exchange item's bytes, so
+// they keep a longer tail.
 constexpr int64_t kItemTail = 512;
-void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks);
+constexpr int64_t kPackScatterTail = 1024;
+void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks,
+                 int64_t tail = kItemTail);
 
 // Work items covering [0, total) in order, pieces of at most `max_len`.
 void flat_items(int64_t total, int max_len, std::vector<int32_t> &items);

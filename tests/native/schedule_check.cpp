@@ -15,11 +15,11 @@ static int fail(const char *what, long long a, long long b) {
     return 1;
 }
 
-static int check_merge() {
+static int check_merge(int64_t tail) {
     for (int64_t ni = 0; ni < 400; ni += 13)
         for (int64_t nb = 0; nb < 6000; nb += 41) {
             std::vector<int32_t> t;
-            napspmv::merge_tasks(ni, nb, t);
+            napspmv::merge_tasks(ni, nb, t, tail);
             if ((int64_t)t.size() != ni + nb) return fail("merge size", ni, nb);
             int64_t ei = 0, eb = 0;
             for (int32_t x : t) {
@@ -31,7 +31,7 @@ static int check_merge() {
             }
             if (ei != ni || eb != nb) return fail("merge counts", ni, nb);
             // the XCD ranges of the launch (xcd_block): proportional shares,
-            // and no item in a range's last kItemTail tasks unless the items
+            // and no item in a range's last `tail` tasks unless the items
             // do not fit before them (then they lead the range)
             const int64_t n = ni + nb, q = n / 8, r = n % 8;
             int64_t start = 0, seen = 0;
@@ -42,7 +42,7 @@ static int check_merge() {
                 for (int64_t s = 0; s < len; ++s)
                     if (t[start + s] < 0) { ++cnt; last = s; }
                 if (cnt != share) return fail("range share", x, cnt);
-                const int64_t limit = std::max(share, len - napspmv::kItemTail);
+                const int64_t limit = std::max(share, len - tail);
                 if (last >= limit) return fail("item in the tail", x, last);
                 seen += cnt;
                 start += len;
@@ -109,7 +109,9 @@ static int check_blocks_and_sort() {
 }
 
 int main() {
-    if (check_merge() || check_blocks_and_sort()) return 1;
+    if (check_merge(napspmv::kItemTail) || check_merge(napspmv::kPackScatterTail) ||
+        check_blocks_and_sort())
+        return 1;
     std::printf("ok\n");
     return 0;
 }
