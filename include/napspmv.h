@@ -135,9 +135,11 @@ extern "C" {
 /* Stages of an apply; napspmv_apply runs LOCAL then REMOTE.  LOCAL is one
  * launch: the exchange gather (standard: every ghost from its owner; NAP:
  * the inter-node send buffer) overlapped with the on-process product
- * w = A_on v.  REMOTE: for NAP the inter-node hop and the scatter of received
- * and fully local values into the ghost buffer, then (both modes) the
- * off-process product w += A_off ghost. */
+ * w = A_on v.  For NAP, the scatter of received and fully local values into
+ * the ghost buffer runs band by band inside LOCAL when the exchange is
+ * received in place (each band's pack, then its scatter), else in REMOTE
+ * after the inter-node hop.  REMOTE: that hop and scatter when not done in
+ * LOCAL, then (both modes) the off-process product w += A_off ghost. */
 #define NAPSPMV_STAGE_LOCAL  0
 #define NAPSPMV_STAGE_REMOTE 1
 
