@@ -319,3 +319,30 @@ def test_apply_argument_checks():
     with pytest.raises(nap.NapspmvError):
         p.apply_stage(7, v, torch.zeros_like(v))
     p.close()
+
+
+def test_nap_scatter_inside_first_launch():
+    """A NAP plan that receives in place packs and scatters band by band in
+    the first launch: after STAGE_LOCAL alone every ghost already holds its
+    owner's value, and STAGE_REMOTE then completes w.  With exchange items
+    narrower than a band (no fusing) or the explicit hop, the scatter stays
+    in STAGE_REMOTE; every form gives the same w bit for bit."""
+    wl = config(2)
+    a = wl.csr
+    ref = _split(a, wl.v, wl.n_p, wl.row_starts)
+    tv = torch.from_numpy(wl.v).to(DEV)
+    for kw, item in (({}, -1), ({}, 256), ({"exchange_copy": True}, -1)):
+        print(f"nap stages {kw} gather_item={item}", flush=True)
+        with nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="nap",
+                      row_starts=wl.row_starts, **kw) as p:
+            p.set_param("gather_item", item)
+            w = torch.full_like(tv, float("nan"))
+            p.apply_stage(nap.STAGE_LOCAL, tv, w)
+            torch.cuda.synchronize()
+            _, gc = p.ghosts()
+            if not kw and item == -1:
+                assert np.array_equal(p.read_ghosts(), wl.v[gc])
+            p.apply_stage(nap.STAGE_REMOTE, tv, w)
+            torch.cuda.synchronize()
+            assert np.array_equal(w.cpu().numpy(), ref)
+            assert np.array_equal(p.read_ghosts(), wl.v[gc])
