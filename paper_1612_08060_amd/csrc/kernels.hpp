@@ -3,12 +3,14 @@
 //
 // An apply is two product launches, as algorithm standard_spmv (section 2.1)
 // and NAPSpMV (section 4.3) order the work: the first launch runs the
-// exchange that fills the ghost buffer (or the NAP send buffer) together
-// with the on-process product local_spmv(A_on, v), which needs no received
-// value; the second adds the off-process product local_spmv(A_off, ghost)
-// into w (for NAP after the hop and the scatter of received values).  The
-// first launch interleaves its two kinds of blocks on every CU, the overlap
-// of local work with communication that the paper's algorithms make.
+// exchange that fills the ghost buffer (or the NAP send buffer and, when it
+// is received in place, band by band the NAP scatter into the ghost buffer)
+// together with the on-process product local_spmv(A_on, v), which needs no
+// received value; the second adds the off-process product
+// local_spmv(A_off, ghost) into w (for NAP with the explicit hop, after the
+// hop and the scatter of received values).  The first launch interleaves
+// its two kinds of blocks on every CU, the overlap of local work with
+// communication that the paper's algorithms make.
 //
 // Every kernel is HBM-bound (the product does 2 flops per 12-16 bytes), so
 // the design is about bytes and latency, not arithmetic: 256-thread blocks of
