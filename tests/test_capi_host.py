@@ -215,3 +215,29 @@ def test_duplicates_and_stored_zeros_are_structure():
         s1 = _compare(a, 8, 2, mode)
         s2 = _compare(z, 8, 2, mode)
         assert s1["phases"] == s2["phases"]
+
+
+def test_index_limits_are_unsupported():
+    """Sizes past the 32-bit index range the kernels form (2^31 - 2^16) are
+    refused with EUNSUPPORTED before any entry is read; only the row
+    pointers are touched, so tiny buffers stand in for the huge matrix."""
+    import ctypes
+    so = lib.load_library()
+    limit = (1 << 31) - (1 << 16)
+    col = np.zeros(4, np.int32)
+    val = np.zeros(4, np.float64)
+    handle = ctypes.c_void_p()
+    # nnz past the limit
+    rowptr = np.array([0, limit + 1], np.int64)
+    rc = so.napspmv_plan_create(rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, 0, 1, 1, 1,
+                                0, None, 0x1, ctypes.byref(handle), None)
+    assert rc == -4 and b"nnz" in so.napspmv_last_error() and not handle.value
+    # n past the limit (checked before the row pointers are walked)
+    rc = so.napspmv_plan_create(rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, 0, limit + 1,
+                                1, 1, 0, None, 0x1, ctypes.byref(handle), None)
+    assert rc == -4 and b"n must be" in so.napspmv_last_error() and not handle.value
+    # just inside: an ordinary error from the next check, not EUNSUPPORTED
+    rowptr = np.array([1, 2], np.int64)
+    rc = so.napspmv_plan_create(rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, 0, 1, 1, 1,
+                                0, None, 0x1, ctypes.byref(handle), None)
+    assert rc == -1
