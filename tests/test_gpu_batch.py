@@ -243,3 +243,27 @@ def test_batched_workload_full_size():
     w64 = _solo(p64, _vec(wl.v, "f64"))
     assert np.array_equal(w64.cpu().numpy(), oracle_spmv.spmv_split(a, wl.v, wl.n_p, wl.row_starts))
     p64.close()
+
+
+def test_batch_mixes_fused_and_separate_nap_scatter():
+    """NAP plans that scatter inside the first launch (pack-and-scatter
+    items) and NAP plans that keep the separate scatter launch (exchange
+    items narrower than a band) in one batch, with standard plans: every
+    product equal to its solo apply bit for bit."""
+    a, b2 = kkt_like(1 << 13, 41), laplacian_3d(12, 12, 12)
+    plans = [_plan(a, 16, 4, mode="nap"), _plan(a, 16, 4, mode="nap"),
+             _plan(b2, 8, 4, mode="nap"), _plan(b2, 8, 4, mode="standard")]
+    plans[1].set_param("gather_item", 256)
+    vs = [_vec(vec_normal(p.n, 60 + k), "f64") for k, p in enumerate(plans)]
+    ref = [_solo(p, v) for p, v in zip(plans, vs)]
+    for rep in range(2):
+        outs = [torch.full_like(v, float("nan")) for v in vs]
+        bt = nap.Batch(len(plans))
+        print(f"batch of fused and separate NAP scatters, pass {rep}", flush=True)
+        bt.apply(plans, vs, outs)
+        torch.cuda.synchronize()
+        bt.close()
+        for k in range(len(plans)):
+            assert torch.equal(outs[k], ref[k]), (rep, k)
+    for p in plans:
+        p.close()
