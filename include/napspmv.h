@@ -370,7 +370,10 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
  *                 least 8192 off-process entries per process, else 4096)
  *   GATHER_ITEM   most entries of one exchange work item (a slice of one
  *                 band of the ghost or send buffer), 256 .. 2^24
- *                 (automatic: 65536)
+ *                 (automatic: 65536).  A NAP plan that receives in place
+ *                 packs and scatters whole bands in one item each when this
+ *                 is automatic or at least the widest band of its send
+ *                 buffer, else it keeps the separate scatter launch.
  *   VWINDOW       on-process product: most elements of v a row block stages
  *                 in LDS, 0 (none), 1024, 2048, 4096 (automatic: 1024)
 

@@ -56,6 +56,7 @@ struct napspmv_plan_s {
     int block_nnz = -1, item = -1, window = -1, remote_nnz = -1;
     int auto_block_nnz = 4096, auto_item = 65536, auto_window = 1024, auto_remote_nnz = 8192;
     int cur_block_nnz = 0, cur_item = 0, cur_window = -1, cur_remote_nnz = 0;   // on the device
+    bool cur_item_auto = true;       // the schedules were built with an automatic item size
     int sorted_remote_nnz = 0;       // block size the off-process entry order was sorted for
     int64_t G = 0, E = 0, H = 0, Gon = 0;
     int32_t *d_rp_on = nullptr, *d_col_on = nullptr, *d_rp_off = nullptr, *d_col_off = nullptr;
@@ -469,7 +470,7 @@ void band_items(const std::vector<int64_t> &bstart, int item, std::vector<int32_
 void refresh_schedules(napspmv_plan_s *p) {
     const int cap = cur_cap(p), win = cur_win(p), item = cur_item(p), rcap = cur_rcap(p);
     if (p->sched.onblk && cap == p->cur_block_nnz && win == p->cur_window && item == p->cur_item &&
-        rcap == p->cur_remote_nnz)
+        rcap == p->cur_remote_nnz && (p->item < 0) == p->cur_item_auto)
         return;
     const HostPlan &hp = p->hp;
     std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems, onbase, gbv;
@@ -510,8 +511,10 @@ void refresh_schedules(napspmv_plan_s *p) {
         int64_t widest = 0;
         for (size_t b = 0; b + 1 < p->sband.size(); ++b)
             widest = std::max(widest, p->sband[b + 1] - p->sband[b]);
+        // (an automatic item size always allows it: a band's item is then
+        // as wide as the band)
         const bool fuse = !hp.three_way && !hp.direct && !(p->flags & NAPSPMV_EXCHANGE_COPY) &&
-                          widest <= item;
+                          (p->item < 0 || widest <= item);
         if (fuse) {
             tail = napspmv::kPackScatterTail;
             for (size_t b = 0; b + 1 < p->sband.size(); ++b) {
@@ -532,6 +535,7 @@ void refresh_schedules(napspmv_plan_s *p) {
     p->cur_block_nnz = cap;
     p->cur_window = win;
     p->cur_item = item;
+    p->cur_item_auto = p->item < 0;
     p->cur_remote_nnz = rcap;
     if (p->part_ready) build_partitions(p);
 }
