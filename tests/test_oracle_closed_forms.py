@@ -153,3 +153,65 @@ def test_invariants(maker):
         else:
             q = rec[(node(tt), jj)]
             assert (q == tt) != ((tt, jj) in l1)
+
+
+STAT_KEYS = ("msgs", "elems", "max_msgs_sent", "max_elems_sent", "max_msgs_recv",
+             "max_elems_recv", "max_msg_elems")
+
+
+def _stats(phase, n_p):
+    st = plan_vec.phase_stats(phase, n_p)
+    return tuple(st[k] for k in STAT_KEYS)
+
+
+def test_laplace2d_per_process_statistics():
+    """All seven statistics per phase (section 5 plots the per-process ones).
+    Standard inter-node: ranks 3, 4, 7, 8, 11, 12 each send one line to the
+    neighbour across a node boundary and receive one.  Intra-node: the two
+    middle ranks of a node exchange a line with both neighbours (2 messages,
+    128 values each way).  NAP: every INTER sender, L0 and L1 rank moves
+    exactly one line (the message lists are in test_laplace2d_closed_forms)."""
+    a = laplacian_2d(64, 64)
+    s = plan_vec.standard_plan(a, 16, 4)["phases"]
+    n = plan_vec.nap_plan(a, 16, 4)["phases"]
+    assert _stats(s["INTER"], 16) == (6, 384, 1, 64, 1, 64, 64)
+    assert _stats(s["L2"], 16) == (24, 1536, 2, 128, 2, 128, 64)
+    assert _stats(n["INTER"], 16) == (6, 384, 1, 64, 1, 64, 64)
+    assert _stats(n["L0"], 16) == (3, 192, 1, 64, 1, 64, 64)
+    assert _stats(n["L1"], 16) == (5, 320, 1, 64, 1, 64, 64)
+    assert _stats(n["L2"], 16) == _stats(s["L2"], 16)
+
+
+def test_laplace3d_per_process_statistics():
+    """Rank t owns y-block t mod 8 (16 lines) of plane t div 8; a node holds
+    planes 2a and 2a+1 (locals 0-7 and 8-15).
+    Standard inter-node: a rank of plane 2a+1 sends its block up to plane
+    2a+2, a rank of plane 2a down to 2a-1: one message of 2048 each way.
+    Standard intra-node: an interior y-block sends a line (128) to each y
+    neighbour and its block (2048) to the other plane of its node: 3
+    messages, 2304 values, sent and received alike.
+    NAP INTER: local 0 sends plane 2a to node a-1 and local 1 plane 2a+1 to
+    node a+1 (equal volumes, lower node id first); local 15 receives from
+    a-1 and local 14 from a+1: one message of 16384 per rank at most.
+    L0: local 1 gathers plane 2a+1 from its 8 owners (8 x 2048 received),
+    local 0 plane 2a from the 7 others; every owner sends one block.
+    L1: local 15 forwards plane 2a-1 to locals 0-7 (8 x 2048 sent), local 14
+    plane 2a+2 to locals 8-13 and 15; every user receives one block."""
+    a = laplacian_3d(128, 128, 128)
+    s = plan_vec.standard_plan(a, 1024, 16)["phases"]
+    n = plan_vec.nap_plan(a, 1024, 16)["phases"]
+    assert _stats(s["INTER"], 1024) == (1008, 1008 * 2048, 1, 2048, 1, 2048, 2048)
+    intra = (7 * 2 * 128 + 64 * 8 * 2, 7 * 2 * 128 * 128 + 64 * 8 * 2 * 2048)
+    assert _stats(s["L2"], 1024) == intra + (3, 2304, 3, 2304, 2048)
+    assert _stats(n["INTER"], 1024) == (126, 126 * 16384, 1, 16384, 1, 16384, 16384)
+    assert _stats(n["L0"], 1024) == (945, 945 * 2048, 1, 2048, 8, 16384, 2048)
+    assert _stats(n["L1"], 1024) == (945, 945 * 2048, 8, 16384, 1, 2048, 2048)
+    assert _stats(n["L2"], 1024) == _stats(s["L2"], 1024)
+
+
+def test_planted_swap_caught_by_laplace3d_pins():
+    """A sender/receiver mix-up in phase_stats turns L0's 8 gathered blocks
+    per sender into 8 sends per owner; the hand-derived pins catch it."""
+    a = laplacian_3d(128, 128, 128)
+    src, dst, ptr, idx = plan_vec.nap_plan(a, 1024, 16)["phases"]["L0"]
+    assert _stats((dst, src, ptr, idx), 1024) != (945, 945 * 2048, 1, 2048, 8, 16384, 2048)

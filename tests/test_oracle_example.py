@@ -140,3 +140,46 @@ def test_printed_inter_table_fails_delivery(ex):
     with pytest.raises(simulate.DeliveryError):
         simulate.simulate_nap(a, lay, bad, np.arange(6.0))
     simulate.simulate_nap(a, lay, p, np.arange(6.0))
+
+
+# Every statistic the paper plots per process (section 5), derived by hand
+# from the tables of Example 2.1 (the corrected ones for NAP; reading Q9-Q12
+# above).  Nodes are {0,1}, {2,3}, {4,5}.
+#   standard, D: (1->0)(3->0)(5->0)(4->1)(3->2)(0->3)(1->3)(2->3)(0->4)(2->4)
+#     (0->5), one value each.  Inter-node (8): rank 0 sends 3 (to 3, 4, 5);
+#     ranks 1, 2, 3, 4, 5 send one each; ranks 0, 3, 4 receive 2 each, 1 and
+#     5 one.  Intra-node (3): 1->0, 3->2, 2->3.
+#   NAP INTER: (0->3 {0,1}) (1->5 {0}) (2->1 {3}) (3->4 {2}) (4->0 {4,5}):
+#     every rank sends and receives at most one message, of at most 2 values.
+#   L0: (0->1)(1->0)(2->3)(3->2)(5->4); L1: (0->1)(1->0)(5->4); L2 as the
+#     standard intra-node messages: one value each, one per rank.
+EXAMPLE_STATS = {
+    # (msgs, elems, max_msgs_sent, max_elems_sent, max_msgs_recv, max_elems_recv, max_msg_elems)
+    ("standard", "INTER"): (8, 8, 3, 3, 2, 2, 1),
+    ("standard", "L2"): (3, 3, 1, 1, 1, 1, 1),
+    ("nap", "INTER"): (5, 7, 1, 2, 1, 2, 2),
+    ("nap", "L0"): (5, 5, 1, 1, 1, 1, 1),
+    ("nap", "L1"): (3, 3, 1, 1, 1, 1, 1),
+    ("nap", "L2"): (3, 3, 1, 1, 1, 1, 1),
+}
+STAT_KEYS = ("msgs", "elems", "max_msgs_sent", "max_elems_sent", "max_msgs_recv",
+             "max_elems_recv", "max_msg_elems")
+
+
+@pytest.mark.parametrize("mode", ["standard", "nap"])
+def test_every_phase_statistic_matches_hand_derivation(ex, mode):
+    g, a, lay = ex
+    vec = plan_vec.plan(a, 6, 2, mode)
+    for ph in plan_ref.PHASES:
+        want = EXAMPLE_STATS.get((mode, ph), (0,) * 7)
+        got = plan_vec.phase_stats(vec["phases"][ph], 6)
+        assert tuple(got[k] for k in STAT_KEYS) == want, (mode, ph)
+
+
+def test_planted_sender_receiver_swap_is_caught(ex):
+    """A phase_stats that mixed up senders and receivers would report rank
+    0's three inter-node sends as receives; the hand-derived values differ."""
+    g, a, lay = ex
+    src, dst, ptr, idx = plan_vec.plan(a, 6, 2, "standard")["phases"]["INTER"]
+    swapped = plan_vec.phase_stats((dst, src, ptr, idx), 6)
+    assert tuple(swapped[k] for k in STAT_KEYS) != EXAMPLE_STATS[("standard", "INTER")]
