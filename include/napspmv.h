@@ -297,39 +297,57 @@ NAPSPMV_API int napspmv_plan_autotune(napspmv_plan_t plan, const void *v, void *
                                       int reps, const char *cache_path, double *best_ms);
 
 /*
- * Serving engine.  Resident plans take requests w = A_id v; requests wait in
+ * Serving engine (plan reuse over many products, the amortisation argument
+ * of section 5).  Resident plans take requests w = A_id v; requests wait in
  * a queue until one of `slots` slots (each its own HIP stream) is free and
  * their workspace fits in `workspace_budget` bytes (0 = no cap; idle
  * workspaces of other plans are released to make room), and each free slot
  * then runs up to `max_batch` queued requests of one kernel group (value
  * type, BLOCK_NNZ, VWINDOW; oldest request first) as one batched launch
  * sequence (a NAP plan with NAPSPMV_EXCHANGE_COPY or NAPSPMV_NAP_THREE_WAY
- * always runs alone, by napspmv_apply_ws).  Requests that arrive while slots are busy are admitted as slots
- * free up, so their work overlaps the work already on the device.
- * Single-threaded: one caller drives a server.  Every result is bitwise the
- * result of napspmv_apply on the same plan and vector.
+ * always runs alone, by napspmv_apply_ws).  Requests that arrive while slots
+ * are busy are admitted as slots free up, so their work overlaps the work
+ * already on the device.  Single-threaded: one caller drives a server.
+ * Every result is bitwise the result of napspmv_apply on the same plan and
+ * vector.
  *
+ * server_create makes no HIP call; the slots' streams, events and batch
+ * tables are made on the current GPU when the first plan is added.
+ * server_add_plan refuses a host-only plan (EINVAL) and a plan whose
+ * workspace exceeds a non-zero budget (ENOMEM: its requests could never
+ * run).  server_submit and server_replay take the caller's stream (void*
+ * hipStream_t, NULL = the default stream): the server records an event on it
+ * and runs the requests after the caller's work issued there before the call
+ * (writes of v, w).  Results are ready once server_wait (or poll, or replay)
+ * has reported the request done.
  * server_poll retires finished slots and admits queued requests; it returns
- * the number of requests completed by this call, or a negative error code.
+ * the number of requests completed by this call, or a negative error code
+ * (ENOMEM if requests are queued, none is running and no workspace can be
+ * allocated for them).
  * server_replay replays an arrival trace natively: request i (plan ids[i],
  * vectors v[i], w[i]) arrives arrival_ns[i] after the call starts; it
  * returns when every request is done, with latency_ns[i] = completion -
  * arrival and (if not NULL) batch_sizes[i] = the size of its batch.
+ * server_reserve allocates, for every resident plan, workspaces until it
+ * holds per_plan of them (within the budget; none is released), so that a
+ * later replay or submit need not allocate.
  * Messages of failed server calls: napspmv_server_last_error().
  */
 typedef struct napspmv_server_s *napspmv_server_t;
 NAPSPMV_API int napspmv_server_create(int slots, int max_batch, int64_t workspace_budget,
                                       napspmv_server_t *out);
 NAPSPMV_API int napspmv_server_add_plan(napspmv_server_t server, napspmv_plan_t plan, int *id_out);
+NAPSPMV_API int napspmv_server_reserve(napspmv_server_t server, int per_plan);
 NAPSPMV_API int napspmv_server_submit(napspmv_server_t server, int id, const void *v, void *w,
-                                      int64_t *ticket_out);
+                                      void *stream, int64_t *ticket_out);
 NAPSPMV_API int64_t napspmv_server_poll(napspmv_server_t server);
 NAPSPMV_API int napspmv_server_wait(napspmv_server_t server, int64_t ticket);
 NAPSPMV_API int napspmv_server_request_info(napspmv_server_t server, int64_t ticket,
                                             int64_t *submit_ns, int64_t *done_ns, int *batch_size);
 NAPSPMV_API int napspmv_server_replay(napspmv_server_t server, int64_t n, const int *ids,
                                       const int64_t *arrival_ns, const void *const *v,
-                                      void *const *w, int64_t *latency_ns, int *batch_sizes);
+                                      void *const *w, void *stream, int64_t *latency_ns,
+                                      int *batch_sizes);
 NAPSPMV_API int64_t napspmv_server_workspace_bytes(napspmv_server_t server);
 NAPSPMV_API const char *napspmv_server_last_error(void);
 NAPSPMV_API int napspmv_server_destroy(napspmv_server_t server);

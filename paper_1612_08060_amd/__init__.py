@@ -80,11 +80,12 @@ _SIGS = {
     "napspmv_plan_autotune": (I32, [P, P, P, P, I32, ctypes.c_char_p, P]),
     "napspmv_server_create": (I32, [I32, I32, I64, P]),
     "napspmv_server_add_plan": (I32, [P, P, P]),
-    "napspmv_server_submit": (I32, [P, I32, P, P, P]),
+    "napspmv_server_reserve": (I32, [P, I32]),
+    "napspmv_server_submit": (I32, [P, I32, P, P, P, P]),
     "napspmv_server_poll": (I64, [P]),
     "napspmv_server_wait": (I32, [P, I64]),
     "napspmv_server_request_info": (I32, [P, I64, P, P, P]),
-    "napspmv_server_replay": (I32, [P, I64, P, P, P, P, P, P]),
+    "napspmv_server_replay": (I32, [P, I64, P, P, P, P, P, P, P]),
     "napspmv_server_workspace_bytes": (I64, [P]),
     "napspmv_server_last_error": (ctypes.c_char_p, []),
     "napspmv_server_destroy": (I32, [P]),
@@ -425,11 +426,18 @@ class Server:
         self.plans.append(plan)
         return i.value
 
-    def submit(self, pid: int, v, w) -> int:
+    def reserve(self, per_plan: int):
+        """Pre-allocate up to ``per_plan`` workspaces of every resident plan."""
+        _scheck(load_library().napspmv_server_reserve(self._h, int(per_plan)))
+
+    def submit(self, pid: int, v, w, stream=None) -> int:
+        """Queue w = A_pid v after the work issued so far on ``stream``
+        (default: the current stream); returns a ticket."""
         p = self.plans[pid]
         t = ctypes.c_int64()
         _scheck(load_library().napspmv_server_submit(self._h, int(pid), p._vec_check(v, "v"),
-                                                     p._vec_check(w, "w"), ctypes.byref(t)))
+                                                     p._vec_check(w, "w"), _stream_handle(stream),
+                                                     ctypes.byref(t)))
         return t.value
 
     def poll(self) -> int:
@@ -446,8 +454,10 @@ class Server:
                                                            ctypes.byref(d), ctypes.byref(b)))
         return s.value, d.value, b.value
 
-    def replay(self, ids, arrival_ns, vs, ws_out):
-        """Replay an arrival trace natively; returns (latency_ns, batch_sizes)."""
+    def replay(self, ids, arrival_ns, vs, ws_out, stream=None):
+        """Replay an arrival trace natively, after the work issued so far on
+        ``stream`` (default: the current stream); returns (latency_ns,
+        batch_sizes)."""
         n = len(ids)
         ids_a = np.ascontiguousarray(ids, dtype=np.int32)
         arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
@@ -457,7 +467,8 @@ class Server:
         lat = np.empty(n, np.int64)
         bs = np.empty(n, np.int32)
         _scheck(load_library().napspmv_server_replay(self._h, n, ids_a.ctypes.data, arr.ctypes.data,
-                                                     hv, hw, lat.ctypes.data, bs.ctypes.data))
+                                                     hv, hw, _stream_handle(stream), lat.ctypes.data,
+                                                     bs.ctypes.data))
         return lat, bs
 
     @property

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "schedule.hpp"
+
 namespace napspmv {
 
 constexpr int kBlock = 256;
@@ -277,18 +279,28 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
         if (tid == 0) w[r0] = s;
         return;
     }
-    // Every load below is unconditional, on an index clamped into the block
-    // (an empty block reads its predecessor's last entry; no array is empty),
-    // so all of them can be in flight at once: a load under a per-lane
-    // condition makes the compiler wait for the loads before it.  Clamped
-    // lanes' values are discarded.
-    const int32_t klast = k1 > 0 ? k1 - 1 : 0;
+    if (k1 == k0) {
+        // A block without entries (rows whose part is empty, e.g. the zero
+        // block of a saddle-point matrix) loads nothing: the clamped loads
+        // below need an entry of the block itself, since a 16-bit column
+        // is an offset from this block's process.  The on-process part
+        // still writes its rows' zero sums; the off-process part leaves
+        // them as they are.
+        if (!REMOTE)
+            for (int32_t r = r0 + tid; r < r1; r += kBlock) store_out<NTW>((XT)0, w + r);
+        return;
+    }
+    // Every load below is unconditional, on an index clamped into the
+    // block's own entries [k0, k1) (non-empty here), so all of them can be
+    // in flight at once: a load under a per-lane condition makes the
+    // compiler wait for the loads before it.  Clamped lanes' values are
+    // discarded.
     int32_t c[U];
     XT a[U];
     int32_t sl[REMOTE ? U : 1];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int32_t k = min(k0 + u * kBlock + tid, klast);
+        const int32_t k = block_entry(k0, k1, u * kBlock + tid);
         c[u] = cbase + (int32_t)__builtin_nontemporal_load(col + k);
         a[u] = (XT)load_val(val, k);
         if (REMOTE) sl[REMOTE ? u : 0] = __builtin_nontemporal_load(slot + k);

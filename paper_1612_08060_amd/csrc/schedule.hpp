@@ -50,6 +50,15 @@ constexpr int64_t kPackScatterTail = 1024;
 void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks,
                  int64_t tail = kItemTail);
 
+// Entry that lane position q (0 <= q < the block's capacity) of a non-empty
+// row block [k0, k1) loads: q's own entry, clamped to the block's last one,
+// so that every lane can issue its loads unconditionally and every load
+// stays inside the block (a 16-bit column is an offset from the block's own
+// process).  Empty blocks load nothing.  constexpr: the kernels use it too.
+constexpr int32_t block_entry(int32_t k0, int32_t k1, int32_t q) {
+    return k0 + q < k1 ? k0 + q : k1 - 1;
+}
+
 // Work items covering [0, total) in order, pieces of at most `max_len`.
 void flat_items(int64_t total, int max_len, std::vector<int32_t> &items);
 

@@ -9,6 +9,9 @@
 //
 // Single-threaded by design: the caller drives it with submit/poll (or
 // replays a whole arrival trace natively with napspmv_server_replay).
+// Requests follow the caller's stream: submit and replay record a fence
+// event on it, and a slot waits for the latest fence before it runs a batch,
+// so the caller's writes of v (and w) before the call are seen.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,6 +51,7 @@ struct ServerSlot {
     napspmv_batch_t batch = nullptr;
     std::vector<int64_t> reqs;
     bool busy = false;
+    int64_t fence_seen = 0;  // the fence generation this slot's stream already waits for
 };
 
 struct ServerPlan {
@@ -61,12 +65,15 @@ struct ServerPlan {
 struct napspmv_server_s {
     int device = 0;
     int max_batch = 1;
+    int n_slots = 0;
     int64_t budget = 0, ws_in_use = 0;
     std::vector<ServerPlan> plans;
-    std::vector<ServerSlot> slots;
+    std::vector<ServerSlot> slots;   // created with the first device plan
     std::deque<int64_t> queue;
     std::vector<ServerRequest> reqs;
     int64_t completed = 0;
+    hipEvent_t fence = nullptr;      // recorded on the caller's stream by submit and replay
+    int64_t fence_gen = 0;           // how many times it was recorded
 };
 
 namespace {
@@ -99,6 +106,42 @@ int sguard(F &&f) {
 }
 
 int64_t ws_size(const ServerPlan &P) { return std::max<int64_t>(P.ws_bytes, 256); }
+
+// Streams, events and batch tables of the slots, on the current device: made
+// when the first device plan is added, so that creating a server and
+// refusing plans needs no GPU.
+void release_slot(ServerSlot &sl) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.batch) napspmv_batch_destroy(sl.batch);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    sl = ServerSlot();
+}
+
+void ensure_slots(napspmv_server_s *s) {
+    if (!s->slots.empty()) return;
+    std::vector<ServerSlot> made(s->n_slots);
+    try {
+        HIP_SOK(hipGetDevice(&s->device));
+        if (!s->fence) HIP_SOK(hipEventCreateWithFlags(&s->fence, hipEventDisableTiming));
+        for (ServerSlot &sl : made) {
+            HIP_SOK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+            HIP_SOK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+            const int brc = napspmv_batch_create(s->max_batch, &sl.batch);
+            if (brc != NAPSPMV_OK) throw Error(brc, napspmv_last_error());
+        }
+    } catch (...) {
+        for (ServerSlot &sl : made) release_slot(sl);
+        throw;
+    }
+    s->slots = std::move(made);
+}
+
+// Order the requests submitted so far after the caller's work on `stream`.
+void record_fence(napspmv_server_s *s, void *stream) {
+    HIP_SOK(hipEventRecord(s->fence, static_cast<hipStream_t>(stream)));
+    ++s->fence_gen;
+}
 
 // A workspace for plan `pi`: from its free list, or newly allocated if the
 // budget allows (idle workspaces of other plans are released to make room);
@@ -185,7 +228,20 @@ void admit(napspmv_server_s *s) {
             it = s->queue.erase(it);
             if (P.solo) break;
         }
-        if (take.empty()) return;
+        if (take.empty()) {
+            // nothing running will ever release a workspace: the queued
+            // requests could wait forever
+            bool running = false;
+            for (const ServerSlot &o : s->slots) running = running || o.busy;
+            if (!running)
+                throw Error(NAPSPMV_ENOMEM, "no workspace can be allocated for the queued requests "
+                                            "and none is in use");
+            return;
+        }
+        if (sl.fence_seen < s->fence_gen) {
+            HIP_SOK(hipStreamWaitEvent(sl.stream, s->fence, 0));
+            sl.fence_seen = s->fence_gen;
+        }
         const int n = (int)take.size();
         std::vector<napspmv_plan_t> plans(n);
         std::vector<void *> wss(n), ws_out(n);
@@ -222,22 +278,11 @@ int napspmv_server_create(int slots, int max_batch, int64_t workspace_budget,
         return sfail(NAPSPMV_EINVAL, "need 1 <= slots <= 64, 1 <= max_batch <= 4096, budget >= 0");
     napspmv_server_s *s = new (std::nothrow) napspmv_server_s();
     if (!s) return sfail(NAPSPMV_ENOMEM, "host allocation failed");
-    const int rc = sguard([&]() {
-        HIP_SOK(hipGetDevice(&s->device));
-        s->max_batch = max_batch;
-        s->budget = workspace_budget;
-        s->slots.resize(slots);
-        for (ServerSlot &sl : s->slots) {
-            HIP_SOK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
-            HIP_SOK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-            const int brc = napspmv_batch_create(max_batch, &sl.batch);
-            if (brc != NAPSPMV_OK) throw Error(brc, napspmv_last_error());
-        }
-        *out = s;
-        return NAPSPMV_OK;
-    });
-    if (rc != NAPSPMV_OK) napspmv_server_destroy(s);
-    return rc;
+    s->max_batch = max_batch;
+    s->n_slots = slots;
+    s->budget = workspace_budget;
+    *out = s;
+    return NAPSPMV_OK;
 }
 
 int napspmv_server_add_plan(napspmv_server_t s, napspmv_plan_t plan, int *id_out) {
@@ -247,8 +292,20 @@ int napspmv_server_add_plan(napspmv_server_t s, napspmv_plan_t plan, int *id_out
     ServerPlan P;
     P.plan = plan;
     P.ws_bytes = wsb;
+    // a request whose workspace can never fit would wait forever
+    if (s->budget > 0 && ws_size(P) > s->budget)
+        return sfail(NAPSPMV_ENOMEM, "the plan's workspace (" + std::to_string(ws_size(P)) +
+                                         " bytes) exceeds the server's workspace budget (" +
+                                         std::to_string(s->budget) + ")");
     napspmv_stats_t st;
     napspmv_plan_stats(plan, &st);
+    if (st.flags & NAPSPMV_HOST_ONLY)
+        return sfail(NAPSPMV_EINVAL, "plan was built with NAPSPMV_HOST_ONLY");
+    const int rc = sguard([&]() {
+        ensure_slots(s);
+        return NAPSPMV_OK;
+    });
+    if (rc != NAPSPMV_OK) return rc;
     P.key_dtype = st.dtype;
     P.key_cap = napspmv_plan_get_param(plan, NAPSPMV_PARAM_BLOCK_NNZ);
     P.key_win = napspmv_plan_get_param(plan, NAPSPMV_PARAM_VWINDOW);
@@ -259,9 +316,15 @@ int napspmv_server_add_plan(napspmv_server_t s, napspmv_plan_t plan, int *id_out
     return NAPSPMV_OK;
 }
 
-int napspmv_server_submit(napspmv_server_t s, int id, const void *v, void *w, int64_t *ticket) {
+int napspmv_server_submit(napspmv_server_t s, int id, const void *v, void *w, void *stream,
+                          int64_t *ticket) {
     if (!s || !v || !w || !ticket) return sfail(NAPSPMV_EINVAL, "NULL argument");
     if (id < 0 || id >= (int)s->plans.size()) return sfail(NAPSPMV_EINVAL, "unknown plan id");
+    const int rc = sguard([&]() {
+        record_fence(s, stream);
+        return NAPSPMV_OK;
+    });
+    if (rc != NAPSPMV_OK) return rc;
     ServerRequest R;
     R.plan = id;
     R.v = v;
@@ -306,13 +369,14 @@ int napspmv_server_request_info(napspmv_server_t s, int64_t ticket, int64_t *sub
 }
 
 int napspmv_server_replay(napspmv_server_t s, int64_t n, const int *ids, const int64_t *arrival_ns,
-                          const void *const *v, void *const *w, int64_t *latency_ns,
+                          const void *const *v, void *const *w, void *stream, int64_t *latency_ns,
                           int *batch_sizes) {
     if (!s || n < 0 || (n > 0 && (!ids || !arrival_ns || !v || !w || !latency_ns)))
         return sfail(NAPSPMV_EINVAL, "NULL argument");
     for (int64_t i = 0; i < n; ++i)
         if (ids[i] < 0 || ids[i] >= (int)s->plans.size()) return sfail(NAPSPMV_EINVAL, "unknown plan id");
     return sguard([&]() {
+        if (n > 0) record_fence(s, stream);   // every vector was written before the call
         const int64_t first = (int64_t)s->reqs.size();
         const int64_t t0 = now_ns();
         for (int64_t i = 0; i < n; ++i) {
@@ -343,6 +407,24 @@ int napspmv_server_replay(napspmv_server_t s, int64_t n, const int *ids, const i
     });
 }
 
+int napspmv_server_reserve(napspmv_server_t s, int per_plan) {
+    if (!s || per_plan < 0) return sfail(NAPSPMV_EINVAL, "bad server or count");
+    return sguard([&]() {
+        for (ServerPlan &P : s->plans) {
+            const int64_t need = ws_size(P);
+            while ((int)P.all_ws.size() < per_plan &&
+                   (s->budget == 0 || s->ws_in_use + need <= s->budget)) {
+                void *w = nullptr;
+                HIP_SOK(hipMalloc(&w, (size_t)need));
+                s->ws_in_use += need;
+                P.all_ws.push_back(w);
+                P.free_ws.push_back(w);
+            }
+        }
+        return NAPSPMV_OK;
+    });
+}
+
 int64_t napspmv_server_workspace_bytes(napspmv_server_t s) {
     if (!s) return sfail(NAPSPMV_EINVAL, "server is NULL");
     return s->ws_in_use;
@@ -352,12 +434,8 @@ const char *napspmv_server_last_error(void) { return g_server_error.c_str(); }
 
 int napspmv_server_destroy(napspmv_server_t s) {
     if (!s) return NAPSPMV_OK;
-    for (ServerSlot &sl : s->slots) {
-        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.batch) napspmv_batch_destroy(sl.batch);
-        if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    }
+    for (ServerSlot &sl : s->slots) release_slot(sl);
+    if (s->fence) (void)hipEventDestroy(s->fence);
     for (ServerPlan &P : s->plans)
         for (void *w : P.all_ws) (void)hipFree(w);
     delete s;

@@ -108,10 +108,71 @@ static int check_blocks_and_sort() {
     return 0;
 }
 
+// Saddle-point matrix [[H, B^T], [B, 0]] (H: n1 x n1 banded, B: m x n1, m < n1)
+// with a process boundary at row n1: the B rows have no on-process entry, so
+// their on-process row blocks are empty.  Every load of a non-empty block
+// (block_entry, the clamp the kernels use) must stay among the block's own
+// entries, whose columns its own process owns: a 16-bit column offset from
+// the block's process then stays below n.  Returns the empty blocks seen.
+static int check_saddle_loads(int64_t &empty_blocks) {
+    empty_blocks = 0;
+    std::mt19937 rng(11);
+    for (int trial = 0; trial < 12; ++trial) {
+        const int n1 = 96 + 32 * (trial % 3), m = 40 + 8 * (trial % 4), n = n1 + m;
+        // processes: n1 split in 3, then the m B rows in 1 or 2
+        std::vector<int64_t> starts = {0, n1 / 3, 2 * n1 / 3, n1};
+        if (trial % 2) starts.push_back(n1 + m / 2);
+        starts.push_back(n);
+        auto owner = [&](int64_t j) {
+            return (int64_t)(std::upper_bound(starts.begin(), starts.end(), j) - starts.begin()) - 1;
+        };
+        std::vector<std::vector<int32_t>> rows(n);
+        for (int i = 0; i < n1; ++i) {
+            for (int j = std::max(0, i - 3); j <= std::min(n1 - 1, i + 3); ++j) rows[i].push_back(j);
+        }
+        for (int q = 0; q < m; ++q) {
+            for (int e = 0; e < 4; ++e) {
+                const int j = (int)(rng() % n1);
+                rows[n1 + q].push_back(j);          // B
+                rows[j].push_back(n1 + q);          // B^T
+            }
+        }
+        // on-process part in stored order
+        std::vector<int32_t> rowptr(n + 1, 0), col;
+        for (int i = 0; i < n; ++i) {
+            for (int32_t j : rows[i])
+                if (owner(j) == owner(i)) col.push_back(j);
+            rowptr[i + 1] = (int32_t)col.size();
+        }
+        for (int cap : {16, 64, 4096}) {
+            std::vector<int32_t> rb, bp;
+            napspmv::row_blocks_per_process(rowptr.data(), starts, cap, 1024, rb, bp);
+            for (size_t b = 0; b + 1 < rb.size(); ++b) {
+                const int32_t k0 = bp[b], k1 = bp[b + 1];
+                const int64_t t = owner(rb[b]);
+                if (k1 == k0) {
+                    ++empty_blocks;
+                    continue;
+                }
+                for (int32_t q = 0; q < cap; ++q) {
+                    const int32_t k = napspmv::block_entry(k0, k1, q);
+                    if (k < k0 || k >= k1) return fail("load outside the block", trial, q);
+                    const int64_t off = col[k] - starts[t];
+                    if (owner(col[k]) != t || starts[t] + off >= n)
+                        return fail("column outside the block's process", trial, k);
+                }
+            }
+        }
+    }
+    return 0;
+}
+
 int main() {
+    int64_t empty = 0;
     if (check_merge(napspmv::kItemTail) || check_merge(napspmv::kPackScatterTail) ||
-        check_blocks_and_sort())
+        check_blocks_and_sort() || check_saddle_loads(empty))
         return 1;
+    if (empty == 0) return fail("saddle matrices produced no empty block", 0, 0);
     std::printf("ok\n");
     return 0;
 }

@@ -241,3 +241,26 @@ def test_index_limits_are_unsupported():
     rc = so.napspmv_plan_create(rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, 0, 1, 1, 1,
                                 0, None, 0x1, ctypes.byref(handle), None)
     assert rc == -1
+
+
+def test_server_refuses_plans_that_can_never_run():
+    """A plan whose workspace exceeds the server's budget is refused with
+    ENOMEM when it is added (its requests would otherwise wait forever), and
+    a host-only plan with EINVAL; neither refusal needs a GPU."""
+    import ctypes
+    so = lib.load_library()
+    a = kkt_like(1 << 10, 2)
+    with lib.Plan(a.rowptr, a.col, a.val, a.n, 4, 2, host_only=True) as p:
+        wsb = p.workspace_bytes
+        assert wsb > 256
+        srv = ctypes.c_void_p()
+        assert so.napspmv_server_create(2, 4, wsb - 1, ctypes.byref(srv)) == 0
+        pid = ctypes.c_int(-1)
+        rc = so.napspmv_server_add_plan(srv, p._h, ctypes.byref(pid))
+        assert rc == -2 and b"budget" in so.napspmv_server_last_error() and pid.value == -1
+        assert so.napspmv_server_destroy(srv) == 0
+        # a budget that fits: the host-only plan is still refused
+        assert so.napspmv_server_create(2, 4, wsb, ctypes.byref(srv)) == 0
+        rc = so.napspmv_server_add_plan(srv, p._h, ctypes.byref(pid))
+        assert rc == -1 and b"HOST_ONLY" in so.napspmv_server_last_error()
+        assert so.napspmv_server_destroy(srv) == 0

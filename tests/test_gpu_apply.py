@@ -257,6 +257,41 @@ def test_remainder_rows_and_empty_matrix():
     assert np.array_equal(w, np.zeros(64)) and g.size == 0
 
 
+def _saddle(n1, m, seed):
+    """[[H, B^T], [B, 0]]: H banded n1 x n1, B m x n1 with 4 random columns
+    per row, a zero m x m block; rows store ascending columns."""
+    rng = np.random.default_rng(seed)
+    rows = [set(range(max(0, i - 2), min(n1, i + 3))) for i in range(n1)] + [set() for _ in range(m)]
+    for q in range(m):
+        for j in rng.integers(0, n1, 4):
+            rows[n1 + q].add(int(j))
+            rows[int(j)].add(n1 + q)
+    rp = np.zeros(n1 + m + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.concatenate([np.array(sorted(r), np.int32) for r in rows])
+    return CSR(n1 + m, rp, col, vec_normal(col.size, seed + 1))
+
+
+@pytest.mark.parametrize("block_nnz", [1024, 4096])
+def test_saddle_point_zero_block_at_process_boundary(block_nnz):
+    """The B rows form whole processes and own no column they use, so their
+    on-process row blocks are empty; their clamped loads must not reach past
+    v (16-bit columns are offsets from the block's own process)."""
+    a = _saddle(3000, 1000, 8)
+    starts = np.array([0, 1000, 2000, 3000, 4000], np.int64)
+    v = vec_normal(a.n, 9)
+    ref = _split(a, v, 4, starts)
+    for mode in ("standard", "nap"):
+        for dtype in ("f64", "f32", "bf16"):
+            w, g, gc = _run(a, v, 4, 2, mode, dtype=dtype, row_starts=starts,
+                            params={"block_nnz": block_nnz})
+            _check_ghosts(g, gc, v, dtype)
+            if dtype == "f64":
+                assert np.array_equal(w, ref), mode
+            else:
+                assert _relerr(w, oracle_spmv.spmv(a, v)) <= TOL[dtype], (mode, dtype)
+
+
 def test_stages_streams_and_graph():
     a = kkt_like(1 << 14, 3)
     v = torch.from_numpy(vec_normal(a.n, 4)).to(DEV)

@@ -1,12 +1,16 @@
 """The serving engine (napspmv_server_*) on an MI355X: many resident plans of
 mixed value types and modes, requests admitted into slots as slots and
 workspace memory free up, batched per kernel group.  Every request's result
-must be bitwise the result of the same apply done alone."""
+must be bitwise the result of the same apply done alone, and must match the
+oracle: float64 bitwise its split-order product (algorithm standard_spmv's
+row sums), float32 values within 1e-5 and bfloat16 values within 2e-2
+normwise of the float64 product."""
 import numpy as np
 import pytest
 import torch
 
 import paper_1612_08060_amd as nap
+from oracle import spmv as oracle_spmv
 from workloads import (bf16_bits, kkt_like, laplacian_2d, laplacian_3d, poisson_arrivals,
                        random_pattern, stencil_27, to_f32, vec_uniform)
 
@@ -30,15 +34,29 @@ def _mats():
     return out
 
 
+TOL = {"f32": 1e-5, "bf16": 2e-2}
+
+
+def _check_oracle(a, n_p, dt, v64, got):
+    """One served result against the oracle (float64 A and v)."""
+    w = got.cpu().numpy().astype(np.float64)
+    if dt == "f64":
+        assert np.array_equal(w, oracle_spmv.spmv_split(a, v64, n_p))
+    else:
+        ref = oracle_spmv.spmv(a, v64)
+        assert np.linalg.norm(w - ref) / max(np.linalg.norm(ref), 1e-300) <= TOL[dt]
+
+
 def _vec(x, dt):
     return torch.from_numpy(np.ascontiguousarray(x if dt == "f64" else to_f32(x))).to(DEV)
 
 
 def _requests(mats, n, seed):
+    """(matrix ids, device vectors, the float64 host vectors they came from)."""
     rng = np.random.default_rng(seed)
     ids = rng.integers(0, len(mats), size=n)
-    vs = [_vec(vec_uniform(mats[i][0].n, 100 + k), mats[i][2]) for k, i in enumerate(ids)]
-    return ids, vs
+    v64 = [vec_uniform(mats[i][0].n, 100 + k) for k, i in enumerate(ids)]
+    return ids, [_vec(x, mats[i][2]) for x, i in zip(v64, ids)], v64
 
 
 def _solo(mats, ids, vs):
@@ -55,7 +73,7 @@ def _solo(mats, ids, vs):
                                                     (3, 6, 2 << 20)])
 def test_submit_poll_matches_solo(slots, max_batch, budget):
     mats = _mats()
-    ids, vs = _requests(mats, 60, seed=slots * 10 + max_batch)
+    ids, vs, v64 = _requests(mats, 60, seed=slots * 10 + max_batch)
     ref = _solo(mats, ids, vs)
     srv = nap.Server(slots=slots, max_batch=max_batch, workspace_budget=budget)
     pids = [srv.add(p) for _, p, _ in mats]
@@ -71,6 +89,8 @@ def test_submit_poll_matches_solo(slots, max_batch, budget):
         assert done >= sub and 1 <= bs <= max_batch
         sizes.append(bs)
         assert torch.equal(outs[k], ref[k]), k
+        a, p, dt = mats[ids[k]]
+        _check_oracle(a, p.n_p, dt, v64[k], outs[k])
     if max_batch > 1:
         assert max(sizes) > 1                 # requests were batched
     if budget:
@@ -85,7 +105,8 @@ def test_replay_trace_matches_solo():
     srv = nap.Server(slots=4, max_batch=8)
     pids = [srv.add(p) for _, p, _ in mats]
     ids, arrival = poisson_arrivals(200, 20000.0, len(mats), seed=9)
-    vs = [_vec(vec_uniform(mats[i][0].n, 500 + k), mats[i][2]) for k, i in enumerate(ids)]
+    v64 = [vec_uniform(mats[i][0].n, 500 + k) for k, i in enumerate(ids)]
+    vs = [_vec(x, mats[i][2]) for x, i in zip(v64, ids)]
     ref = _solo(mats, ids, vs)
     outs = [torch.full_like(v, float("nan")) for v in vs]
     lat, bs = srv.replay([pids[i] for i in ids], arrival, vs, outs)
@@ -93,6 +114,8 @@ def test_replay_trace_matches_solo():
     assert np.all(lat > 0) and np.all(bs >= 1)
     for k in range(len(ids)):
         assert torch.equal(outs[k], ref[k]), k
+        a, p, dt = mats[ids[k]]
+        _check_oracle(a, p.n_p, dt, v64[k], outs[k])
     srv.close()
     for _, p, _ in mats:
         p.close()
@@ -111,7 +134,10 @@ def test_mixed_kernel_groups_and_solo_plans():
     """Plans that differ in REMOTE_NNZ share a kernel group (one second
     launch per block size), plans that differ in BLOCK_NNZ do not; an
     explicit-hop NAP plan, a three-way plan and a strided plan run alone or
-    in their groups; every result equals the apply done alone."""
+    in their groups; every result equals the apply done alone and, bit for
+    bit, the oracle's product in the plan's summation order (the three-way
+    plan's is algorithm NAPSpMV's; the strided plan works in process-major
+    order)."""
     a1, a2, a3 = kkt_like(7000, 11), kkt_like(5000, 12), laplacian_2d(70, 50)
     plans = [nap.Plan(a1.rowptr, a1.col, a1.val, a1.n, 16, 4, mode="standard"),
              nap.Plan(a1.rowptr, a1.col, a1.val, a1.n, 16, 4, mode="standard"),
@@ -122,10 +148,12 @@ def test_mixed_kernel_groups_and_solo_plans():
                       variant=("owner_map", "dedup"))]
     plans[1].set_param("remote_nnz", 2048)
     plans[5].set_param("block_nnz", 1024)
+    mats = [a1, a1, a2, a2, a3, a3]
     sizes = [p.n for p in plans]
     rng = np.random.default_rng(3)
     ids = rng.integers(0, len(plans), size=48)
-    vs = [_vec(vec_uniform(sizes[i], 900 + k), "f64") for k, i in enumerate(ids)]
+    v64 = [vec_uniform(sizes[i], 900 + k) for k, i in enumerate(ids)]
+    vs = [_vec(x, "f64") for x in v64]
     ref = []
     for i, v in zip(ids, vs):
         w = torch.empty_like(v)
@@ -144,6 +172,18 @@ def test_mixed_kernel_groups_and_solo_plans():
         if ids[k] in (2, 3):
             assert bs == 1                      # never batched
         assert torch.equal(outs[k], ref[k]), k
+        i, a, p = int(ids[k]), mats[ids[k]], plans[ids[k]]
+        got = outs[k].cpu().numpy()
+        if i == 3:
+            assert np.array_equal(got, oracle_spmv.spmv_split3(a, v64[k], p.n_p, p.ppn))
+        elif i == 4:
+            rows = p.rows()                     # position k holds row rows[k]
+            v_nat = np.empty(a.n)
+            v_nat[rows] = v64[k]
+            w_nat = oracle_spmv.spmv_split(a, v_nat, p.n_p, strided=True)
+            assert np.array_equal(got, w_nat[rows])
+        else:
+            assert np.array_equal(got, oracle_spmv.spmv_split(a, v64[k], p.n_p))
     srv.close()
     for p in plans:
         p.close()

@@ -4,7 +4,10 @@ permutation of items and row blocks, proportional per XCD range, no item in
 a range's tail), per-process row blocks (cover, never span two processes,
 respect the entry and row limits) and the gather-order sort of off-process
 blocks (sorted, slots a permutation pointing at each entry's stored
-position, long single-row blocks left in stored order)."""
+position, long single-row blocks left in stored order), and, on saddle-point
+matrices whose zero block starts at a process boundary, that every load a
+non-empty on-process block issues (the kernels' own clamp) stays among the
+block's entries, whose columns the block's process owns."""
 import os
 import shutil
 import subprocess
