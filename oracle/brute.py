@@ -128,3 +128,64 @@ def nap_sets(csr, n_p: int, ppn: int, row_starts=None, strided: bool = False) ->
                 J2[(p, s)] = loc
     return {"N": N, "E": E, "send_rank": send_rank, "recv_rank": recv_rank,
             "I": I, "J0": J0, "J1": J1, "J2": J2}
+
+
+def socket_sets(csr, n_p: int, ppn: int, pps: int, row_starts=None) -> dict:
+    """The socket routes of the three intra-node steps (reading in
+    ``plan_ref``), each set straight from its quantifier over the steps' J
+    sets of ``nap_sets``, the mapping from a dense socket-to-socket volume
+    matrix and ``numpy.lexsort``.  Returns {step: {part: {(src, dst):
+    sorted list}}} for step in J0, J1, J2 and part in on, gather, cross,
+    scatter."""
+    b = nap_sets(csr, n_p, ppn, row_starts)
+    n_sock = n_p // pps
+    per_node = ppn // pps
+    sock = lambda r: r // pps  # noqa: E731
+    out = {}
+    for key in ("J0", "J1", "J2"):
+        J = b[key]
+        on = {k: v for k, v in J.items() if sock(k[0]) == sock(k[1])}
+        F = {}
+        for s in range(n_sock):
+            for s2 in range(n_sock):
+                if s2 == s or s // per_node != s2 // per_node:
+                    continue
+                idx = sorted({j for (x, y), v in J.items() if sock(x) == s and sock(y) == s2
+                              for j in v})
+                if idx:
+                    F[(s, s2)] = idx
+        vol = np.zeros((n_sock, n_sock), dtype=np.int64)
+        for (s, s2), idx in F.items():
+            vol[s, s2] = len(idx)
+        send, recv = {}, {}
+        for s in range(n_sock):
+            partners = np.flatnonzero(vol[s] > 0)
+            for k, s2 in enumerate(partners[np.lexsort((partners, -vol[s, partners]))]):
+                send[(s, int(s2))] = s * pps + k % pps
+            senders = np.flatnonzero(vol[:, s] > 0)
+            for k, s2 in enumerate(senders[np.lexsort((senders, -vol[s, senders]))]):
+                recv[(int(s2), s)] = s * pps + pps - 1 - k % pps
+        cross = {(send[k], recv[k]): v for k, v in F.items()}
+        gather, scatter = {}, {}
+        for h in range(n_p):
+            for q in range(sock(h) * pps, (sock(h) + 1) * pps):
+                if q == h:
+                    continue
+                # indices h holds for another socket whose sender is q
+                idx = sorted({j for (s, s2), v in F.items() if send[(s, s2)] == q
+                              for j in v
+                              if any(j in J.get((h, y), ()) for y in range(s2 * pps, (s2 + 1) * pps))})
+                if idx:
+                    gather[(h, q)] = idx
+        for y in range(n_p):
+            for r in range(sock(y) * pps, (sock(y) + 1) * pps):
+                if r == y:
+                    continue
+                # indices y needs from another socket whose receiver is r
+                idx = sorted({j for (s, s2), v in F.items() if recv[(s, s2)] == r
+                              for j in v
+                              if any(j in J.get((x, y), ()) for x in range(s * pps, (s + 1) * pps))})
+                if idx:
+                    scatter[(r, y)] = idx
+        out[key] = {"on": on, "gather": gather, "cross": cross, "scatter": scatter}
+    return out

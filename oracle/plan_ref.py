@@ -63,6 +63,26 @@ Variants (none is the default; each leaves every ghost value and w unchanged):
   {3}, which that step also carries).
 * ``three_way``: no change to any set; the product is summed in three parts
   as algorithm NAPSpMV writes it (``spmv.spmv_split3``).
+
+A third hierarchy level (section 6 names splitting intra-node messages into
+on-socket and off-socket ones as future work, and the introduction says
+socket information could be used the way node information is): sockets of
+``pps`` consecutive ranks inside a node.  Reading (``socket_plan``): each of
+the three intra-node steps keeps its messages whose two ranks share a socket
+(``on``), and routes the others the way section 4 routes inter-node messages,
+one level down: per ordered socket pair (s, s') of a node, F(s, s') is the
+sorted union of the indices its off-socket messages carry from s to s'
+(deduplicated); one process of s sends F(s, s') to one process of s'
+(``cross``), chosen by the node-level mapping rule applied to the sockets of
+the node (partners of s by |F(s, .)| descending, ties by ascending socket,
+the k-th sent by the k mod pps-th process of s; senders to s by the same key,
+the k-th received by process pps-1-(k mod pps) of s); the holder of each
+index (its owner for the on_node -> off_node and fully local steps, the
+inter-node receiver for the off_node -> on_node step; unique within a node)
+hands it to the socket sender first (``gather``, deduplicated per pair), and
+the socket receiver forwards it to every other process of s' whose message
+carried it (``scatter``), using its own values directly.  One socket per node
+(pps = ppn) or one process per socket (pps = 1) leaves the two-level plan.
 """
 from __future__ import annotations
 
@@ -72,6 +92,8 @@ import numpy as np
 
 PHASES = ("INTER", "L0", "L1", "L2")
 VARIANTS = frozenset({"owner_map", "dedup", "split", "three_way"})
+SOCKET_PARTS = ("on", "gather", "cross", "scatter")
+SOCKET_PHASES = tuple(f"{ph}_{part}" for ph in ("L0", "L1", "L2") for part in SOCKET_PARTS)
 
 
 class Layout:
@@ -311,6 +333,70 @@ def nap_plan(csr, lay: Layout, variant=()) -> dict:
         "phases": {"INTER": _canon(I), "L0": _canon(J0), "L1": _canon(J1),
                    "L2": _canon(J2)},
     }
+
+
+def socket_route(lay: Layout, pps: int, msgs: list) -> dict:
+    """One intra-node step's messages [(x, y, idx)] routed over sockets of
+    ``pps`` consecutive ranks (see the module docstring): returns the
+    messages of its four parts, {"on", "gather", "cross", "scatter"}."""
+    if pps < 1 or lay.ppn % pps:
+        raise ValueError("pps must divide ppn")
+
+    def sock(r):
+        return r // pps
+
+    on, F, holder, need = [], defaultdict(set), {}, defaultdict(set)
+    for x, y, idx in msgs:
+        assert lay.node(x) == lay.node(y), "an intra-node step"
+        if sock(x) == sock(y):
+            on.append((x, y, tuple(idx)))
+            continue
+        for j in idx:
+            F[(sock(x), sock(y))].add(j)
+            if holder.setdefault((sock(x), j), x) != x:
+                raise AssertionError(f"index {j} held by two ranks of socket {sock(x)}")
+            need[(sock(x), sock(y), j)].add(y)
+
+    def order(s, partners):
+        return sorted(partners, key=lambda b: (-len(F.get((s, b), ())), b))
+
+    sender, receiver = {}, {}
+    sockets = sorted({a for a, _ in F} | {b for _, b in F})
+    for s in sockets:
+        for k, b in enumerate(order(s, [b for (a, b) in F if a == s])):
+            sender[(s, b)] = s * pps + k % pps
+        for k, a in enumerate(order(s, [a for (a, b) in F if b == s])):
+            receiver[(a, s)] = s * pps + pps - 1 - k % pps
+    cross = {(sender[k], receiver[k]): set(v) for k, v in F.items()}
+    gather, scatter = defaultdict(set), defaultdict(set)
+    for (a, b), idx in F.items():
+        q, r = sender[(a, b)], receiver[(a, b)]
+        for j in idx:
+            h = holder[(a, j)]
+            if h != q:
+                gather[(h, q)].add(j)
+            for y in need[(a, b, j)]:
+                if y != r:
+                    scatter[(r, y)].add(j)
+    return {"on": sorted(on), "gather": _canon(gather), "cross": _canon(cross),
+            "scatter": _canon(scatter), "F": {k: sorted(v) for k, v in F.items()},
+            "sender": sender, "receiver": receiver}
+
+
+def socket_plan(csr, lay: Layout, pps: int) -> dict:
+    """The NAP plan with a third hierarchy level: sockets of ``pps``
+    consecutive ranks route the three intra-node steps (socket_route).  The
+    two-level phases stay as they are (they say what each step delivers);
+    the socket phases "L0_on", ..., "L2_scatter" say how."""
+    out = nap_plan(csr, lay)
+    routes = {}
+    for ph in ("L0", "L1", "L2"):
+        routes[ph] = socket_route(lay, pps, out["phases"][ph])
+        for part in SOCKET_PARTS:
+            out["phases"][f"{ph}_{part}"] = routes[ph][part]
+    out["pps"] = pps
+    out["socket_routes"] = routes
+    return out
 
 
 def plan(csr, lay: Layout, mode: str, variant=()) -> dict:

@@ -18,6 +18,8 @@ import numpy as np
 
 PHASES = ("INTER", "L0", "L1", "L2")
 VARIANTS = frozenset({"owner_map", "dedup", "split", "three_way"})
+SOCKET_PARTS = ("on", "gather", "cross", "scatter")
+SOCKET_PHASES = tuple(f"{ph}_{part}" for ph in ("L0", "L1", "L2") for part in SOCKET_PARTS)
 
 
 def row_starts(n: int, n_p: int, given=None) -> np.ndarray:
@@ -224,6 +226,96 @@ def plan(csr, n_p: int, ppn: int, mode: str, given_starts=None, variant=(),
     if mode == "nap":
         return nap_plan(csr, n_p, ppn, given_starts, variant, strided)
     raise ValueError(mode)
+
+
+def _select(phase, keep):
+    """The messages of a phase for which keep (one bool per message) holds."""
+    src, dst, ptr, idx = phase
+    k = np.flatnonzero(keep)
+    sizes = np.diff(ptr)[k]
+    take = np.repeat(ptr[k], sizes) + (np.arange(int(sizes.sum())) -
+                                       np.repeat(np.cumsum(sizes) - sizes, sizes))
+    return (src[k].astype(np.int32), dst[k].astype(np.int32),
+            np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64),
+            idx[take.astype(np.int64)].astype(np.int32))
+
+
+def socket_route(phase, n_p: int, pps: int) -> dict:
+    """One intra-node step routed over sockets of ``pps`` consecutive ranks
+    (reading in ``plan_ref``'s module docstring): the messages whose ranks
+    share a socket stay (``on``); per ordered socket pair (a, b) the union
+    F(a, b) of the others' indices goes from one sender of a to one
+    receiver of b (``cross``), the holders hand it to the sender first
+    (``gather``) and the receiver forwards it (``scatter``)."""
+    src, dst, ptr, idx = phase
+    sizes = np.diff(ptr)
+    x = np.repeat(src.astype(np.int64), sizes)
+    y = np.repeat(dst.astype(np.int64), sizes)
+    j = idx.astype(np.int64)
+    on = _select(phase, src // pps == dst // pps)
+    off = (x // pps) != (y // pps)
+    x, y, j = x[off], y[off], j[off]
+    a, b = x // pps, y // pps
+    n_sock = n_p // pps
+    big = int(j.max()) + 1 if j.size else 1
+    # F(a, b): unique (a, b, j); the holder of (a, j) is unique
+    fkey = np.unique((a * n_sock + b) * big + j)
+    fab, fj = fkey // big, fkey % big
+    fa, fb = fab // n_sock, fab % n_sock
+    hkey, hfirst = np.unique(a * big + j, return_index=True)
+    hold = x[hfirst]
+    if np.unique(a * big + j).size != np.unique((a * big + j) * n_p + x).size:
+        raise AssertionError("an index held by two ranks of one socket")
+    # socket pairs and their volumes
+    pairs, vol = np.unique(fab, return_counts=True)
+    pa, pb = pairs // n_sock, pairs % n_sock
+    # sender: partners b of a by (|F(a, b)| desc, b asc), k-th -> a*pps + k mod pps
+    o = np.lexsort((pb, -vol, pa))
+    rank = np.empty(pairs.size, np.int64)
+    heads = np.concatenate([[0], np.flatnonzero(np.diff(pa[o]) != 0) + 1])
+    run = np.arange(pairs.size) - np.repeat(heads, np.diff(np.concatenate([heads, [pairs.size]])))
+    rank[o] = run
+    sender = pa * pps + rank % pps
+    # receiver: senders a of b by (|F(b, a)| desc, a asc), k-th -> b*pps + pps-1 - k mod pps
+    rev = pb * n_sock + pa
+    pos = np.searchsorted(pairs, rev)
+    back = np.where((pos < pairs.size) & (pairs[np.minimum(pos, pairs.size - 1)] == rev),
+                    vol[np.minimum(pos, pairs.size - 1)], 0)
+    o = np.lexsort((pa, -back, pb))
+    heads = np.concatenate([[0], np.flatnonzero(np.diff(pb[o]) != 0) + 1])
+    run = np.arange(pairs.size) - np.repeat(heads, np.diff(np.concatenate([heads, [pairs.size]])))
+    rank[o] = run
+    receiver = pb * pps + pps - 1 - rank % pps
+    # cross: one message per socket pair
+    pi = np.searchsorted(pairs, fab)
+    cross = _segments(sender[pi], receiver[pi], fj)
+    # gather: holder -> sender, unique per pair
+    h = hold[np.searchsorted(hkey, fa * big + fj)]
+    q = sender[pi]
+    g = h != q
+    gk = np.unique((h[g] * n_p + q[g]) * big + fj[g])
+    gather = _segments(gk // big // n_p, gk // big % n_p, gk % big)
+    # scatter: receiver -> every other rank that needs the index
+    r = receiver[np.searchsorted(pairs, a * n_sock + b)]
+    sc = r != y
+    sk = np.unique((r[sc] * n_p + y[sc]) * big + j[sc])
+    scatter = _segments(sk // big // n_p, sk // big % n_p, sk % big)
+    return {"on": on, "gather": gather, "cross": cross, "scatter": scatter}
+
+
+def socket_plan(csr, n_p: int, ppn: int, pps: int, given_starts=None,
+                strided: bool = False) -> dict:
+    """nap_plan plus the socket routes of its three intra-node steps
+    (phases "L0_on" ... "L2_scatter")."""
+    if pps < 1 or ppn % pps:
+        raise ValueError("pps must divide ppn")
+    out = nap_plan(csr, n_p, ppn, given_starts, (), strided)
+    for ph in ("L0", "L1", "L2"):
+        route = socket_route(out["phases"][ph], n_p, pps)
+        for part in SOCKET_PARTS:
+            out["phases"][f"{ph}_{part}"] = route[part]
+    out["pps"] = pps
+    return out
 
 
 def phase_stats(phase, n_p: int) -> dict:

@@ -69,28 +69,88 @@ def simulate_standard(csr, lay: Layout, plan: dict, v):
     return ghost_vals, w
 
 
+def _route_socket(lay: Layout, ph: dict, step: str, held, needs):
+    """One intra-node step delivered along its socket routes (phases
+    step_on, step_gather, step_cross, step_scatter): on-socket messages go
+    directly from the holder's values; holders hand off-socket values to the
+    socket sender, which sends them to the socket receiver, which uses the
+    ones it needs (``needs(r, j)``) and forwards the others.  ``held[r]`` is
+    what rank r holds at the start of the step.  Returns, per rank, j ->
+    tuple of the values it received."""
+    out = [dict() for _ in range(lay.n_p)]
+
+    def take(r, j, extra=None):
+        if j in held[r]:
+            return held[r][j]
+        if extra is not None and j in extra[r]:
+            return extra[r][j]
+        raise DeliveryError(f"{step}: rank {r} sends {j} it does not hold")
+
+    for x, y, idx in ph[f"{step}_on"]:
+        for j in idx:
+            out[y][j] = out[y].get(j, ()) + (take(x, j),)
+    sbuf = [dict() for _ in range(lay.n_p)]
+    for h, q, idx in ph[f"{step}_gather"]:
+        for j in idx:
+            sbuf[q][j] = take(h, j)
+    rbuf = [dict() for _ in range(lay.n_p)]
+    for q, r, idx in ph[f"{step}_cross"]:
+        for j in idx:
+            if j in rbuf[r]:
+                raise DeliveryError(f"{step}: rank {r} received {j} twice off-socket")
+            rbuf[r][j] = take(q, j, sbuf)
+            if needs(r, j):
+                out[r][j] = out[r].get(j, ()) + (rbuf[r][j],)
+    for r, y, idx in ph[f"{step}_scatter"]:
+        for j in idx:
+            if j not in rbuf[r]:
+                raise DeliveryError(f"{step}: rank {r} forwards {j} it never received")
+            out[y][j] = out[y].get(j, ()) + (rbuf[r][j],)
+    return out
+
+
 def simulate_nap(csr, lay: Layout, plan: dict, v):
     """NAPSpMV on every rank.  Returns (ghost values per rank, w).
 
     Under the ``dedup`` variant a process also uses, for its own product,
-    the values it receives in the on_node -> off_node step."""
+    the values it receives in the on_node -> off_node step.  A plan with a
+    socket level (``plan_ref.socket_plan``) delivers the three intra-node
+    steps along their socket routes."""
     dedup = "dedup" in plan.get("variant", ())
     gh = ghosts(csr, lay)
+    gh_set = [set(g) for g in gh]
     v_loc = _local_v(lay, v)
     ph = plan["phases"]
+    sockets = "pps" in plan
 
     # local_comm(on_node -> on_node): b_{l->l}.
     b_ll = [dict() for _ in range(lay.n_p)]
-    for r, t, idx in ph["L2"]:
-        assert lay.node(r) == lay.node(t)
-        for j, x in zip(idx, _send(lay, v_loc, r, idx)):
-            b_ll[t][j] = b_ll[t].get(j, ()) + (x,)
+    if sockets:
+        b_ll = _route_socket(lay, ph, "L2", v_loc,
+                             lambda r, j: j in gh_set[r] and lay.node(lay.owner(j)) == lay.node(r))
+    else:
+        for r, t, idx in ph["L2"]:
+            assert lay.node(r) == lay.node(t)
+            for j, x in zip(idx, _send(lay, v_loc, r, idx)):
+                b_ll[t][j] = b_ll[t].get(j, ()) + (x,)
     # local_comm(on_node -> off_node): b_{l->nl}.
     b_lnl = [dict() for _ in range(lay.n_p)]
-    for p, s, idx in ph["L0"]:
-        assert lay.node(p) == lay.node(s)
-        for j, x in zip(idx, _send(lay, v_loc, p, idx)):
-            b_lnl[s][j] = x
+    if sockets:
+        sends = [set() for _ in range(lay.n_p)]
+        for s_, q_, idx in ph["INTER"]:
+            sends[s_].update(idx)
+        got = _route_socket(lay, ph, "L0", v_loc,
+                            lambda r, j: j in sends[r] and lay.owner(j) != r)
+        for s_ in range(lay.n_p):
+            for j, xs in got[s_].items():
+                if len(xs) != 1:
+                    raise DeliveryError(f"L0: rank {s_} received {j} {len(xs)} times")
+                b_lnl[s_][j] = xs[0]
+    else:
+        for p, s, idx in ph["L0"]:
+            assert lay.node(p) == lay.node(s)
+            for j, x in zip(idx, _send(lay, v_loc, p, idx)):
+                b_lnl[s][j] = x
     # Inter-node pack: own values from v|R, the rest from b_{l->nl}.
     g_recv = [dict() for _ in range(lay.n_p)]
     for s, q, idx in ph["INTER"]:
@@ -109,12 +169,17 @@ def simulate_nap(csr, lay: Layout, plan: dict, v):
             g_recv[q][j] = x
     # local_comm(off_node -> on_node): forwards from g_recv.
     b_nll = [dict() for _ in range(lay.n_p)]
-    for q, t, idx in ph["L1"]:
-        assert lay.node(q) == lay.node(t)
-        for j in idx:
-            if j not in g_recv[q]:
-                raise DeliveryError(f"rank {q} forwards {j} it never received")
-            b_nll[t][j] = b_nll[t].get(j, ()) + (g_recv[q][j],)
+    if sockets:
+        b_nll = _route_socket(lay, ph, "L1", g_recv,
+                              lambda r, j: (j in gh_set[r] and j not in g_recv[r]
+                                            and lay.node(lay.owner(j)) != lay.node(r)))
+    else:
+        for q, t, idx in ph["L1"]:
+            assert lay.node(q) == lay.node(t)
+            for j in idx:
+                if j not in g_recv[q]:
+                    raise DeliveryError(f"rank {q} forwards {j} it never received")
+                b_nll[t][j] = b_nll[t].get(j, ()) + (g_recv[q][j],)
 
     ghost_vals = []
     for t in range(lay.n_p):
