@@ -248,6 +248,25 @@ NAPSPMV_API int napspmv_apply_ws(napspmv_plan_t plan, void *ws, const void *v, v
                                  void *stream);
 
 /*
+ * napspmv_apply for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels and result bits as napspmv_apply_ws, but the
+ * workspace is a static array of the library (64 MiB, see
+ * napspmv_noalloc_max_workspace_bytes; held on each GPU the library runs on
+ * until the process ends) instead of the plan's own or the caller's.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library call);
+ * the first call on a GPU looks up the array's device address once.  A plan
+ * whose workspace (napspmv_plan_workspace_bytes) is larger is refused with
+ * NAPSPMV_EUNSUPPORTED.  Every call on one GPU shares the one array: calls
+ * whose applies overlap on the device (on different streams, or from
+ * different threads) race and give wrong results; applies issued on one
+ * stream are ordered and safe.  No part of the array needs to start at
+ * zero: an apply writes every position it later reads.
+ */
+NAPSPMV_API int napspmv_apply_noalloc(napspmv_plan_t plan, const void *v, void *w, void *stream);
+NAPSPMV_API int64_t napspmv_noalloc_max_workspace_bytes(void);
+
+/*
  * Batched applies: `count` independent products w[i] = A_i v[i] (plans
  * plans[i], different matrices or the same one with different workspaces)
  * in one launch sequence -- one first launch over every product's exchange

@@ -69,6 +69,8 @@ _SIGS = {
     "napspmv_plan_read_ghost_values": (I32, [P, P, P, P]),
     "napspmv_plan_workspace_bytes": (I64, [P]),
     "napspmv_apply_ws": (I32, [P, P, P, P, P]),
+    "napspmv_apply_noalloc": (I32, [P, P, P, P]),
+    "napspmv_noalloc_max_workspace_bytes": (I64, []),
     "napspmv_batch_create": (I32, [I32, P]),
     "napspmv_batch_apply": (I32, [P, I32, P, P, P, P, P]),
     "napspmv_batch_destroy": (I32, [P]),
@@ -302,6 +304,14 @@ class Plan:
         _check(load_library().napspmv_apply_ws(
             self._h, ctypes.c_void_p(ws.data_ptr()), self._vec_check(v, "v"),
             self._vec_check(w, "w"), _stream_handle(stream)))
+        return w
+
+    def apply_noalloc(self, v, w, stream=None):
+        """w = A v with the library's static workspace (allocates nothing;
+        see napspmv_apply_noalloc)."""
+        _check(load_library().napspmv_apply_noalloc(self._h, self._vec_check(v, "v"),
+                                                    self._vec_check(w, "w"),
+                                                    _stream_handle(stream)))
         return w
 
     def prepare_partitions(self):

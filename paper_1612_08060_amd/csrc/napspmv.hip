@@ -1055,6 +1055,35 @@ bool valid_cfg(const int c[4]) {
            c[2] <= kMaxItem;
 }
 
+// ---- the allocation-free apply ---------------------------------------------------
+
+// Workspace of napspmv_apply_noalloc: one array per GPU, held by the loaded
+// code object until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host the name stands for a host-side shadow, not
+// a device address): it passes the device address hipGetSymbolAddress gives
+// for the current GPU.
+constexpr int64_t kScratchBytes = (int64_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on GPU `dev` (current), looked up on the
+// first call for that GPU.
+void *scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) throw Error(NAPSPMV_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) % kAlign) != 0)
+            throw Error(NAPSPMV_EHIP, "scratch symbol has no aligned device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1128,6 +1157,27 @@ int napspmv_apply_ws(napspmv_plan_t plan, void *ws, const void *v, void *w, void
 
 int napspmv_apply(napspmv_plan_t plan, const void *v, void *w, void *stream) {
     return napspmv_apply_ws(plan, nullptr, v, w, stream);
+}
+
+int64_t napspmv_noalloc_max_workspace_bytes(void) { return kScratchBytes; }
+
+int napspmv_apply_noalloc(napspmv_plan_t plan, const void *v, void *w, void *stream) {
+    int rc = check_vectors(plan, v, w);
+    if (rc) return rc;
+    const int64_t need = ws_layout(plan).total;
+    if (need > kScratchBytes)
+        return fail(NAPSPMV_EUNSUPPORTED,
+                    "napspmv_apply_noalloc: the plan needs a workspace of " + std::to_string(need) +
+                        " bytes, more than the " + std::to_string(kScratchBytes) +
+                        " bytes of the static workspace");
+    return guarded([&]() {
+        DeviceGuard g(plan->device);
+        // every apply writes each ghost and send position before it reads it,
+        // so nothing left in the array by an earlier call needs clearing
+        run_apply(plan, ws_ptrs(plan, scratch_address(plan->device)), v, w,
+                  static_cast<hipStream_t>(stream));
+        return NAPSPMV_OK;
+    });
 }
 
 int64_t napspmv_plan_workspace_bytes(napspmv_plan_t plan) {
