@@ -79,6 +79,19 @@ extern "C" {
 #define NAPSPMV_PHASE_L0    1   /* NAP on_node -> off_node: owner to inter-node sender */
 #define NAPSPMV_PHASE_L1    2   /* NAP off_node -> on_node: inter-node receiver to user */
 #define NAPSPMV_PHASE_L2    3   /* on_node -> on_node: direct on-node messages */
+/* Socket-level phases of a plan built by napspmv_plan_create_sockets: how
+ * each intra-node step (L0, L1, L2) travels between sockets.  Phase
+ * NAPSPMV_PHASE_SOCKET(step, part) for step = NAPSPMV_PHASE_L0..L2 and part:
+ *   ON      the step's messages whose two ranks share a socket (direct)
+ *   GATHER  holder -> socket sender, the indices the sender passes on
+ *   CROSS   socket sender -> socket receiver, one message per socket pair
+ *           (F(a, b): the union of the step's indices from socket a to b)
+ *   SCATTER socket receiver -> the other ranks of its socket that need them */
+#define NAPSPMV_PART_ON      0
+#define NAPSPMV_PART_GATHER  1
+#define NAPSPMV_PART_CROSS   2
+#define NAPSPMV_PART_SCATTER 3
+#define NAPSPMV_PHASE_SOCKET(step, part) (4 * (step) + (part))   /* 4 .. 15 */
 
 /* Plan flags. */
 #define NAPSPMV_HOST_ONLY     0x1u  /* build the plan on the host only (no GPU needed):
@@ -202,9 +215,49 @@ NAPSPMV_API int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, c
                         const int64_t *row_starts, uint32_t flags,
                         napspmv_plan_t *plan_out, napspmv_stats_t *stats_out);
 
-/* Third hierarchy level (section 6, future work: intra-node messages split
- * into on-socket and off-socket).  Sockets hold procs_per_socket
- * consecutive ranks (it must divide ppn).  out[2 phase] receives the
+/*
+ * A NAP plan with a third hierarchy level (section 6 leaves splitting
+ * intra-node messages into on-socket and off-socket ones to future work; the
+ * introduction notes that socket information could be used the way node
+ * information is).  Sockets hold procs_per_socket consecutive ranks (it must
+ * divide ppn).  The inter-node messages and the three intra-node steps are
+ * those of the NAP plan (phases INTER, L0, L1, L2, and napspmv_stats_t's
+ * phase statistics); each intra-node step then travels as section 4 routes
+ * inter-node messages, one level down: its messages inside a socket go
+ * directly; for every ordered socket pair (a, b) of a node the union F(a, b)
+ * of its other indices from a to b goes in one message from a socket sender
+ * of a to a socket receiver of b (the partners of a ranked by |F(a, b)|
+ * descending, ties by ascending socket, the k-th sent by rank k mod
+ * procs_per_socket of a; the senders to b ranked by |F(b, a)| descending,
+ * ties by ascending socket, the k-th received by rank procs_per_socket - 1 -
+ * (k mod procs_per_socket) of b); each index's holder (its owner, or for
+ * L1 the inter-node receiver) hands it to the socket sender first, and the
+ * socket receiver forwards it to the other ranks of b that need it.
+ * procs_per_socket = ppn or 1 gives the NAP plan's messages.  Arguments as
+ * napspmv_plan_create (mode NAP); flags may hold NAPSPMV_HOST_ONLY and
+ * NAPSPMV_PARTITION_STRIDED only (EINVAL otherwise).  On the device the
+ * cross-socket messages of L2 are gathered from v with the inter-node send
+ * buffer, those of L1 are copied from the received buffer into a
+ * cross-socket buffer, and the ghosts they serve read those buffers;
+ * napspmv_apply gives the NAP plan's w bit for bit.
+ */
+NAPSPMV_API int napspmv_plan_create_sockets(const int64_t *rowptr, const int32_t *col,
+                                            const void *val, int dtype, int64_t n, int64_t n_p,
+                                            int64_t ppn, int64_t procs_per_socket,
+                                            const int64_t *row_starts, uint32_t flags,
+                                            napspmv_plan_t *plan_out, napspmv_stats_t *stats_out);
+
+/* Statistics of the 12 socket-level phases (out[NAPSPMV_PHASE_SOCKET(step,
+ * part) - 4], caller-owned, may be NULL) and the plan's procs_per_socket (0
+ * if it has no socket level; may be NULL).  EINVAL for out on a plan
+ * without a socket level. */
+NAPSPMV_API int napspmv_plan_socket_stats(napspmv_plan_t plan, int64_t *procs_per_socket,
+                                          napspmv_phase_stats_t *out);
+
+/* The same socket split as a filter of any plan's own messages (section 6:
+ * intra-node messages split into on-socket and off-socket).  Sockets hold
+ * procs_per_socket consecutive ranks (it must divide ppn).  out[2 phase]
+ * receives the
  * statistics of the phase's messages whose source and destination share a
  * socket, out[2 phase + 1] those of the others (8 entries, caller-owned).
  * Inter-node messages are always off-socket.  Works for host-only plans. */
@@ -375,11 +428,14 @@ NAPSPMV_API int napspmv_server_destroy(napspmv_server_t server);
 NAPSPMV_API int napspmv_plan_stats(napspmv_plan_t plan, napspmv_stats_t *out);
 
 /*
- * Canonical export of one phase's messages, for bit-exact comparison:
- * messages sorted by (src, dst), indices ascending by global column inside a
- * message, one message per (src, dst) pair.  Two-call pattern: pass NULL
- * arrays to get *n_msgs and *n_idx, then arrays of n_msgs (src, dst),
- * n_msgs+1 (ptr) and n_idx (idx) elements.
+ * Canonical export of one phase's messages (section 5's statistics are
+ * computed from them), for bit-exact comparison: messages sorted by (src,
+ * dst), indices ascending by global column inside a message, one message
+ * per (src, dst) pair.  phase: NAPSPMV_PHASE_INTER .. L2, or a socket-level
+ * phase NAPSPMV_PHASE_SOCKET(step, part) of a plan built with a socket level
+ * (EINVAL otherwise).  Two-call pattern: pass NULL arrays to get *n_msgs and
+ * *n_idx, then arrays of n_msgs (src, dst), n_msgs+1 (ptr) and n_idx (idx)
+ * elements.
  */
 NAPSPMV_API int napspmv_plan_export(napspmv_plan_t plan, int phase, int64_t *n_msgs, int64_t *n_idx,
                         int32_t *src, int32_t *dst, int64_t *ptr, int32_t *idx);

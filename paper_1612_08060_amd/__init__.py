@@ -15,13 +15,15 @@ import os
 import numpy as np
 
 __all__ = ["Plan", "Graph", "Batch", "Server", "NapspmvError", "load_library", "LIB_PATH", "MODES",
-           "DTYPES", "PHASES",
+           "DTYPES", "PHASES", "SOCKET_PHASES",
            "STAGE_LOCAL", "STAGE_REMOTE", "set_device_budget", "device_bytes_in_use"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnapspmv.so")
 MODES = {"standard": 0, "nap": 1}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 PHASES = ("INTER", "L0", "L1", "L2")
+SOCKET_PARTS = ("on", "gather", "cross", "scatter")
+SOCKET_PHASES = tuple(f"{ph}_{part}" for ph in ("L0", "L1", "L2") for part in SOCKET_PARTS)
 STAGE_LOCAL, STAGE_REMOTE = 0, 1
 HOST_ONLY, EXCHANGE_COPY = 0x1, 0x2
 VARIANTS = {"owner_map": 0x4, "split": 0x8, "dedup": 0x10, "three_way": 0x20,
@@ -59,6 +61,8 @@ _lib = None
 P, I64, I32, U32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
 _SIGS = {
     "napspmv_plan_create": (I32, [P, P, P, I32, I64, I64, I64, I32, P, U32, P, P]),
+    "napspmv_plan_create_sockets": (I32, [P, P, P, I32, I64, I64, I64, I64, P, U32, P, P]),
+    "napspmv_plan_socket_stats": (I32, [P, P, P]),
     "napspmv_apply": (I32, [P, P, P, P]),
     "napspmv_apply_stage": (I32, [P, I32, P, P, P]),
     "napspmv_plan_stats": (I32, [P, P]),
@@ -150,12 +154,16 @@ class Plan:
     three parts of algorithm NAPSpMV (on_process, on_node, off_node) with the
     inter-node hop overlapped with the on_node product.  ``strided`` puts
     row r on process r mod n_p (section 5); the plan, its exports and v, w
-    are then in process-major order (see ``rows``).
+    are then in process-major order (see ``rows``).  ``sockets`` (NAP mode,
+    no variant) adds a third hierarchy level of that many consecutive ranks
+    per socket (napspmv_plan_create_sockets): phases "L0_on" ... "L2_scatter"
+    and ``socket_stats``.
     """
 
     def __init__(self, rowptr, col, val, n: int, n_p: int, ppn: int, mode: str = "standard",
                  dtype: str = "f64", row_starts=None, host_only: bool = False,
-                 exchange_copy: bool = False, variant=(), strided: bool = False):
+                 exchange_copy: bool = False, variant=(), strided: bool = False,
+                 sockets: int = 0):
         lib = load_library()
         unknown = set(variant) - set(VARIANTS)
         if unknown:
@@ -184,11 +192,20 @@ class Plan:
         handle = ctypes.c_void_p()
         st = Stats()
         self._h = None
-        rc = lib.napspmv_plan_create(
-            self._rowptr.ctypes.data, self._col.ctypes.data, self._val.ctypes.data,
-            DTYPES[dtype], self.n, self.n_p, self.ppn, MODES[mode],
-            None if self._starts is None else self._starts.ctypes.data, flags,
-            ctypes.byref(handle), ctypes.byref(st))
+        self.sockets = int(sockets)
+        starts = None if self._starts is None else self._starts.ctypes.data
+        if self.sockets:
+            if mode != "nap":
+                raise ValueError("a socket level needs mode='nap'")
+            rc = lib.napspmv_plan_create_sockets(
+                self._rowptr.ctypes.data, self._col.ctypes.data, self._val.ctypes.data,
+                DTYPES[dtype], self.n, self.n_p, self.ppn, self.sockets, starts, flags,
+                ctypes.byref(handle), ctypes.byref(st))
+        else:
+            rc = lib.napspmv_plan_create(
+                self._rowptr.ctypes.data, self._col.ctypes.data, self._val.ctypes.data,
+                DTYPES[dtype], self.n, self.n_p, self.ppn, MODES[mode], starts, flags,
+                ctypes.byref(handle), ctypes.byref(st))
         _check(rc)
         self._h = handle
         # the plan has copied everything it needs
@@ -207,9 +224,10 @@ class Plan:
         return out
 
     def export(self, phase: str):
-        """(src int32, dst int32, ptr int64, idx int32) of a phase, canonical."""
+        """(src int32, dst int32, ptr int64, idx int32) of a phase (a name of
+        PHASES, or of SOCKET_PHASES for a plan with a socket level), canonical."""
         lib = load_library()
-        ph = PHASES.index(phase)
+        ph = PHASES.index(phase) if phase in PHASES else 4 + SOCKET_PHASES.index(phase)
         nm, ni = ctypes.c_int64(), ctypes.c_int64()
         _check(lib.napspmv_plan_export(self._h, ph, ctypes.byref(nm), ctypes.byref(ni),
                                        None, None, None, None))
@@ -220,6 +238,14 @@ class Plan:
         _check(lib.napspmv_plan_export(self._h, ph, None, None, src.ctypes.data,
                                        dst.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
         return src, dst, ptr, idx
+
+    def socket_stats(self) -> dict:
+        """Statistics of the socket-level phases (plans built with ``sockets``)."""
+        out = (PhaseStats * 12)()
+        pps = ctypes.c_int64()
+        _check(load_library().napspmv_plan_socket_stats(self._h, ctypes.byref(pps), out))
+        return {name: {k: getattr(out[i], k) for k, _ in PhaseStats._fields_}
+                for i, name in enumerate(SOCKET_PHASES)}
 
     def level_stats(self, procs_per_socket: int) -> dict:
         """Per phase, statistics of its on-socket and off-socket messages

@@ -201,10 +201,17 @@ __device__ __forceinline__ void scatter_item(int4 it, int32_t n, int32_t which,
 // receiver's own use), and the fully local positions from the band of v
 // still in LDS.  The pack uses plain stores: its values are read back at
 // once, from this CU's cache.  item = (b, first send entry, count, 1).
+// A plan with a socket level also copies, between the two, the received
+// values of band b that cross a socket in the off_node -> on_node step into
+// their cross-socket buffer (s1band: its band boundaries, as positions of
+// the received region; s1src: the received position of each entry), which
+// the scatter then reads like the received buffer.
 template <typename T, int CAP>
 __device__ __forceinline__ void pack_scatter_item(int4 it, int32_t n, const uint16_t *__restrict__ off,
                                                   const T *__restrict__ v, T *send,
                                                   const int32_t *__restrict__ gband,
+                                                  const int32_t *__restrict__ s1band,
+                                                  const int32_t *__restrict__ s1src,
                                                   const uint32_t *__restrict__ code,
                                                   const T *recv, T *__restrict__ ghost, T *lds,
                                                   bool nt) {
@@ -213,6 +220,15 @@ __device__ __forceinline__ void pack_scatter_item(int4 it, int32_t n, const uint
     // the band's packed values are visible to the whole workgroup (recv and
     // send are the same memory: no restrict on either)
     __syncthreads();
+    if (s1band) {
+        const int32_t b0 = s1band[it.x], b1 = s1band[it.x + 1];
+        if (b1 > b0) {
+            const int32_t e = s1band[0];     // first position of the cross-socket buffer
+            for (int32_t k = b0 + (int32_t)threadIdx.x; k < b1; k += kBlock)
+                send[k] = recv[__builtin_nontemporal_load(s1src + (k - e))];
+            __syncthreads();
+        }
+    }
     const int4 sit = make_int4(it.x, gband[it.x], gband[it.x + 1] - gband[it.x], 1);
     if (nt)
         scatter_values<T, true>(sit, 0, code, recv, ghost, lds);
@@ -385,6 +401,7 @@ struct LocalView {
     // NAP pack-and-scatter items (item.w = 1): ghost band boundaries, the
     // scatter codes, the received buffer and the ghost buffer
     const int32_t *gband;
+    const int32_t *s1band, *s1src;   // socket plans: cross-socket copies of received values
     const uint32_t *code;
     const XT *recv;
     XT *ghost;
@@ -428,8 +445,8 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
     if (task < 0) {
         const int4 it = L.items[~task];
         if (it.w == 1) {
-            pack_scatter_item<XT, CAP>(it, L.n, L.off, L.v, L.xdst, L.gband, L.code, L.recv,
-                                       L.ghost, prod, L.nt != 0);
+            pack_scatter_item<XT, CAP>(it, L.n, L.off, L.v, L.xdst, L.gband, L.s1band, L.s1src,
+                                       L.code, L.recv, L.ghost, prod, L.nt != 0);
             return;
         }
         exchange_item<XT, CAP>(it, L.n, L.off, L.idx, L.dpos, L.v, L.xdst, prod, L.nt != 0);

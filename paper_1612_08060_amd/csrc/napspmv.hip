@@ -41,6 +41,7 @@ struct Schedules {
     int32_t *onbase = nullptr;                      // first row of each on-process block's process
     int32_t *sitems = nullptr;                      // NAP: band items of the ghost scatter
     int32_t *gband = nullptr;                       // NAP: ghost band boundaries (pack-and-scatter items)
+    int32_t *s1band = nullptr;                      // socket plans: l1x band boundaries
     int64_t n_on = 0, n_off = 0, n_items = 0, n_tasks = 0, n_nd = 0, n_sitems = 0, bytes = 0;
     // per-partition schedules only: each process's range of tasks and of
     // off-process blocks
@@ -59,6 +60,7 @@ struct napspmv_plan_s {
     bool cur_item_auto = true;       // the schedules were built with an automatic item size
     int sorted_remote_nnz = 0;       // block size the off-process entry order was sorted for
     int64_t G = 0, E = 0, H = 0, Gon = 0;
+    int64_t E1 = 0;                  // socket plans: entries of the l1x cross-socket buffer
     int32_t *d_rp_on = nullptr, *d_col_on = nullptr, *d_rp_off = nullptr, *d_col_off = nullptr;
     uint16_t *d_col16_on = nullptr;  // on-process columns as offsets from the process's first row
     void *d_val_on = nullptr, *d_val_off = nullptr;
@@ -71,6 +73,8 @@ struct napspmv_plan_s {
     std::vector<int32_t> gpos;
     std::vector<int32_t> dmap;           // direct reads: source code of every ghost
     std::vector<int64_t> gband, sband;   // band boundaries of the ghost / send buffers
+    std::vector<int64_t> s1band;         // socket plans: band boundaries of the l1x buffer
+    int32_t *d_s1src = nullptr;          // socket plans: source position of every l1x entry
     uint16_t *d_off = nullptr;
     uint32_t *d_code = nullptr;
     int32_t *d_pgcol = nullptr, *d_pgpos = nullptr;   // per-process indexed gathers
@@ -163,7 +167,9 @@ WsLayout ws_layout(const napspmv_plan_s *p) {
     const bool copy = nap && (p->flags & NAPSPMV_EXCHANGE_COPY);
     WsLayout l;
     l.send = p->hp.direct ? 0 : align_up(p->G * vb);     // direct reads fill no ghost buffer
-    l.total = l.send + (nap ? align_up(p->E * vb) : 0);
+    // the received region: the send buffer (received in place) followed by
+    // the cross-socket buffer of a socket plan
+    l.total = l.send + (nap ? align_up((p->E + p->E1) * vb) : 0);
     l.recv = copy ? l.total : l.send;
     if (copy) l.total += align_up(p->E * vb);
     return l;
@@ -204,7 +210,7 @@ void charge(napspmv_plan_s *p, int64_t bytes) {
 
 void free_schedules(napspmv_plan_s *p, Schedules &s) {
     void *ptrs[] = {s.onblk, s.onptr, s.win, s.offblk, s.offptr, s.items, s.tasks, s.ndblk, s.ndptr,
-                    s.sitems, s.onbase, s.gband};
+                    s.sitems, s.onbase, s.gband, s.s1band};
     for (void *q : ptrs) free_ptr(q);
     charge(p, -s.bytes);
     s = Schedules();
@@ -218,12 +224,13 @@ void free_device(napspmv_plan_s *p) {
                     p->d_val_off, p->d_off, p->d_code, p->d_pgcol, p->d_pgpos, p->d_ws,
                     p->d_l2pos, p->d_l2col,
                     p->d_rp_nd, p->d_col_nd, p->d_val_nd, p->d_slot_off, p->d_slot_nd,
-                    p->d_col16_on};
+                    p->d_col16_on, p->d_s1src};
     for (void *q : ptrs) free_ptr(q);
     p->d_rp_nd = p->d_col_nd = nullptr;
     p->d_val_nd = nullptr;
     p->d_slot_off = p->d_slot_nd = nullptr;
     p->d_col16_on = nullptr;
+    p->d_s1src = nullptr;
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->helper) (void)hipStreamDestroy(p->helper);
@@ -250,6 +257,7 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
     b += (int64_t)(hp.col_off.size() + hp.col_nd.size()) * 2;   // gather-order slots
     // band offsets (ghosts or send entries) and, for NAP, the scatter codes
     b += hp.mode == NAPSPMV_NAP ? p->E * 2 + p->G * 4 : p->G * 2;
+    b += p->E1 * 4;                                               // l1x sources
     return b + ws_layout(p).total;
 }
 
@@ -259,7 +267,7 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
                       const std::vector<int32_t> &items, const std::vector<int32_t> &tasks,
                       const std::vector<int32_t> &ndblk = {}, const std::vector<int32_t> &ndptr = {},
                       const std::vector<int32_t> &sitems = {}, const std::vector<int32_t> &onbase = {},
-                      const std::vector<int32_t> &gband = {}) {
+                      const std::vector<int32_t> &gband = {}, const std::vector<int32_t> &s1band = {}) {
     free_schedules(p, s);
     int64_t total = 0;
     try {
@@ -275,6 +283,7 @@ void upload_schedules(napspmv_plan_s *p, Schedules &s, const std::vector<int32_t
         upload(s.sitems, sitems, total);
         upload(s.onbase, onbase, total);
         upload(s.gband, gband, total);
+        if (!s1band.empty()) upload(s.s1band, s1band, total);
     } catch (...) {
         s.bytes = total;
         charge(p, total);
@@ -418,18 +427,31 @@ void build_layout(napspmv_plan_s *p, int cap) {
         for (int64_t k = 0; k < G; ++k) off[gpos[k]] = (uint16_t)(hp.ghost_col[k] % cap);
         if (G) HIP_OK(hipMemcpy(p->d_off, off.data(), G * 2, hipMemcpyHostToDevice));
     } else {
-        // inside a band, the send buffer is grouped by receiving node, so the
-        // values one node's ghosts take from a band lie together
-        const napspmv::Phase &I = hp.phase[NAPSPMV_PHASE_INTER];
-        std::vector<int32_t> dst_node(E);
-        for (size_t k = 0; k < I.src.size(); ++k)
-            for (int64_t e = I.ptr[k]; e < I.ptr[k + 1]; ++e) dst_node[e] = (int32_t)(I.dst[k] / hp.ppn);
+        // inside a band, the send buffer is grouped by destination (receiving
+        // node, or socket for the cross-socket entries of a socket plan), so
+        // the values one destination's ghosts take from a band lie together
+        int64_t ngroups = 1;
+        for (int32_t g : hp.pack_group) ngroups = std::max<int64_t>(ngroups, (int64_t)g + 1);
+        for (int32_t g : hp.l1x_group) ngroups = std::max<int64_t>(ngroups, (int64_t)g + 1);
         std::vector<int32_t> spos;
-        band_order(hp.pack_idx.data(), E, cap, nb, dst_node.data(), hp.n_nodes, spos, p->sband);
+        band_order(hp.pack_idx.data(), E, cap, nb, hp.pack_group.data(), ngroups, spos, p->sband);
         std::vector<uint16_t> off(E);
         for (int64_t e = 0; e < E; ++e) off[spos[e]] = (uint16_t)(hp.pack_idx[e] % cap);
+        // socket plans: the l1x buffer follows the send buffer, band-ordered
+        // the same way; each entry copies a received value of its band
+        std::vector<int32_t> l1pos;
+        if (p->E1 > 0) {
+            band_order(hp.l1x_col.data(), p->E1, cap, nb, hp.l1x_group.data(), ngroups, l1pos,
+                       p->s1band);
+            std::vector<int32_t> src(p->E1);
+            for (int64_t k = 0; k < p->E1; ++k) src[l1pos[k]] = spos[hp.l1x_src[k]];
+            HIP_OK(hipMemcpy(p->d_s1src, src.data(), p->E1 * 4, hipMemcpyHostToDevice));
+        }
         std::vector<uint32_t> code(G, 0);
-        for (int64_t h = 0; h < p->H; ++h) code[gpos[hp.scat_dst[h]]] = (uint32_t)spos[hp.scat_src[h]];
+        for (int64_t h = 0; h < p->H; ++h) {
+            const int64_t src = hp.scat_src[h];
+            code[gpos[hp.scat_dst[h]]] = (uint32_t)(src < E ? spos[src] : E + l1pos[src - E]);
+        }
         for (int64_t k = 0; k < p->Gon; ++k)
             code[gpos[hp.l2_dst[k]]] = napspmv::kFromV | (uint32_t)(hp.l2_src[k] % cap);
         if (E) HIP_OK(hipMemcpy(p->d_off, off.data(), E * 2, hipMemcpyHostToDevice));
@@ -473,7 +495,7 @@ void refresh_schedules(napspmv_plan_s *p) {
         rcap == p->cur_remote_nnz && (p->item < 0) == p->cur_item_auto)
         return;
     const HostPlan &hp = p->hp;
-    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems, onbase, gbv;
+    std::vector<int32_t> onblk, onptr, wins, offblk, offptr, items, tasks, sitems, onbase, gbv, s1v;
     int64_t tail = napspmv::kItemTail;
     // on-process blocks never span two processes: each block's columns are
     // offsets from its process's first row
@@ -513,8 +535,10 @@ void refresh_schedules(napspmv_plan_s *p) {
             widest = std::max(widest, p->sband[b + 1] - p->sband[b]);
         // (an automatic item size always allows it: a band's item is then
         // as wide as the band)
-        const bool fuse = !hp.three_way && !hp.direct && !(p->flags & NAPSPMV_EXCHANGE_COPY) &&
-                          (p->item < 0 || widest <= item);
+        // (a socket plan always fuses: its l1x copies run inside the items)
+        const bool fuse = hp.pps > 0 ||
+                          (!hp.three_way && !hp.direct && !(p->flags & NAPSPMV_EXCHANGE_COPY) &&
+                           (p->item < 0 || widest <= item));
         if (fuse) {
             tail = napspmv::kPackScatterTail;
             for (size_t b = 0; b + 1 < p->sband.size(); ++b) {
@@ -524,6 +548,11 @@ void refresh_schedules(napspmv_plan_s *p) {
                 items.insert(items.end(), q, q + 4);
             }
             gbv.assign(p->gband.begin(), p->gband.end());
+            if (p->E1 > 0) {
+                // l1x band boundaries, offset to their place after the send buffer
+                s1v.resize(p->s1band.size());
+                for (size_t b = 0; b < p->s1band.size(); ++b) s1v[b] = (int32_t)(p->E + p->s1band[b]);
+            }
         } else {
             band_items(p->sband, item, items);
             band_items(p->gband, item, sitems);
@@ -531,7 +560,7 @@ void refresh_schedules(napspmv_plan_s *p) {
     }
     napspmv::merge_tasks((int64_t)items.size() / 4, (int64_t)onblk.size() - 1, tasks, tail);
     upload_schedules(p, p->sched, onblk, onptr, wins, offblk, offptr, items, tasks, ndblk, ndptr,
-                     sitems, onbase, gbv);
+                     sitems, onbase, gbv, s1v);
     p->cur_block_nnz = cap;
     p->cur_window = win;
     p->cur_item = item;
@@ -603,6 +632,7 @@ void to_device(napspmv_plan_s *p) {
         } else {
             alloc(p->d_off, (size_t)p->E * 2);
             alloc(p->d_code, (size_t)p->G * 4);
+            if (p->E1 > 0) alloc(p->d_s1src, (size_t)p->E1 * 4);
         }
         const int64_t wsb = ws_layout(p).total;
         if (wsb > 0) {
@@ -660,6 +690,8 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
     L.w = w;
     L.nt = stream_out(p);
     L.gband = s.gband;
+    L.s1band = s.s1band;
+    L.s1src = p->d_s1src;
     L.code = p->d_code;
     L.recv = static_cast<const XT *>(ws.recv);
     L.ghost = static_cast<XT *>(ws.ghost);
@@ -1084,19 +1116,17 @@ void *scratch_address(int dev) {
     return g_scratch_ptr[dev];
 }
 
-}  // namespace
-
-extern "C" {
-
-int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *val, int dtype,
-                        int64_t n, int64_t n_p, int64_t ppn, int mode, const int64_t *row_starts,
-                        uint32_t flags, napspmv_plan_t *plan_out, napspmv_stats_t *stats_out) {
+int plan_create(const int64_t *rowptr, const int32_t *col, const void *val, int dtype, int64_t n,
+                int64_t n_p, int64_t ppn, int mode, int64_t pps, const int64_t *row_starts,
+                uint32_t flags, napspmv_plan_t *plan_out, napspmv_stats_t *stats_out) {
     if (!plan_out) return fail(NAPSPMV_EINVAL, "plan_out is NULL");
     *plan_out = nullptr;
     if (flags & ~(NAPSPMV_HOST_ONLY | NAPSPMV_EXCHANGE_COPY | NAPSPMV_NAP_OWNER_MAP |
                   NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP | NAPSPMV_NAP_THREE_WAY |
                   NAPSPMV_NAP_DIRECT | NAPSPMV_PARTITION_STRIDED))
         return fail(NAPSPMV_EINVAL, "unknown flag bits");
+    if (pps != 0 && (flags & NAPSPMV_EXCHANGE_COPY))
+        return fail(NAPSPMV_EINVAL, "the socket level receives the inter-node messages in place");
     napspmv_plan_s *p = nullptr;
     const int rc = guarded([&]() {
         p = new napspmv_plan_s();
@@ -1105,11 +1135,12 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
         napspmv::build_plan(p->hp, rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts,
                             flags & (NAPSPMV_NAP_OWNER_MAP | NAPSPMV_NAP_SPLIT | NAPSPMV_NAP_DEDUP |
                                      NAPSPMV_NAP_THREE_WAY | NAPSPMV_NAP_DIRECT),
-                            (flags & NAPSPMV_PARTITION_STRIDED) != 0);
+                            (flags & NAPSPMV_PARTITION_STRIDED) != 0, pps);
         const auto t1 = std::chrono::steady_clock::now();
         p->build_s = std::chrono::duration<double>(t1 - t0).count();
         p->G = p->hp.ghost_ptr.back();
         p->E = (int64_t)p->hp.pack_idx.size();
+        p->E1 = (int64_t)p->hp.l1x_col.size();
         p->H = (int64_t)p->hp.scat_src.size();
         p->Gon = (int64_t)p->hp.l2_src.size();
         // automatic off-process block size: the larger block lets a
@@ -1128,6 +1159,44 @@ int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *v
     });
     if (rc != NAPSPMV_OK) delete p;
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int napspmv_plan_create(const int64_t *rowptr, const int32_t *col, const void *val, int dtype,
+                        int64_t n, int64_t n_p, int64_t ppn, int mode, const int64_t *row_starts,
+                        uint32_t flags, napspmv_plan_t *plan_out, napspmv_stats_t *stats_out) {
+    return plan_create(rowptr, col, val, dtype, n, n_p, ppn, mode, 0, row_starts, flags, plan_out,
+                       stats_out);
+}
+
+int napspmv_plan_create_sockets(const int64_t *rowptr, const int32_t *col, const void *val,
+                                int dtype, int64_t n, int64_t n_p, int64_t ppn,
+                                int64_t procs_per_socket, const int64_t *row_starts, uint32_t flags,
+                                napspmv_plan_t *plan_out, napspmv_stats_t *stats_out) {
+    if (procs_per_socket < 1) {
+        if (plan_out) *plan_out = nullptr;
+        return fail(NAPSPMV_EINVAL, "procs_per_socket must be at least 1");
+    }
+    return plan_create(rowptr, col, val, dtype, n, n_p, ppn, NAPSPMV_NAP, procs_per_socket,
+                       row_starts, flags, plan_out, stats_out);
+}
+
+int napspmv_plan_socket_stats(napspmv_plan_t plan, int64_t *procs_per_socket,
+                              napspmv_phase_stats_t *out) {
+    if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
+    if (procs_per_socket) *procs_per_socket = plan->hp.pps;
+    if (out) {
+        if (plan->hp.pps == 0) return fail(NAPSPMV_EINVAL, "the plan has no socket level");
+        for (int k = 0; k < 12; ++k) {
+            const napspmv::PhaseStats &q = plan->hp.sock_stats[k];
+            out[k] = napspmv_phase_stats_t{q.msgs, q.elems, q.max_msgs_sent, q.max_elems_sent,
+                                           q.max_msgs_recv, q.max_elems_recv, q.max_msg_elems};
+        }
+    }
+    return NAPSPMV_OK;
 }
 
 int napspmv_apply_stage(napspmv_plan_t plan, int stage, const void *v, void *w, void *stream) {
@@ -1457,8 +1526,9 @@ int napspmv_plan_stats(napspmv_plan_t plan, napspmv_stats_t *out) {
 int napspmv_plan_export(napspmv_plan_t plan, int phase, int64_t *n_msgs, int64_t *n_idx,
                         int32_t *src, int32_t *dst, int64_t *ptr, int32_t *idx) {
     if (!plan) return fail(NAPSPMV_EINVAL, "plan is NULL");
-    if (phase < 0 || phase > 3) return fail(NAPSPMV_EINVAL, "unknown phase");
-    const napspmv::Phase &ph = plan->hp.phase[phase];
+    if (phase < 0 || phase > 15) return fail(NAPSPMV_EINVAL, "unknown phase");
+    if (phase > 3 && plan->hp.pps == 0) return fail(NAPSPMV_EINVAL, "the plan has no socket level");
+    const napspmv::Phase &ph = phase < 4 ? plan->hp.phase[phase] : plan->hp.sock_phase[phase - 4];
     if (n_msgs) *n_msgs = (int64_t)ph.src.size();
     if (n_idx) *n_idx = ph.ptr.back();
     if (src) std::copy(ph.src.begin(), ph.src.end(), src);

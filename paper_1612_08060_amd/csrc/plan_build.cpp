@@ -29,6 +29,18 @@
 //    U-process q of its node pair; if q != t, q forwards it to t.
 //  * on_node -> on_node (L2): the runs of gh(t) owned by another process of
 //    t's node (the standard intra-node messages).
+//  * Socket level (a third level of the hierarchy, which section 6 leaves
+//    to future work): sockets of pps consecutive ranks route each of the
+//    three intra-node steps as section 4 routes inter-node messages, one
+//    level down.  The step's messages whose ranks share a socket stay; for
+//    an ordered socket pair (a, b) of a node, F(a, b) = the sorted union of
+//    the indices its other messages carry from a to b; the partners of a are
+//    ranked by (|F(a, b)| descending, b ascending), the k-th sent by rank
+//    k mod pps of a, the senders to b by (|F(b, a)| descending, a
+//    ascending), the k-th received by rank pps - 1 - (k mod pps) of b; the
+//    holder of each index (unique in a node) hands it to the socket sender,
+//    and the socket receiver forwards it to the other ranks of b whose
+//    message carried it.
 #include "plan_build.hpp"
 
 #include <algorithm>
@@ -88,6 +100,194 @@ void finalize_phase(std::vector<MsgRef> &refs, Phase &ph) {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t k = 0; k < (int64_t)m; ++k)
         std::memcpy(ph.idx.data() + ph.ptr[k], refs[k].data, sizeof(int32_t) * refs[k].len);
+}
+
+// A (src, dst, index) triple of a message.
+struct Trip {
+    int32_t s, d, j;
+    bool operator<(const Trip &o) const {
+        return s != o.s ? s < o.s : d != o.d ? d < o.d : j < o.j;
+    }
+    bool operator==(const Trip &o) const { return s == o.s && d == o.d && j == o.j; }
+};
+
+// A phase from triples already sorted by (src, dst, index) and unique.
+void phase_from_sorted_triples(const std::vector<Trip> &t, Phase &ph) {
+    ph = Phase();
+    ph.idx.resize(t.size());
+    for (size_t k = 0; k < t.size(); ++k) {
+        if (k == 0 || t[k].s != t[k - 1].s || t[k].d != t[k - 1].d) {
+            if (k) ph.ptr.push_back((int64_t)k);
+            ph.src.push_back(t[k].s);
+            ph.dst.push_back(t[k].d);
+        }
+        ph.idx[k] = t[k].j;
+    }
+    if (!t.empty()) ph.ptr.push_back((int64_t)t.size());
+}
+
+// The socket route of one intra-node step `in` (see the file comment):
+// out[0..3] = its on-socket, gather, cross and scatter messages.  For the
+// cross messages, also the sorted keys (destination socket) * n + index
+// (`cross_key`) with the position of each in out[2].idx (`cross_pos`).
+// Nodes are independent: each node's messages (a contiguous run of `in`,
+// sorted by source) are routed in parallel and the results concatenated,
+// which keeps every phase sorted by (source, destination).
+void socket_route(const Phase &in, int64_t n, int64_t ppn, int64_t pps, Phase out[4],
+                  std::vector<int64_t> *cross_key = nullptr,
+                  std::vector<int64_t> *cross_pos = nullptr) {
+    const int64_t m = (int64_t)in.src.size();
+    const int64_t n_nodes = m ? in.src[m - 1] / ppn + 1 : 0;
+    std::vector<int64_t> first(n_nodes + 1, m);
+    for (int64_t k = m - 1; k >= 0; --k) first[in.src[k] / ppn] = k;
+    for (int64_t x = n_nodes - 1; x >= 0; --x) first[x] = std::min(first[x], first[x + 1]);
+    struct NodeOut {
+        std::vector<MsgRef> on;
+        std::vector<Trip> gather, cross, scatter;
+    };
+    std::vector<NodeOut> per(n_nodes);
+    bool two_holders = false;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|| : two_holders)
+    for (int64_t node = 0; node < n_nodes; ++node) {
+        NodeOut &o = per[node];
+        struct Off {
+            int32_t a, b;      // source and destination socket
+            int32_t j, x, y;   // index, holder, user
+        };
+        std::vector<Off> off;
+        for (int64_t k = first[node]; k < first[node + 1]; ++k) {
+            const int32_t a = (int32_t)(in.src[k] / pps), b = (int32_t)(in.dst[k] / pps);
+            const int64_t len = in.ptr[k + 1] - in.ptr[k];
+            if (a == b) {
+                o.on.push_back(MsgRef{in.src[k], in.dst[k], in.idx.data() + in.ptr[k], len});
+                continue;
+            }
+            for (int64_t e = in.ptr[k]; e < in.ptr[k + 1]; ++e)
+                off.push_back(Off{a, b, in.idx[e], in.src[k], in.dst[k]});
+        }
+        std::sort(off.begin(), off.end(), [](const Off &u, const Off &v) {
+            return u.a != v.a ? u.a < v.a : u.b != v.b ? u.b < v.b : u.j != v.j ? u.j < v.j : u.y < v.y;
+        });
+        // F(a, b): unique (a, b, j) with its holder; a holder is unique per
+        // (a, j) inside the node
+        struct FE {
+            int32_t a, b, j, h;
+        };
+        std::vector<FE> F;
+        for (size_t k = 0; k < off.size(); ++k)
+            if (k == 0 || off[k].a != off[k - 1].a || off[k].b != off[k - 1].b || off[k].j != off[k - 1].j)
+                F.push_back(FE{off[k].a, off[k].b, off[k].j, off[k].x});
+        {
+            std::vector<std::pair<int64_t, int32_t>> hold(F.size());
+            for (size_t k = 0; k < F.size(); ++k) hold[k] = {(int64_t)F[k].a * n + F[k].j, F[k].h};
+            std::sort(hold.begin(), hold.end());
+            for (size_t k = 1; k < hold.size(); ++k)
+                if (hold[k].first == hold[k - 1].first && hold[k].second != hold[k - 1].second)
+                    two_holders = true;
+        }
+        struct SP {
+            int32_t a, b;
+            int64_t begin, end, vol = 0, back = 0;
+            int32_t sender = 0, receiver = 0;
+        };
+        std::vector<SP> sp;
+        for (size_t k = 0; k < F.size(); ++k) {
+            if (k == 0 || F[k].a != F[k - 1].a || F[k].b != F[k - 1].b)
+                sp.push_back(SP{F[k].a, F[k].b, (int64_t)k, (int64_t)k});
+            sp.back().end = (int64_t)k + 1;
+        }
+        for (SP &q : sp) q.vol = q.end - q.begin;
+        for (SP &q : sp)
+            for (const SP &r : sp)
+                if (r.a == q.b && r.b == q.a) q.back = r.vol;
+        std::vector<size_t> ord(sp.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+            const SP &u = sp[x], &v = sp[y];
+            if (u.a != v.a) return u.a < v.a;
+            if (u.vol != v.vol) return u.vol > v.vol;
+            return u.b < v.b;
+        });
+        for (size_t k = 0, run = 0; k < ord.size(); ++k) {
+            run = (k > 0 && sp[ord[k]].a == sp[ord[k - 1]].a) ? run + 1 : 0;
+            sp[ord[k]].sender = (int32_t)(sp[ord[k]].a * pps + (int64_t)run % pps);
+        }
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+            const SP &u = sp[x], &v = sp[y];
+            if (u.b != v.b) return u.b < v.b;
+            if (u.back != v.back) return u.back > v.back;
+            return u.a < v.a;
+        });
+        for (size_t k = 0, run = 0; k < ord.size(); ++k) {
+            run = (k > 0 && sp[ord[k]].b == sp[ord[k - 1]].b) ? run + 1 : 0;
+            sp[ord[k]].receiver = (int32_t)(sp[ord[k]].b * pps + pps - 1 - (int64_t)run % pps);
+        }
+        for (const SP &q : sp)
+            for (int64_t k = q.begin; k < q.end; ++k) {
+                o.cross.push_back(Trip{q.sender, q.receiver, F[k].j});
+                if (F[k].h != q.sender) o.gather.push_back(Trip{F[k].h, q.sender, F[k].j});
+            }
+        size_t q = 0;
+        for (const Off &f : off) {
+            while (sp[q].a != f.a || sp[q].b != f.b) ++q;     // off and sp share the (a, b) order
+            if (f.y != sp[q].receiver) o.scatter.push_back(Trip{sp[q].receiver, f.y, f.j});
+        }
+        for (auto *t : {&o.cross, &o.gather, &o.scatter}) {
+            std::sort(t->begin(), t->end());
+            t->erase(std::unique(t->begin(), t->end()), t->end());
+        }
+    }
+    if (two_holders) throw Error(NAPSPMV_EINVAL, "socket level: an index with two holders on one socket");
+    std::vector<MsgRef> on;
+    for (const NodeOut &o : per) on.insert(on.end(), o.on.begin(), o.on.end());
+    finalize_phase(on, out[0]);
+    auto concat = [&](std::vector<Trip> NodeOut::*part, Phase &ph) {
+        std::vector<Trip> all;
+        size_t total = 0;
+        for (const NodeOut &o : per) total += (o.*part).size();
+        all.reserve(total);
+        for (NodeOut &o : per) {
+            all.insert(all.end(), (o.*part).begin(), (o.*part).end());
+            std::vector<Trip>().swap(o.*part);
+        }
+        phase_from_sorted_triples(all, ph);
+    };
+    concat(&NodeOut::gather, out[1]);
+    concat(&NodeOut::cross, out[2]);
+    concat(&NodeOut::scatter, out[3]);
+    if (cross_key) {
+        const Phase &c = out[2];
+        const int64_t nm = (int64_t)c.src.size();
+        std::vector<int64_t> cfirst(n_nodes + 1, nm);
+        for (int64_t k = nm - 1; k >= 0; --k) cfirst[c.src[k] / ppn] = k;
+        for (int64_t x = n_nodes - 1; x >= 0; --x) cfirst[x] = std::min(cfirst[x], cfirst[x + 1]);
+        cross_key->assign(c.idx.size(), 0);
+        cross_pos->assign(c.idx.size(), 0);
+        // per node, sorted by (destination socket, index); the destination
+        // sockets of successive nodes ascend, so the concatenation is sorted
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t node = 0; node < n_nodes; ++node) {
+            const int64_t e0 = cfirst[node] < nm ? c.ptr[cfirst[node]] : (int64_t)c.idx.size();
+            const int64_t e1 = cfirst[node + 1] < nm ? c.ptr[cfirst[node + 1]] : (int64_t)c.idx.size();
+            std::vector<std::pair<int64_t, int64_t>> kp;
+            kp.reserve((size_t)(e1 - e0));
+            for (int64_t k = cfirst[node]; k < cfirst[node + 1]; ++k)
+                for (int64_t e = c.ptr[k]; e < c.ptr[k + 1]; ++e)
+                    kp.emplace_back((int64_t)(c.dst[k] / pps) * n + c.idx[e], e);
+            std::sort(kp.begin(), kp.end());
+            for (size_t x = 0; x < kp.size(); ++x) {
+                (*cross_key)[e0 + x] = kp[x].first;
+                (*cross_pos)[e0 + x] = kp[x].second;
+            }
+        }
+    }
+}
+
+int64_t lookup(const std::vector<int64_t> &keys, const std::vector<int64_t> &vals, int64_t key) {
+    auto it = std::lower_bound(keys.begin(), keys.end(), key);
+    if (it == keys.end() || *it != key) throw Error(NAPSPMV_EINVAL, "socket level: missing route");
+    return vals[it - keys.begin()];
 }
 
 // Statistics of the messages of `ph` for which keep(k) holds (all if null).
@@ -171,7 +371,8 @@ namespace {
 // depends only on which process owns which index, so the plan of the
 // permuted matrix is the strided plan with indices renumbered.
 void build_strided(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
-                   int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode, uint32_t variant) {
+                   int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode, uint32_t variant,
+                   int64_t pps) {
     std::vector<int64_t> st(n_p + 1, 0);
     for (int64_t p = 0; p < n_p; ++p) st[p + 1] = st[p] + (n - p + n_p - 1) / n_p;
     auto pos = [&](int64_t r) { return st[r % n_p] + r / n_p; };
@@ -190,17 +391,134 @@ void build_strided(HostPlan &hp, const int64_t *rowptr, const int32_t *col, cons
         if (len) std::memcpy(&v2[(size_t)(rp[k] * vs)], vb + rowptr[r] * vs, (size_t)(len * vs));
     }
     build_plan(hp, rp.data(), c2.data(), v2.data(), dtype, n, n_p, ppn, mode, st.data(), variant,
-               false);
+               false, pps);
     hp.strided = true;
     hp.rows_natural.swap(natural);
+}
+
+// The socket level of a NAP plan (see the file comment) and its device
+// lists: the cross-socket messages of the fully local step join the send
+// buffer (gathered from v like the inter-node messages), those of the
+// off_node -> on_node step form the l1x buffer (copied from the received
+// buffer), and every ghost whose step crosses a socket reads the cross
+// buffer of its destination socket instead of v or the received buffer.
+void build_sockets(HostPlan &hp, int64_t pps) {
+    hp.pps = pps;
+    const int64_t n = hp.n, ppn = hp.ppn, n_p = hp.n_p;
+    std::vector<int64_t> l1_key, l1_pos, l2_key, l2_pos;
+    socket_route(hp.phase[NAPSPMV_PHASE_L0], n, ppn, pps, hp.sock_phase + 0);
+    socket_route(hp.phase[NAPSPMV_PHASE_L1], n, ppn, pps, hp.sock_phase + 4, &l1_key, &l1_pos);
+    socket_route(hp.phase[NAPSPMV_PHASE_L2], n, ppn, pps, hp.sock_phase + 8, &l2_key, &l2_pos);
+    const int64_t n_sock = n_p / pps;
+    const int64_t E = (int64_t)hp.pack_idx.size();
+    // fully local cross messages: gathered from v into the send buffer
+    const Phase &x2 = hp.sock_phase[8 + 2];
+    for (size_t k = 0; k < x2.src.size(); ++k)
+        for (int64_t e = x2.ptr[k]; e < x2.ptr[k + 1]; ++e) {
+            hp.pack_idx.push_back(x2.idx[e]);
+            hp.pack_group.push_back((int32_t)(hp.n_nodes + x2.dst[k] / pps));
+        }
+    const int64_t E_send = (int64_t)hp.pack_idx.size();
+    // the send-buffer entry holding each received index, per destination node
+    std::vector<int64_t> rkey, rpos;
+    {
+        // bucketed by destination node, each bucket sorted in parallel
+        const Phase &I = hp.phase[NAPSPMV_PHASE_INTER];
+        const int64_t nn = hp.n_nodes;
+        std::vector<int64_t> cnt(nn + 1, 0);
+        for (size_t k = 0; k < I.src.size(); ++k) cnt[I.dst[k] / ppn + 1] += I.ptr[k + 1] - I.ptr[k];
+        for (int64_t x = 0; x < nn; ++x) cnt[x + 1] += cnt[x];
+        std::vector<std::pair<int64_t, int64_t>> kp(I.idx.size());
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (size_t k = 0; k < I.src.size(); ++k) {
+            const int64_t node = I.dst[k] / ppn;
+            for (int64_t e = I.ptr[k]; e < I.ptr[k + 1]; ++e)
+                kp[fill[node]++] = {node * n + I.idx[e], e};
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t x = 0; x < nn; ++x) std::sort(kp.begin() + cnt[x], kp.begin() + cnt[x + 1]);
+        rkey.resize(kp.size());
+        rpos.resize(kp.size());
+        for (size_t x = 0; x < kp.size(); ++x) {
+            rkey[x] = kp[x].first;
+            rpos[x] = kp[x].second;
+        }
+    }
+    // off_node -> on_node cross messages: copied from the received buffer
+    const Phase &x1 = hp.sock_phase[4 + 2];
+    const int64_t E1 = (int64_t)x1.idx.size();
+    hp.l1x_col.assign(x1.idx.begin(), x1.idx.end());
+    hp.l1x_src.resize(E1);
+    hp.l1x_group.resize(E1);
+    bool unrouted = false;
+#pragma omp parallel for schedule(dynamic, 16) reduction(|| : unrouted)
+    for (int64_t k = 0; k < (int64_t)x1.src.size(); ++k)
+        for (int64_t e = x1.ptr[k]; e < x1.ptr[k + 1]; ++e) {
+            const int64_t key = (int64_t)(x1.src[k] / ppn) * n + x1.idx[e];
+            auto it = std::lower_bound(rkey.begin(), rkey.end(), key);
+            if (it == rkey.end() || *it != key) {
+                unrouted = true;
+                continue;
+            }
+            hp.l1x_src[e] = (int32_t)rpos[it - rkey.begin()];
+            hp.l1x_group[e] = (int32_t)(hp.n_nodes + n_sock + x1.dst[k] / pps);
+        }
+    if (unrouted) throw Error(NAPSPMV_EINVAL, "socket level: missing route");
+    // re-route the ghosts whose step crosses a socket
+    auto rank_of_slot = [&](int64_t slot) {
+        return (int64_t)(std::upper_bound(hp.ghost_ptr.begin(), hp.ghost_ptr.end(), slot) -
+                         hp.ghost_ptr.begin()) - 1;
+    };
+    const Phase &I = hp.phase[NAPSPMV_PHASE_INTER];
+    std::vector<int32_t> recv_rank(E);
+    for (size_t k = 0; k < I.src.size(); ++k)
+        for (int64_t e = I.ptr[k]; e < I.ptr[k + 1]; ++e) recv_rank[e] = I.dst[k];
+    bool missing = false;
+#pragma omp parallel for schedule(static) reduction(|| : missing)
+    for (int64_t k = 0; k < (int64_t)hp.scat_src.size(); ++k) {
+        const int64_t t = rank_of_slot(hp.scat_dst[k]);
+        const int64_t e = hp.scat_src[k], q = recv_rank[e];
+        if (q != t && q / pps != t / pps) {
+            const int64_t key = (t / pps) * n + I.idx[e];
+            auto it = std::lower_bound(l1_key.begin(), l1_key.end(), key);
+            if (it == l1_key.end() || *it != key)
+                missing = true;
+            else
+                hp.scat_src[k] = (int32_t)(E_send + l1_pos[it - l1_key.begin()]);
+        }
+    }
+    if (missing) throw Error(NAPSPMV_EINVAL, "socket level: missing route");
+    std::vector<int32_t> ls, ld;
+    for (size_t k = 0; k < hp.l2_src.size(); ++k) {
+        const int64_t t = rank_of_slot(hp.l2_dst[k]);
+        const int32_t j = hp.l2_src[k];
+        const int64_t own = std::upper_bound(hp.starts.begin(), hp.starts.end(), (int64_t)j) -
+                            hp.starts.begin() - 1;
+        if (own / pps == t / pps) {
+            ls.push_back(j);
+            ld.push_back(hp.l2_dst[k]);
+        } else {
+            hp.scat_src.push_back((int32_t)(E + lookup(l2_key, l2_pos, (t / pps) * n + j)));
+            hp.scat_dst.push_back(hp.l2_dst[k]);
+        }
+    }
+    hp.l2_src.swap(ls);
+    hp.l2_dst.swap(ld);
+    if (E_send + (int64_t)hp.l1x_col.size() > kInt32Max)
+        throw Error(NAPSPMV_EUNSUPPORTED, "send and cross-socket buffers must stay below 2^31 - 2^16");
 }
 
 }  // namespace
 
 void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
-                const int64_t *row_starts, uint32_t variant, bool strided) {
+                const int64_t *row_starts, uint32_t variant, bool strided, int64_t pps) {
     validate(rowptr, col, val, dtype, n, n_p, ppn, mode, row_starts);
+    if (pps != 0) {
+        if (mode != NAPSPMV_NAP) throw Error(NAPSPMV_EINVAL, "the socket level needs a NAP plan");
+        if (pps < 1 || ppn % pps != 0) throw Error(NAPSPMV_EINVAL, "procs_per_socket must divide ppn");
+        if (variant) throw Error(NAPSPMV_EINVAL, "the socket level takes no NAP plan variant");
+    }
     if (variant & ~kVariantFlags) throw Error(NAPSPMV_EINVAL, "unknown plan variant flag");
     if (variant && mode != NAPSPMV_NAP)
         throw Error(NAPSPMV_EINVAL, "plan variant flags apply to NAP plans only");
@@ -213,7 +531,7 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
             throw Error(NAPSPMV_EINVAL,
                         "the split variant cuts E(n, m) in index order, which a strided "
                         "partition does not keep");
-        build_strided(hp, rowptr, col, val, dtype, n, n_p, ppn, mode, variant);
+        build_strided(hp, rowptr, col, val, dtype, n, n_p, ppn, mode, variant, pps);
         return;
     }
     hp.n = n;
@@ -686,8 +1004,16 @@ void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const v
             hp.phase[NAPSPMV_PHASE_L2] = Phase();
             finalize_phase(refs, hp.phase[NAPSPMV_PHASE_L2]);
         }
+        // send-buffer groups: the destination node of every inter-node entry
+        const Phase &I = hp.phase[NAPSPMV_PHASE_INTER];
+        hp.pack_group.resize(hp.pack_idx.size());
+        for (size_t k = 0; k < I.src.size(); ++k)
+            for (int64_t e = I.ptr[k]; e < I.ptr[k + 1]; ++e)
+                hp.pack_group[e] = (int32_t)(I.dst[k] / ppn);
+        if (pps > 0) build_sockets(hp, pps);
     }
     for (int ph = 0; ph < 4; ++ph) hp.stats[ph] = phase_stats(hp.phase[ph], n_p);
+    for (int ph = 0; ph < 12; ++ph) hp.sock_stats[ph] = phase_stats(hp.sock_phase[ph], n_p);
 }
 
 }  // namespace napspmv

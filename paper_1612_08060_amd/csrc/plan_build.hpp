@@ -70,19 +70,41 @@ struct HostPlan {
     Phase phase[4];                    // INTER, L0, L1, L2
     PhaseStats stats[4];
 
+    // Third hierarchy level (sockets of `pps` consecutive ranks; 0 = none):
+    // the socket routes of the three intra-node steps, sock_phase[4 (s - 1)
+    // + part] for step s = L0, L1, L2 and part = on, gather, cross,
+    // scatter (NAPSPMV_PHASE_L0_ON ... minus 4).
+    int64_t pps = 0;
+    Phase sock_phase[12];
+    PhaseStats sock_stats[12];
+
     // Device index lists.
     std::vector<int32_t> gather_idx;              // standard: ghost[k] = v[gather_idx[k]]
-    std::vector<int32_t> pack_idx;                // NAP: send[k] = v[pack_idx[k]]
-    std::vector<int32_t> scat_src, scat_dst;      // NAP: ghost[scat_dst[k]] = recv[scat_src[k]]
-    std::vector<int32_t> l2_src, l2_dst;          // NAP: ghost[l2_dst[k]] = v[l2_src[k]]
+    // NAP: send[k] = v[pack_idx[k]]: the inter-node messages in canonical
+    // order, then (socket plans) the cross-socket messages of the fully
+    // local step; pack_group[k] groups the entries of one destination (node
+    // or socket) inside a column band of the send buffer
+    std::vector<int32_t> pack_idx, pack_group;
+    // socket plans: cross-socket messages of the off_node -> on_node step,
+    // l1x[k] = recv[l1x_src[k]] (entries of the send buffer), column
+    // l1x_col[k], grouped by destination socket
+    std::vector<int32_t> l1x_col, l1x_src, l1x_group;
+    // NAP: ghost[scat_dst[k]] = received value scat_src[k] (an entry of the
+    // send buffer, or pack_idx.size() + an entry of l1x);
+    // ghost[l2_dst[k]] = v[l2_src[k]]
+    std::vector<int32_t> scat_src, scat_dst;
+    std::vector<int32_t> l2_src, l2_dst;
 };
 
 // Validates the inputs and builds the plan.  `variant` holds NAPSPMV_NAP_*
 // flags (NAP mode only); `strided` selects the strided partition (then
 // row_starts must be NULL).  Throws Error or std::bad_alloc.
+// `pps` > 0 (NAP mode, no variant) adds the socket level: sockets of pps
+// consecutive ranks (pps dividing ppn).
 void build_plan(HostPlan &hp, const int64_t *rowptr, const int32_t *col, const void *val,
                 int dtype, int64_t n, int64_t n_p, int64_t ppn, int mode,
-                const int64_t *row_starts, uint32_t variant, bool strided = false);
+                const int64_t *row_starts, uint32_t variant, bool strided = false,
+                int64_t pps = 0);
 
 // Message statistics split by a third hierarchy level (section 6 names
 // on-socket and off-socket intra-node messages): sockets of `pps`
