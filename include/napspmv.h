@@ -329,10 +329,13 @@ NAPSPMV_API int64_t napspmv_noalloc_max_workspace_bytes(void);
  * EINVAL), be on the batch's device, receive
  * NAP messages in place and use the two-part product (no NAPSPMV_NAP_THREE_WAY).  ws may be NULL (every plan's own workspace) or hold
  * per-product workspaces (NULL entries = the plan's own).  The batch object
- * owns a device descriptor table (and a pinned host copy) for up to
- * max_count products; a call waits until the previous call's launches have
- * read the table, so use one batch object per stream.  napspmv_batch_apply
- * allocates nothing.
+ * owns a ring of 4 device descriptor tables (each with a pinned host copy)
+ * for up to max_count products: call k uploads table k mod 4 with an
+ * asynchronous copy, and waits for the device only if the call 4 before it
+ * has not yet been read.  Use one batch object per stream.  A graph that
+ * captures a call replays the upload of that call's table, which later
+ * calls of the same object overwrite: give captured calls a batch object of
+ * their own.  napspmv_batch_apply allocates nothing.
  */
 NAPSPMV_API int napspmv_batch_create(int max_count, napspmv_batch_t *out);
 NAPSPMV_API int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *plans,

@@ -97,14 +97,20 @@ struct napspmv_plan_s {
     double build_s = 0, upload_s = 0;
 };
 
+// A batch object owns a ring of descriptor tables: call k fills table
+// k mod kBatchRing, so a call waits for the device only when the call
+// kBatchRing before it has not yet been read.
+constexpr int kBatchRing = 4;
+
 struct napspmv_batch_s {
     int capacity = 0;
     int device = 0;
-    void *d_desc = nullptr;          // device descriptor table
-    void *h_desc = nullptr;          // pinned host staging of the table
     size_t desc_bytes = 0;
-    hipEvent_t done = nullptr;       // recorded after the last batch's launches
-    bool pending = false;
+    int next = 0;                            // table of the next call
+    void *d_desc[kBatchRing] = {};           // device descriptor tables
+    void *h_desc[kBatchRing] = {};           // their pinned host staging
+    hipEvent_t done[kBatchRing] = {};        // recorded after the launches that read each
+    bool pending[kBatchRing] = {};
 };
 
 namespace {
@@ -950,8 +956,8 @@ void batch_launch(napspmv_batch_s *B, int count, const napspmv_plan_t *plans, vo
                   const void *const *v, void *const *w, hipStream_t s) {
     using namespace napspmv;
     const BatchTable t = batch_table<VT, XT>(count);
-    char *h = static_cast<char *>(B->h_desc);
-    char *d = static_cast<char *>(B->d_desc);
+    char *h = static_cast<char *>(B->h_desc[B->next]);
+    char *d = static_cast<char *>(B->d_desc[B->next]);
     int32_t *pl = reinterpret_cast<int32_t *>(h + t.pre_local);
     int32_t *ps = reinterpret_cast<int32_t *>(h + t.pre_scatter);
     int32_t *pr = reinterpret_cast<int32_t *>(h + t.pre_remote);
@@ -1296,17 +1302,15 @@ int napspmv_batch_create(int max_count, napspmv_batch_t *out) {
         b->capacity = max_count;
         HIP_OK(hipGetDevice(&b->device));
         b->desc_bytes = batch_bytes(max_count);
-        HIP_OK(hipMalloc(&b->d_desc, b->desc_bytes));
-        HIP_OK(hipHostMalloc(&b->h_desc, b->desc_bytes, hipHostMallocDefault));
-        HIP_OK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+        for (int k = 0; k < kBatchRing; ++k) {
+            HIP_OK(hipMalloc(&b->d_desc[k], b->desc_bytes));
+            HIP_OK(hipHostMalloc(&b->h_desc[k], b->desc_bytes, hipHostMallocDefault));
+            HIP_OK(hipEventCreateWithFlags(&b->done[k], hipEventDisableTiming));
+        }
         *out = b;
         return NAPSPMV_OK;
     });
-    if (rc != NAPSPMV_OK && b) {
-        if (b->d_desc) (void)hipFree(b->d_desc);
-        if (b->h_desc) (void)hipHostFree(b->h_desc);
-        delete b;
-    }
+    if (rc != NAPSPMV_OK && b) napspmv_batch_destroy(b);
     return rc;
 }
 
@@ -1332,8 +1336,10 @@ int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *
     return guarded([&]() {
         DeviceGuard g(batch->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        // the descriptor table is reused: the previous batch must be done with it
-        if (batch->pending) HIP_OK(hipEventSynchronize(batch->done));
+        // the ring's next table is reused: the call that last filled it must
+        // have been read by the device
+        const int k = batch->next;
+        if (batch->pending[k]) HIP_OK(hipEventSynchronize(batch->done[k]));
         switch (p0->hp.dtype) {
             case NAPSPMV_F64:
                 batch_launch_t<double, double>(p0->cur_block_nnz, p0->cur_window, batch, count,
@@ -1348,8 +1354,9 @@ int napspmv_batch_apply(napspmv_batch_t batch, int count, const napspmv_plan_t *
                                                 plans, ws, v, w, s);
                 break;
         }
-        HIP_OK(hipEventRecord(batch->done, s));
-        batch->pending = true;
+        HIP_OK(hipEventRecord(batch->done[k], s));
+        batch->pending[k] = true;
+        batch->next = (k + 1) % kBatchRing;
         return NAPSPMV_OK;
     });
 }
@@ -1358,10 +1365,12 @@ int napspmv_batch_destroy(napspmv_batch_t batch) {
     if (!batch) return NAPSPMV_OK;
     try {
         DeviceGuard g(batch->device);
-        if (batch->pending) (void)hipEventSynchronize(batch->done);
-        if (batch->done) (void)hipEventDestroy(batch->done);
-        if (batch->d_desc) (void)hipFree(batch->d_desc);
-        if (batch->h_desc) (void)hipHostFree(batch->h_desc);
+        for (int k = 0; k < kBatchRing; ++k) {
+            if (batch->pending[k]) (void)hipEventSynchronize(batch->done[k]);
+            if (batch->done[k]) (void)hipEventDestroy(batch->done[k]);
+            if (batch->d_desc[k]) (void)hipFree(batch->d_desc[k]);
+            if (batch->h_desc[k]) (void)hipHostFree(batch->h_desc[k]);
+        }
     } catch (const Error &) {
     }
     delete batch;
