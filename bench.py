@@ -235,10 +235,19 @@ def config_row(torch, nap, plan, v, w, nbytes, steps, warmup, flush, nnz=None, g
     if nnz is not None:
         row["gflops_cold"] = round(2 * nnz / (cm * 1e-3) / 1e9, 1)
     if graph:
-        g = plan.graph(v, w)
-        reps = 200
-        row[f"graph_{unit}_per_apply"] = round(_time_ms(torch, g.launch, reps) * scale, 3)
-        g.close()
+        # 50 back-to-back applies captured in one HIP graph: per-apply device
+        # time without the host's launch overhead
+        cg = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        with torch.cuda.stream(cs):
+            plan.apply(v, w, stream=cs)
+            cs.synchronize()
+            with torch.cuda.graph(cg, stream=cs):
+                for _ in range(50):
+                    plan.apply(v, w, stream=cs)
+        torch.cuda.synchronize()
+        row[f"graph_{unit}_per_apply"] = round(_time_ms(torch, cg.replay, 5) / 50 * scale, 4)
+        del cg
     return row
 
 
@@ -703,6 +712,21 @@ def main():
                              for side in ("on_socket", "off_socket")}
                          for k in ("L0", "L1", "L2") if mode == "nap" or k == "L2"}
         result["socket_level"] = lev
+        # the socket level as a plan: each intra-node step routed per socket pair
+        pk = nap.Plan(a.rowptr, a.col, a.val, a.n, wl.n_p, wl.ppn, mode="nap", dtype="f64",
+                      row_starts=wl.row_starts, sockets=8)
+        wk = torch.empty_like(v)
+        tk, _, _, _ = time_applies(torch, pk, v, wk, nap, steps2, 2)
+        torch.cuda.synchronize()
+        sk = pk.socket_stats()
+        lev["socket_plan"] = {
+            "build_s": round(pk.stats["build_seconds"], 3), "warm_ms": pct(tk),
+            "bitwise_equal_to_standard": bool(torch.equal(w, wk)),
+            "workspace_bytes": pk.workspace_bytes,
+            "phases": {k: {"msgs": x["msgs"], "elems": x["elems"], "max_msgs_sent": x["max_msgs_sent"]}
+                       for k, x in sk.items()}}
+        pk.close()
+        del wk
         # strided partition (row r on process r mod n_p): process-major v and w
         strided = {}
         for mode in ("standard", "nap"):
