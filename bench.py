@@ -549,16 +549,19 @@ def main():
     # write-only flush
     cold, c_loc, c_rem, _ = time_applies(torch, plan, v, w, nap, args.steps, args.warmup, flush)
     warm, w_loc, w_rem, wall = time_applies(torch, plan, v, w, nap, args.steps, args.warmup)
-    cold_wo, _, _, _ = time_applies(torch, plan, v, w, nap, args.steps, 0,
-                                    Flush(torch, dev, write_only=True))
+    cold_wo, o_loc, o_rem, _ = time_applies(torch, plan, v, w, nap, args.steps, 0,
+                                            Flush(torch, dev, write_only=True))
     total = apply_bytes(st, 8, 8)
     rows_off = rows_with_off_entries(a, wl.n_p, wl.row_starts)
     lb, rb = launch_bytes(st, 8, 8, rows_off)
     ms = float(np.median(cold))
     log(f"apply cold median {ms:.4f} ms, warm median {np.median(warm):.4f} ms "
         f"(cold local {np.mean(c_loc):.4f}, remote {np.mean(c_rem):.4f})")
-    # roofline of the dominant launch: its mean duration over the cold applies
-    loc_ms, rem_ms = float(np.mean(c_loc)), float(np.mean(c_rem))
+    # roofline of the dominant launch: its mean duration over every timed
+    # launch (cold, warm and write-only cold), the average a kernel trace of
+    # the same command reports
+    loc_ms = float(np.mean(c_loc + w_loc + o_loc))
+    rem_ms = float(np.mean(c_rem + w_rem + o_rem))
     dom = "k_local" if loc_ms >= rem_ms else "k_remote"
     dom_ms, dom_bytes = (loc_ms, lb) if dom == "k_local" else (rem_ms, rb)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
@@ -584,7 +587,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(f"{dom}_kkt_f64"), "kernel": dom,
-                     "kernel_ms": round(dom_ms, 5), "kernel_bytes": dom_bytes},
+                     "kernel_ms": round(dom_ms, 5), "kernel_bytes": dom_bytes,
+                     "kernel_ms_is": "mean of every timed launch (cold, warm, write-only cold)"},
         "timing": {"cold_ms": pct(cold), "warm_ms": pct(warm), "cold_write_only_ms": pct(cold_wo),
                    "warm_wall_ms_per_apply": round(wall, 5),
                    "cold_launch_ms": {"k_local": pct(c_loc), "k_remote": pct(c_rem)},
@@ -595,8 +599,10 @@ def main():
                              "warm": round(gbs_warm / PEAK_HBM_GBS, 4)},
         "copy_denominator": dict(copy, frac_cold=round(gbs_cold / copy["gbs"], 4)),
         "gflops": round(2 * a.nnz / (ms * 1e-3) / 1e9, 1),
-        "launches": {"k_local": {"bytes": lb, "gbs_cold": round(lb / (loc_ms * 1e-3) / 1e9, 1)},
-                     "k_remote": {"bytes": rb, "gbs_cold": round(rb / (rem_ms * 1e-3) / 1e9, 1)}},
+        "launches": {"k_local": {"bytes": lb, "mean_ms": round(loc_ms, 5),
+                                 "gbs": round(lb / (loc_ms * 1e-3) / 1e9, 1)},
+                     "k_remote": {"bytes": rb, "mean_ms": round(rem_ms, 5),
+                                  "gbs": round(rb / (rem_ms * 1e-3) / 1e9, 1)}},
         "plan_build_s": {"standard": round(st["build_seconds"], 3)},
     }
     plan.close()
