@@ -458,9 +458,11 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
  * device plan rebuilds and re-uploads the launch schedules (it allocates and
  * synchronizes the device): do not call it while an apply of the plan is in
  * flight.
- *   BLOCK_NNZ     entries per row block of the on-process product, and
- *                 columns of v per band of the exchange buffers: 1024, 2048,
- *                 4096, 8192 (automatic: 4096)
+ *   BLOCK_NNZ     entries per row block of the on-process product (a block
+ *                 of several rows holds at most BLOCK_NNZ - 7, so that its
+ *                 aligned vector loads stay within BLOCK_NNZ), and columns
+ *                 of v per band of the exchange buffers: 1024, 2048, 4096,
+ *                 8192 (automatic: 4096)
  *   REMOTE_NNZ    entries per row block of the off-process product: 1024,
  *                 2048, 4096, 8192 (automatic: 8192 when the plan has at
  *                 least 8192 off-process entries per process, else 4096)

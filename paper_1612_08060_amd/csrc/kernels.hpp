@@ -100,17 +100,49 @@ __device__ __forceinline__ void store_out(T x, T *p) {
         *p = x;
 }
 
+// E consecutive entries of an E-aligned run of an array, as one vector.
+template <typename T, int E>
+using Vec = T __attribute__((ext_vector_type(E)));
+
+template <int E, typename T>
+__device__ __forceinline__ Vec<T, E> load_vec(const T *p, int32_t k) {
+    return __builtin_nontemporal_load(reinterpret_cast<const Vec<T, E> *>(p + k));
+}
+
+// dst[k] = lds[off[k]] for k in [begin, end), by aligned runs of E = 16 bytes
+// of values: each lane loads E offsets at once and stores E values with one
+// 16-byte store, so a wave moves several entries' bytes per instruction and
+// every store instruction writes whole lines; the few entries before the
+// first and after the last aligned run go one per lane.
 template <typename T, bool NT>
-__device__ __forceinline__ void band_copy(int32_t k, int32_t end, const uint16_t *__restrict__ off,
-                                          T *__restrict__ dst, const T *lds) {
-    for (; k + 7 * kBlock < end; k += 8 * kBlock) {
-        uint16_t o[8];
+__device__ __forceinline__ void band_copy(int32_t begin, int32_t end,
+                                          const uint16_t *__restrict__ off, T *__restrict__ dst,
+                                          const T *lds) {
+    constexpr int E = 16 / sizeof(T);
+    const int32_t tid = (int32_t)threadIdx.x;
+    const int32_t a = min((begin + E - 1) & -E, end), b = max(end & -E, a);
+    if (begin + tid < a) store_out<NT>(lds[off[begin + tid]], dst + begin + tid);
+    if (b + tid < end) store_out<NT>(lds[off[b + tid]], dst + b + tid);
+    int32_t q = a + E * tid;
+    for (; q + 3 * E * kBlock < b; q += 4 * E * kBlock) {
+        Vec<uint16_t, E> o[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) o[u] = __builtin_nontemporal_load(off + k + u * kBlock);
+        for (int u = 0; u < 4; ++u) o[u] = load_vec<E>(off, q + E * u * kBlock);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) store_out<NT>(lds[o[u]], dst + k + u * kBlock);
+        for (int u = 0; u < 4; ++u) {
+            Vec<T, E> x;
+#pragma unroll
+            for (int j = 0; j < E; ++j) x[j] = lds[o[u][j]];
+            store_out<NT>(x, reinterpret_cast<Vec<T, E> *>(dst + q + E * u * kBlock));
+        }
     }
-    for (; k < end; k += kBlock) store_out<NT>(lds[__builtin_nontemporal_load(off + k)], dst + k);
+    for (; q < b; q += E * kBlock) {
+        const Vec<uint16_t, E> o = load_vec<E>(off, q);
+        Vec<T, E> x;
+#pragma unroll
+        for (int j = 0; j < E; ++j) x[j] = lds[o[j]];
+        store_out<NT>(x, reinterpret_cast<Vec<T, E> *>(dst + q));
+    }
 }
 
 template <typename T, int CAP>
@@ -120,15 +152,15 @@ __device__ __forceinline__ void exchange_item(int4 it, int32_t n, const uint16_t
                                               const T *__restrict__ src, T *__restrict__ dst,
                                               T *lds, bool nt) {
     const int32_t end = it.y + it.z;
-    int32_t k = it.y + (int32_t)threadIdx.x;
     if (it.x >= 0) {
         stage_band<T, CAP>(it.x, n, src, lds);
         if (nt)
-            band_copy<T, true>(k, end, off, dst, lds);
+            band_copy<T, true>(it.y, end, off, dst, lds);
         else
-            band_copy<T, false>(k, end, off, dst, lds);
+            band_copy<T, false>(it.y, end, off, dst, lds);
         return;
     }
+    int32_t k = it.y + (int32_t)threadIdx.x;
     for (; k + 3 * kBlock < end; k += 4 * kBlock) {
         int32_t j[4], d[4];
 #pragma unroll
@@ -216,7 +248,7 @@ __device__ __forceinline__ void pack_scatter_item(int4 it, int32_t n, const uint
                                                   const T *recv, T *__restrict__ ghost, T *lds,
                                                   bool nt) {
     stage_band<T, CAP>(it.x, n, v, lds);
-    band_copy<T, false>(it.y + (int32_t)threadIdx.x, it.y + it.z, off, send, lds);
+    band_copy<T, false>(it.y, it.y + it.z, off, send, lds);
     // the band's packed values are visible to the whole workgroup (recv and
     // send are the same memory: no restrict on either)
     __syncthreads();
@@ -378,6 +410,126 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
     }
 }
 
+// A stored value of A widened into the accumulation type.
+__device__ __forceinline__ double widen(double a) { return a; }
+__device__ __forceinline__ float widen(float a) { return a; }
+__device__ __forceinline__ float widen(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Entries per lane of the on-process product: runs of 16 bytes of values
+// (more for bfloat16, whose columns and values are both 2 bytes).
+template <typename VT, int CAP>
+constexpr int product_run() {
+    constexpr int e = sizeof(VT) == 8 ? 2 : (sizeof(VT) == 4 ? 4 : 8);
+    return e * kBlock <= CAP ? e : CAP / kBlock;
+}
+
+// On-process row block with E consecutive entries per lane: each lane loads
+// the columns and values of its entries as aligned runs (one vector load
+// each), so a wave moves E times the bytes per load instruction of
+// product_block's one entry per lane, and writes its E products to LDS with
+// one vector store.  The runs cover [k0 & -E, k1); LDS position q holds the
+// product of entry (k0 & -E) + q.  Entries of the runs outside [k0, k1) (a
+// neighbouring block's, or the arrays' zero padding past the last entry) are
+// loaded and discarded, and their columns are not used to read v.  Each row
+// adds its products in stored order, as in product_block, so the sums are
+// the same.  A block whose aligned span is longer than CAP (the schedules
+// leave only single rows so long) or that is empty goes to product_block.
+// E > 1.
+template <typename VT, typename XT, typename CT, int CAP, int W, bool NTW, int E>
+__device__ __forceinline__ void local_product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
+                                                   int2 win, const int32_t *__restrict__ rowptr,
+                                                   const CT *__restrict__ col, int32_t cbase,
+                                                   const VT *__restrict__ val,
+                                                   const XT *__restrict__ xsrc,
+                                                   XT *__restrict__ w, XT *prod, XT *wbuf) {
+    const int32_t k0a = k0 & -E;
+    if (k1 == k0 || k1 - k0a > CAP) {
+        product_block<VT, XT, CT, CAP, W, false, false, NTW>(r0, r1, k0, k1, win, rowptr, col,
+                                                              cbase, val, nullptr, xsrc, w, prod,
+                                                              wbuf);
+        return;
+    }
+    constexpr int Q = CAP / (E * kBlock);
+    constexpr int R = kMaxRows / kBlock;
+    const int32_t tid = (int32_t)threadIdx.x;
+    // lanes past the block load its last run (every load unconditional, as
+    // in product_block)
+    const int32_t klast = (k1 - 1) & -E;
+    int32_t c[E * Q];
+    XT a[E * Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+        const int32_t e = min(k0a + E * (u * kBlock + tid), klast);
+        const Vec<CT, E> cq = load_vec<E>(col, e);
+        const Vec<VT, E> aq = load_vec<E>(val, e);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            c[E * u + j] = cbase + (int32_t)cq[j];
+            a[E * u + j] = widen(aq[j]);
+        }
+    }
+    XT t[W > 0 ? W / kBlock : 1];
+    if (W > 0) {
+        const int32_t qlast = win.y > 0 ? win.y - 1 : 0;
+#pragma unroll
+        for (int u = 0; u < W / kBlock; ++u) t[u] = xsrc[win.x + min(u * kBlock + tid, qlast)];
+    }
+    int32_t rb[R], re[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int32_t r = min(r0 + i * kBlock + tid, r1 - 1);
+        rb[i] = rowptr[r];
+        re[i] = rowptr[r + 1];
+    }
+    XT x[E * Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int32_t e = k0a + E * (u * kBlock + tid) + j;
+            // a column outside the block may be another process's offset:
+            // read the block's own first column of v instead
+            if (e < k0 || e >= k1) c[E * u + j] = cbase;
+            const int32_t cc = c[E * u + j];
+            const bool inwin = W > 0 && (uint32_t)(cc - win.x) < (uint32_t)win.y;
+            x[E * u + j] = xsrc[inwin ? win.x : cc];
+        }
+    }
+    if (W > 0) {
+#pragma unroll
+        for (int u = 0; u < W / kBlock; ++u) {
+            const int32_t q = u * kBlock + tid;
+            if (q < win.y) wbuf[q] = t[u];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+        const int32_t e0 = k0a + E * (u * kBlock + tid);
+        if (e0 < k1) {
+            Vec<XT, E> pv;
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int32_t cc = c[E * u + j];
+                XT xv = x[E * u + j];
+                if (W > 0 && (uint32_t)(cc - win.x) < (uint32_t)win.y) xv = wbuf[cc - win.x];
+                pv[j] = a[E * u + j] * xv;
+            }
+            *reinterpret_cast<Vec<XT, E> *>(prod + (e0 - k0a)) = pv;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int32_t r = r0 + i * kBlock + tid;
+        if (r < r1) {
+            XT acc = (XT)0;
+            for (int32_t q = rb[i] - k0a; q < re[i] - k0a; ++q) acc = acc + prod[q];
+            store_out<NTW>(acc, w + r);
+        }
+    }
+}
+
 // Everything one product needs, by launch.  A plain launch passes one view by
 // value; a batched launch reads views from a device table.
 template <typename VT, typename XT>
@@ -433,9 +585,16 @@ template <typename VT, typename XT, typename CT, int CAP, int W, bool NT>
 __device__ __forceinline__ void local_block(const LocalView<VT, XT> &L, int32_t task, const CT *col,
                                             int32_t cbase, XT *prod, XT *wbuf) {
     const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
-    product_block<VT, XT, CT, CAP, W, false, false, NT>(
-        L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr, col,
-        cbase, L.val, nullptr, L.v, L.w, prod, wbuf);
+    constexpr int E = product_run<VT, CAP>();
+    if constexpr (E == 1)
+        product_block<VT, XT, CT, CAP, W, false, false, NT>(
+            L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
+            col, cbase, L.val, nullptr, L.v, L.w, prod, wbuf);
+    else
+        local_product_runs<VT, XT, CT, CAP, W, NT, E>(L.rowblk[task], L.rowblk[task + 1],
+                                                      L.blkptr[task], L.blkptr[task + 1], wn,
+                                                      L.rowptr, col, cbase, L.val, L.v, L.w,
+                                                      prod, wbuf);
 }
 
 template <typename VT, typename XT, int CAP, int W>
@@ -500,7 +659,7 @@ __device__ __forceinline__ int32_t find_range(const int32_t *__restrict__ prefix
 // task list, so every CU runs both at once.
 template <typename VT, typename XT, int CAP, int W>
 __global__ __launch_bounds__(kBlock) void k_local(LocalView<VT, XT> L) {
-    __shared__ XT prod[CAP];
+    __shared__ __align__(32) XT prod[CAP];
     __shared__ XT wbuf[W > 0 ? W : 1];
     local_task<VT, XT, CAP, W>(L, (int32_t)xcd_block(blockIdx.x, gridDim.x), prod, wbuf);
 }
@@ -518,7 +677,7 @@ template <typename VT, typename XT, int CAP, int W>
 __global__ __launch_bounds__(kBlock) void k_local_batch(const LocalView<VT, XT> *__restrict__ views,
                                                         const int32_t *__restrict__ prefix,
                                                         int32_t count) {
-    __shared__ XT prod[CAP];
+    __shared__ __align__(32) XT prod[CAP];
     __shared__ XT wbuf[W > 0 ? W : 1];
     const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
     const int32_t i = find_range(prefix, count, b);

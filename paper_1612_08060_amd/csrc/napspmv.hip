@@ -203,10 +203,17 @@ Ws ws_ptrs(const napspmv_plan_s *p, void *base) {
 // Device arrays are never empty and start zeroed: the product kernels read
 // clamped dummy entries (index 0 of an empty part) whose values they discard.
 constexpr size_t kMinAlloc = 256;
+// Entries of zero padding after the on-process columns and values: the
+// on-process product loads aligned runs of up to 8 entries, up to seven
+// entries past a block.
+constexpr size_t kQuadPad = 8;
+// On-process row blocks hold at most block_nnz - 7 entries, so that the
+// aligned runs over a block of several rows stay within block_nnz.
+constexpr int kQuadSlack = 7;
 
 template <typename T>
-void upload(T *&dst, const std::vector<T> &src, int64_t &total) {
-    const size_t bytes = src.size() * sizeof(T), cap = std::max(bytes, kMinAlloc);
+void upload(T *&dst, const std::vector<T> &src, int64_t &total, size_t pad = 0) {
+    const size_t bytes = src.size() * sizeof(T), cap = std::max(bytes + pad * sizeof(T), kMinAlloc);
     HIP_OK(hipMalloc(reinterpret_cast<void **>(&dst), cap));
     total += (int64_t)cap;
     if (bytes) HIP_OK(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
@@ -269,6 +276,7 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
                           hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
     b += (int64_t)(hp.rowptr_nd.size() + hp.col_nd.size()) * 4 + (int64_t)hp.val_nd.size();
     b += (int64_t)(hp.col_off.size() + hp.col_nd.size()) * 2;   // gather-order slots
+    b += (int64_t)kQuadPad * (4 + hp.value_size);                 // on-process padding
     // band offsets (ghosts or send entries) and, for NAP, the scatter codes
     const int64_t gd = p->G + ghost_slack(p->G);
     b += hp.mode == NAPSPMV_NAP ? p->E * 2 + gd * 4 : gd * 2;
@@ -348,7 +356,8 @@ void build_partitions(napspmv_plan_s *p) {
     for (int64_t t = 0; t < hp.n_p; ++t) {
         const int64_t r0 = hp.starts[t], r1 = hp.starts[t + 1];
         std::vector<int32_t> ob, op, fb, fp, it, ts, wn;
-        napspmv::row_blocks(hp.rowptr_on.data() + r0, r1 - r0, cap, kMaxRowsPerBlock, ob, op);
+        napspmv::row_blocks(hp.rowptr_on.data() + r0, r1 - r0, cap - kQuadSlack, kMaxRowsPerBlock,
+                            ob, op);
         napspmv::row_blocks(hp.rowptr_off.data() + r0, r1 - r0, cur_rcap(p), kMaxRowsPerBlock, fb, fp);
         for (auto &x : ob) x += (int32_t)r0;
         for (auto &x : fb) x += (int32_t)r0;
@@ -625,8 +634,8 @@ void refresh_schedules(napspmv_plan_s *p) {
     int64_t tail = napspmv::kItemTail;
     // on-process blocks never span two processes: each block's columns are
     // offsets from its process's first row
-    napspmv::row_blocks_per_process(hp.rowptr_on.data(), hp.starts, cap, kMaxRowsPerBlock, onblk,
-                                    onptr);
+    napspmv::row_blocks_per_process(hp.rowptr_on.data(), hp.starts, cap - kQuadSlack,
+                                    kMaxRowsPerBlock, onblk, onptr);
     onbase.resize(onblk.size() - 1);
     for (size_t b = 0; b + 1 < onblk.size(); ++b)
         onbase[b] = (int32_t)hp.starts[(std::upper_bound(hp.starts.begin(), hp.starts.end(), onblk[b]) -
@@ -716,9 +725,9 @@ void to_device(napspmv_plan_s *p) {
             for (int64_t t = 0; t < hp.n_p; ++t)
                 for (int64_t k = hp.rowptr_on[hp.starts[t]]; k < hp.rowptr_on[hp.starts[t + 1]]; ++k)
                     c16[k] = (uint16_t)(hp.col_on[k] - hp.starts[t]);
-            upload(p->d_col16_on, c16, total);
+            upload(p->d_col16_on, c16, total, kQuadPad);
         } else {
-            upload(p->d_col_on, hp.col_on, total);
+            upload(p->d_col_on, hp.col_on, total, kQuadPad);
         }
         upload(p->d_rp_off, hp.rowptr_off, total);
         auto alloc = [&](auto *&dst, size_t bytes) {
@@ -732,15 +741,15 @@ void to_device(napspmv_plan_s *p) {
         alloc(p->d_col_off, hp.col_off.size() * 4);
         alloc(p->d_val_off, hp.val_off.size());
         alloc(p->d_slot_off, hp.col_off.size() * 2);
-        auto upload_bytes = [&](void *&dst, const std::vector<uint8_t> &src) {
-            const size_t cap = std::max(src.size(), kMinAlloc);
+        auto upload_bytes = [&](void *&dst, const std::vector<uint8_t> &src, size_t pad) {
+            const size_t cap = std::max(src.size() + pad, kMinAlloc);
             HIP_OK(hipMalloc(&dst, cap));
             total += (int64_t)cap;
             if (!src.empty()) HIP_OK(hipMemcpy(dst, src.data(), src.size(), hipMemcpyHostToDevice));
             if (cap > src.size())
                 HIP_OK(hipMemset(static_cast<char *>(dst) + src.size(), 0, cap - src.size()));
         };
-        upload_bytes(p->d_val_on, hp.val_on);
+        upload_bytes(p->d_val_on, hp.val_on, kQuadPad * (size_t)hp.value_size);
         if (hp.three_way) {
             upload(p->d_rp_nd, hp.rowptr_nd, total);
             alloc(p->d_col_nd, hp.col_nd.size() * 4);
