@@ -530,6 +530,99 @@ __device__ __forceinline__ void local_product_runs(int32_t r0, int32_t r1, int32
     }
 }
 
+// Off-process row block with E consecutive positions per lane: each lane
+// loads columns, values and slots of its positions with one vector load
+// each.  The host lays such a block out by runs (sort_blocks with run E):
+// gather order fills the positions of [k0, k1) in the order of the load
+// instructions (vector u, component j, lane t), so every gather instruction
+// still reads, across its lanes, consecutive entries of gather order.
+// Positions of the runs outside [k0, k1) (a neighbouring block's entries, or
+// the arrays' zero padding) are loaded and discarded.  The products land in
+// LDS at their slots and each row adds them in stored order to its partial
+// sum, as in product_block.  A block whose aligned span is longer than CAP,
+// or that is empty, goes to product_block (the host keeps plain gather
+// order, or stored order, for such blocks).  E > 1.
+template <typename VT, typename XT, int CAP, bool DIRECT, bool NTW, int E>
+__device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const VT *__restrict__ val,
+                                                    const uint16_t *__restrict__ slot,
+                                                    const XT *__restrict__ xsrc,
+                                                    XT *__restrict__ w, XT *prod,
+                                                    const XT *__restrict__ vsrc) {
+    const int32_t k0a = k0 & -E;
+    if (k1 == k0 || k1 - k0a > CAP) {
+        product_block<VT, XT, int32_t, CAP, 0, true, DIRECT, NTW>(
+            r0, r1, k0, k1, make_int2(0, 0), rowptr, col, 0, val, slot, xsrc, w, prod, nullptr,
+            vsrc);
+        return;
+    }
+    static_assert(kBlock == kLanes, "the host's run layout assumes the kernels' lane count");
+    constexpr int Q = CAP / (E * kBlock);
+    constexpr int R = kMaxRows / kBlock;
+    const int32_t tid = (int32_t)threadIdx.x;
+    const int32_t klast = (k1 - 1) & -E;
+    int32_t c[E * Q], sl[E * Q];
+    XT a[E * Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+        const int32_t e = min(k0a + run_offset(E, u, tid, 0), klast);
+        const Vec<int32_t, E> cq = load_vec<E>(col, e);
+        const Vec<VT, E> aq = load_vec<E>(val, e);
+        const Vec<uint16_t, E> sq = load_vec<E>(slot, e);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            c[E * u + j] = cq[j];
+            a[E * u + j] = widen(aq[j]);
+            sl[E * u + j] = sq[j];
+        }
+    }
+    int32_t rb[R], re[R];
+    XT s[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int32_t r = min(r0 + i * kBlock + tid, r1 - 1);
+        rb[i] = rowptr[r];
+        re[i] = rowptr[r + 1];
+        s[i] = w[r];
+    }
+    // a discarded position reads element 0 of v (direct reads) or of the
+    // ghost buffer (not empty: this block has entries)
+    XT x[E * Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int32_t e = k0a + run_offset(E, u, tid, j);
+            int32_t &cc = c[E * u + j];
+            if (e < k0 || e >= k1) cc = DIRECT ? INT32_MIN : 0;
+            if (DIRECT)
+                x[E * u + j] = (cc < 0 ? vsrc : xsrc)[cc & 0x7fffffff];
+            else
+                x[E * u + j] = xsrc[cc];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int32_t e = k0a + run_offset(E, u, tid, j);
+            if (e >= k0 && e < k1) prod[sl[E * u + j]] = a[E * u + j] * x[E * u + j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int32_t r = r0 + i * kBlock + tid;
+        if (r < r1 && rb[i] != re[i]) {
+            XT acc = s[i];
+            for (int32_t q = rb[i] - k0; q < re[i] - k0; ++q) acc = acc + prod[q];
+            store_out<NTW>(acc, w + r);
+        }
+    }
+}
+
 // Everything one product needs, by launch.  A plain launch passes one view by
 // value; a batched launch reads views from a device table.
 template <typename VT, typename XT>
@@ -626,9 +719,9 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
 
 template <typename VT, typename XT, int CAP, bool DIRECT, bool NT>
 __device__ __forceinline__ void remote_part(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
-    product_block<VT, XT, int32_t, CAP, 0, true, DIRECT, NT>(
-        R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], make_int2(0, 0), R.rowptr,
-        R.col, 0, R.val, R.slot, R.ghost, R.w, prod, nullptr, R.v);
+    remote_product_runs<VT, XT, CAP, DIRECT, NT, remote_run((int)sizeof(VT), CAP)>(
+        R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], R.rowptr, R.col, R.val, R.slot,
+        R.ghost, R.w, prod, R.v);
 }
 
 template <typename VT, typename XT, int CAP>

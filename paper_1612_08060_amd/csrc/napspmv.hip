@@ -203,12 +203,13 @@ Ws ws_ptrs(const napspmv_plan_s *p, void *base) {
 // Device arrays are never empty and start zeroed: the product kernels read
 // clamped dummy entries (index 0 of an empty part) whose values they discard.
 constexpr size_t kMinAlloc = 256;
-// Entries of zero padding after the on-process columns and values: the
-// on-process product loads aligned runs of up to 8 entries, up to seven
-// entries past a block.
+// Entries of zero padding after the entry arrays of the products (columns,
+// values, slots): the products load aligned runs of up to 8 entries, up to
+// seven entries past a block.
 constexpr size_t kQuadPad = 8;
-// On-process row blocks hold at most block_nnz - 7 entries, so that the
-// aligned runs over a block of several rows stay within block_nnz.
+// Row blocks of several rows hold at most block_nnz - 7 (remote_nnz - 7)
+// entries, so that the aligned runs over a block stay within block_nnz
+// (remote_nnz).
 constexpr int kQuadSlack = 7;
 
 template <typename T>
@@ -276,7 +277,7 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
                           hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
     b += (int64_t)(hp.rowptr_nd.size() + hp.col_nd.size()) * 4 + (int64_t)hp.val_nd.size();
     b += (int64_t)(hp.col_off.size() + hp.col_nd.size()) * 2;   // gather-order slots
-    b += (int64_t)kQuadPad * (4 + hp.value_size);                 // on-process padding
+    b += (int64_t)kQuadPad * (4 + hp.value_size) * 3;             // padding for vector loads
     // band offsets (ghosts or send entries) and, for NAP, the scatter codes
     const int64_t gd = p->G + ghost_slack(p->G);
     b += hp.mode == NAPSPMV_NAP ? p->E * 2 + gd * 4 : gd * 2;
@@ -358,7 +359,8 @@ void build_partitions(napspmv_plan_s *p) {
         std::vector<int32_t> ob, op, fb, fp, it, ts, wn;
         napspmv::row_blocks(hp.rowptr_on.data() + r0, r1 - r0, cap - kQuadSlack, kMaxRowsPerBlock,
                             ob, op);
-        napspmv::row_blocks(hp.rowptr_off.data() + r0, r1 - r0, cur_rcap(p), kMaxRowsPerBlock, fb, fp);
+        napspmv::row_blocks(hp.rowptr_off.data() + r0, r1 - r0, cur_rcap(p) - kQuadSlack,
+                            kMaxRowsPerBlock, fb, fp);
         for (auto &x : ob) x += (int32_t)r0;
         for (auto &x : fb) x += (int32_t)r0;
         if (win > 0) napspmv::row_block_windows(ob, hp.on_lo, hp.on_hi, hp.n, win, wn);
@@ -407,7 +409,8 @@ void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &ma
     for (int64_t k = 0; k < (int64_t)col.size(); ++k) cm[k] = map[col[k]];
     std::vector<uint8_t> v2(val.size());
     std::vector<uint16_t> s2(col.size());
-    napspmv::sort_blocks(blkptr, cap, cm.data(), val.data(), vs, c2.data(), v2.data(), s2.data());
+    napspmv::sort_blocks(blkptr, cap, cm.data(), val.data(), vs, c2.data(), v2.data(), s2.data(),
+                         napspmv::remote_run(vs, cap));
     HIP_OK(hipMemcpy(d_col, c2.data(), c2.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_val, v2.data(), v2.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_slot, s2.data(), s2.size() * 2, hipMemcpyHostToDevice));
@@ -641,12 +644,12 @@ void refresh_schedules(napspmv_plan_s *p) {
         onbase[b] = (int32_t)hp.starts[(std::upper_bound(hp.starts.begin(), hp.starts.end(), onblk[b]) -
                                         hp.starts.begin()) - 1];
     if (win > 0) napspmv::row_block_windows(onblk, hp.on_lo, hp.on_hi, hp.n, win, wins);
-    napspmv::row_blocks_per_process(hp.rowptr_off.data(), hp.starts, rcap, kMaxRowsPerBlock, offblk,
-                                    offptr);
+    napspmv::row_blocks_per_process(hp.rowptr_off.data(), hp.starts, rcap - kQuadSlack,
+                                    kMaxRowsPerBlock, offblk, offptr);
     std::vector<int32_t> ndblk, ndptr;
     if (hp.three_way)
-        napspmv::row_blocks_per_process(hp.rowptr_nd.data(), hp.starts, rcap, kMaxRowsPerBlock,
-                                        ndblk, ndptr);
+        napspmv::row_blocks_per_process(hp.rowptr_nd.data(), hp.starts, rcap - kQuadSlack,
+                                        kMaxRowsPerBlock, ndblk, ndptr);
     if (cap != p->layout_cap || rcap != p->sorted_remote_nnz) {
         // the exchange layout follows the band width and the off-process
         // block cuts; the entry order of the off-process blocks follows the
@@ -738,9 +741,9 @@ void to_device(napspmv_plan_s *p) {
         };
         // entry arrays of the off-process blocks: filled in gather order by
         // refresh_schedules
-        alloc(p->d_col_off, hp.col_off.size() * 4);
-        alloc(p->d_val_off, hp.val_off.size());
-        alloc(p->d_slot_off, hp.col_off.size() * 2);
+        alloc(p->d_col_off, (hp.col_off.size() + kQuadPad) * 4);
+        alloc(p->d_val_off, hp.val_off.size() + kQuadPad * hp.value_size);
+        alloc(p->d_slot_off, (hp.col_off.size() + kQuadPad) * 2);
         auto upload_bytes = [&](void *&dst, const std::vector<uint8_t> &src, size_t pad) {
             const size_t cap = std::max(src.size() + pad, kMinAlloc);
             HIP_OK(hipMalloc(&dst, cap));
@@ -752,9 +755,9 @@ void to_device(napspmv_plan_s *p) {
         upload_bytes(p->d_val_on, hp.val_on, kQuadPad * (size_t)hp.value_size);
         if (hp.three_way) {
             upload(p->d_rp_nd, hp.rowptr_nd, total);
-            alloc(p->d_col_nd, hp.col_nd.size() * 4);
-            alloc(p->d_val_nd, hp.val_nd.size());
-            alloc(p->d_slot_nd, hp.col_nd.size() * 2);
+            alloc(p->d_col_nd, (hp.col_nd.size() + kQuadPad) * 4);
+            alloc(p->d_val_nd, hp.val_nd.size() + kQuadPad * hp.value_size);
+            alloc(p->d_slot_nd, (hp.col_nd.size() + kQuadPad) * 2);
             alloc(p->d_l2pos, (size_t)p->Gon * 4);
             upload(p->d_l2col, hp.l2_src, total);
             HIP_OK(hipStreamCreateWithFlags(&p->helper, hipStreamNonBlocking));

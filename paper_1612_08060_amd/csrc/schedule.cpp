@@ -48,11 +48,11 @@ void row_blocks_per_process(const int32_t *rowptr, const std::vector<int64_t> &s
 
 void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col,
                  const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
-                 uint16_t *slot_out) {
+                 uint16_t *slot_out, int run) {
     const int64_t nb = (int64_t)blkptr.size() - 1;
 #pragma omp parallel
     {
-        std::vector<int32_t> ord;
+        std::vector<int32_t> ord, at;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t b = 0; b < nb; ++b) {
             const int64_t k0 = blkptr[b], len = blkptr[b + 1] - k0;
@@ -63,11 +63,25 @@ void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col
                 std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
                     return col[k0 + x] < col[k0 + y];
                 });
+            // at[q]: the position, from k0, of the q-th entry of gather order
+            at.resize((size_t)len);
+            const int64_t a = k0 & -(int64_t)run, lo = k0 - a, hi = lo + len;
+            if (sorted && run > 1 && cap % (run * kLanes) == 0 && hi <= cap) {
+                int64_t q = 0;
+                for (int u = 0; u < cap / (run * kLanes); ++u)
+                    for (int j = 0; j < run; ++j)
+                        for (int t = 0; t < kLanes; ++t) {
+                            const int64_t d = run_offset(run, u, t, j);
+                            if (d >= lo && d < hi) at[(size_t)q++] = (int32_t)(d - lo);
+                        }
+            } else {
+                std::iota(at.begin(), at.end(), 0);
+            }
             for (int64_t q = 0; q < len; ++q) {
-                const int64_t from = k0 + ord[q];
-                col_out[k0 + q] = col[from];
-                std::memcpy(val_out + (k0 + q) * vs, val + from * vs, (size_t)vs);
-                slot_out[k0 + q] = (uint16_t)(sorted ? ord[q] : 0);
+                const int64_t from = k0 + ord[q], to = k0 + at[q];
+                col_out[to] = col[from];
+                std::memcpy(val_out + to * vs, val + from * vs, (size_t)vs);
+                slot_out[to] = (uint16_t)(sorted ? ord[q] : 0);
             }
         }
     }

@@ -20,14 +20,36 @@ void row_blocks_per_process(const int32_t *rowptr, const std::vector<int64_t> &s
                             int max_rows, std::vector<int32_t> &rowblk,
                             std::vector<int32_t> &blkptr);
 
+// Lanes of a workgroup of the apply kernels.
+constexpr int kLanes = 256;
+
+// Entries per lane that the off-process product loads with one vector load
+// of columns, values and slots: 2 for 8-byte values (16-byte value loads), 4
+// for smaller ones, and no more than cap / kLanes.
+constexpr int remote_run(int value_size, int cap) {
+    return (value_size == 8 ? 2 : 4) <= cap / kLanes ? (value_size == 8 ? 2 : 4) : cap / kLanes;
+}
+
+// Offset from a = k0 & -run of the entry that lane t loads as component j of
+// its u-th vector: the kernels' load order.
+constexpr int32_t run_offset(int run, int u, int t, int j) { return run * (u * kLanes + t) + j; }
+
 // Gather order of a block's entries: each block [blkptr[b], blkptr[b+1]) of
 // at most `cap` entries is reordered by ascending column (stable), so the
 // lanes of a wave read nearby ghost values; slot_out[k] = the stored
 // position, inside its block, of the entry now at k.  Longer blocks (a
 // single long row) keep stored order (slot 0).  `vs` = bytes of one value.
+// With run > 1 (cap a multiple of run * kLanes), a block whose aligned span
+// k1 - (k0 & -run) fits in `cap` is laid out for vector loads of `run`
+// entries per lane: the gather-ordered
+// entries fill the positions of [k0, k1) in the order the kernel's load
+// instructions visit them (vector u, component j, lane t; see run_offset),
+// so that each load instruction still reads, across its lanes, consecutive
+// entries of gather order.  Other blocks of at most `cap` entries keep plain
+// gather order.
 void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col,
                  const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
-                 uint16_t *slot_out);
+                 uint16_t *slot_out, int run = 1);
 
 // The window of v (first column, length <= `window`) each row block stages
 // in LDS, as interleaved pairs: the block's whole on-process column range if

@@ -51,6 +51,112 @@ static int check_merge(int64_t tail) {
     return 0;
 }
 
+// Gather-order sort of the blocks `bp` of a random column pattern: every
+// block of at most `cap` entries holds a permutation of its entries with
+// slots pointing at their stored positions; read in the order the kernel's
+// load instructions visit positions (plain order, or for a run layout the
+// order of run_offset restricted to the block), columns ascend; longer
+// blocks stay in stored order.
+static int check_sort(std::mt19937 &rng, const std::vector<int32_t> &rowptr,
+                      const std::vector<int32_t> &bp, int cap, int run, int trial) {
+    const int nnz = rowptr.back();
+    std::vector<int32_t> col(nnz), col_out(nnz);
+    std::vector<double> val(nnz), val_out(nnz);
+    std::vector<uint16_t> slot(nnz);
+    for (int k = 0; k < nnz; ++k) { col[k] = (int32_t)(rng() % 1000); val[k] = k + 0.5; }
+    napspmv::sort_blocks(bp, cap, col.data(), reinterpret_cast<const uint8_t *>(val.data()), 8,
+                         col_out.data(), reinterpret_cast<uint8_t *>(val_out.data()), slot.data(),
+                         run);
+    int64_t tiled = 0;
+    for (size_t b = 0; b + 1 < bp.size(); ++b) {
+        const int32_t k0 = bp[b], len = bp[b + 1] - k0;
+        if (len > cap) {
+            for (int32_t q = 0; q < len; ++q)
+                if (slot[k0 + q] != 0 || col_out[k0 + q] != col[k0 + q] ||
+                    val_out[k0 + q] != val[k0 + q])
+                    return fail("long block moved", trial, q);
+            continue;
+        }
+        // positions in load order
+        std::vector<int32_t> order;
+        const int32_t a = k0 & -run;
+        if (run > 1 && k0 - a + len <= cap) {
+            ++tiled;
+            for (int u = 0; u < cap / (run * napspmv::kLanes); ++u)
+                for (int j = 0; j < run; ++j)
+                    for (int t = 0; t < napspmv::kLanes; ++t) {
+                        const int32_t k = a + napspmv::run_offset(run, u, t, j);
+                        if (k >= k0 && k < k0 + len) order.push_back(k);
+                    }
+        } else {
+            for (int32_t q = 0; q < len; ++q) order.push_back(k0 + q);
+        }
+        if ((int32_t)order.size() != len) return fail("load order size", trial, (long long)b);
+        std::vector<char> hit(len, 0);
+        for (int32_t q = 0; q < len; ++q) {
+            const int32_t k = order[q];
+            if (q && col_out[k] < col_out[order[q - 1]]) return fail("not sorted", trial, q);
+            const int32_t from = slot[k];
+            if (from >= len || hit[from]++) return fail("slot permutation", trial, q);
+            if (col_out[k] != col[k0 + from] || val_out[k] != val[k0 + from])
+                return fail("slot target", trial, q);
+        }
+    }
+    if (run > 1 && tiled == 0) return fail("no block took the run layout", trial, run);
+    return 0;
+}
+
+// The loads of the run kernels (local_product_runs, remote_product_runs):
+// lane t's u-th vector starts at min(a + run_offset(run, u, t, 0), last
+// aligned start) with a = k0 & -run.  Over blocks cut at cap - 7 entries,
+// every loaded position lies in [0, nnz + 8) (the arrays' padding), the
+// positions inside [k0, k1) are visited exactly once, and each lands at an
+// LDS index below cap (its offset from a).
+static int check_run_loads() {
+    std::mt19937 rng(5);
+    for (int trial = 0; trial < 40; ++trial) {
+        const int n_p = 1 + trial % 5, n = n_p * (20 + trial * 7 % 60);
+        std::vector<int32_t> rowptr(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            const int len = (rng() % 23 == 0) ? 1500 + rng() % 3000 : rng() % 40;
+            rowptr[i + 1] = rowptr[i] + len;
+        }
+        const int nnz = rowptr[n];
+        std::vector<int64_t> starts(n_p + 1);
+        for (int t = 0; t <= n_p; ++t) starts[t] = (int64_t)n * t / n_p;
+        for (int cap : {1024, 2048, 4096, 8192}) {
+            std::vector<int32_t> rb, bp;
+            napspmv::row_blocks_per_process(rowptr.data(), starts, cap - 7, 1024, rb, bp);
+            for (int run : {2, 4, 8}) {
+                if (cap < run * napspmv::kLanes) continue;
+                for (size_t b = 0; b + 1 < bp.size(); ++b) {
+                    const int32_t k0 = bp[b], k1 = bp[b + 1], a = k0 & -run;
+                    const bool multi = rb[b + 1] - rb[b] > 1;
+                    if (multi && k1 - a > cap) return fail("aligned span over cap", trial, (long long)b);
+                    if (k1 == k0 || k1 - a > cap) continue;     // the one-entry-per-lane path
+                    const int32_t last = (k1 - 1) & -run;
+                    std::vector<char> seen(k1 - k0, 0);
+                    for (int u = 0; u < cap / (run * napspmv::kLanes); ++u)
+                        for (int t = 0; t < napspmv::kLanes; ++t) {
+                            const int32_t e = std::min(a + napspmv::run_offset(run, u, t, 0), last);
+                            if (e < 0 || e + run > nnz + 8) return fail("load outside the arrays", trial, e);
+                            for (int j = 0; j < run; ++j) {
+                                const int32_t k = a + napspmv::run_offset(run, u, t, j);
+                                if (k < k0 || k >= k1) continue;
+                                if (e != k - j) return fail("used entry from a clamped load", trial, k);
+                                if (seen[k - k0]++) return fail("entry loaded twice", trial, k);
+                                if (k - a >= cap) return fail("LDS index over cap", trial, k);
+                            }
+                        }
+                    for (char c : seen)
+                        if (!c) return fail("entry not loaded", trial, (long long)b);
+                }
+            }
+        }
+    }
+    return 0;
+}
+
 static int check_blocks_and_sort() {
     std::mt19937 rng(7);
     for (int trial = 0; trial < 60; ++trial) {
@@ -78,31 +184,16 @@ static int check_blocks_and_sort() {
                 if (!single && (rowptr[r1] - rowptr[r0] > cap || r1 - r0 > max_rows))
                     return fail("block too large", trial, (long long)b);
             }
-            // sort inside blocks by column; slots give the stored positions
-            const int nnz = rowptr[n];
-            std::vector<int32_t> col(nnz), col_out(nnz);
-            std::vector<double> val(nnz), val_out(nnz);
-            std::vector<uint16_t> slot(nnz);
-            for (int k = 0; k < nnz; ++k) { col[k] = (int32_t)(rng() % 1000); val[k] = k + 0.5; }
-            napspmv::sort_blocks(bp, cap, col.data(), reinterpret_cast<const uint8_t *>(val.data()),
-                                 8, col_out.data(), reinterpret_cast<uint8_t *>(val_out.data()),
-                                 slot.data());
-            for (size_t b = 0; b + 1 < bp.size(); ++b) {
-                const int32_t k0 = bp[b], len = bp[b + 1] - k0;
-                std::vector<char> hit(len, 0);
-                for (int32_t q = 0; q < len; ++q) {
-                    if (len <= cap) {
-                        if (q && col_out[k0 + q] < col_out[k0 + q - 1]) return fail("not sorted", trial, q);
-                        const int32_t from = slot[k0 + q];
-                        if (from >= len || hit[from]++) return fail("slot permutation", trial, q);
-                        if (col_out[k0 + q] != col[k0 + from] || val_out[k0 + q] != val[k0 + from])
-                            return fail("slot target", trial, q);
-                    } else if (slot[k0 + q] != 0 || col_out[k0 + q] != col[k0 + q] ||
-                               val_out[k0 + q] != val[k0 + q]) {
-                        return fail("long block moved", trial, q);
-                    }
-                }
-            }
+            if (check_sort(rng, rowptr, bp, cap, 1, trial)) return 1;
+        }
+        // run layouts: blocks of at most cap - 7 entries, as the library
+        // cuts them, so that a block of several rows has an aligned span
+        // of at most cap
+        for (int cap : {1024, 2048}) {
+            std::vector<int32_t> rb, bp;
+            napspmv::row_blocks_per_process(rowptr.data(), starts, cap - 7, 8, rb, bp);
+            for (int run : {2, 4})
+                if (check_sort(rng, rowptr, bp, cap, run, trial)) return 1;
         }
     }
     return 0;
@@ -170,7 +261,7 @@ static int check_saddle_loads(int64_t &empty_blocks) {
 int main() {
     int64_t empty = 0;
     if (check_merge(napspmv::kItemTail) || check_merge(napspmv::kPackScatterTail) ||
-        check_blocks_and_sort() || check_saddle_loads(empty))
+        check_blocks_and_sort() || check_run_loads() || check_saddle_loads(empty))
         return 1;
     if (empty == 0) return fail("saddle matrices produced no empty block", 0, 0);
     std::printf("ok\n");

@@ -3,11 +3,15 @@ schedule source with the host compiler: the first launch's task order (a
 permutation of items and row blocks, proportional per XCD range, no item in
 a range's tail), per-process row blocks (cover, never span two processes,
 respect the entry and row limits) and the gather-order sort of off-process
-blocks (sorted, slots a permutation pointing at each entry's stored
-position, long single-row blocks left in stored order), and, on saddle-point
-matrices whose zero block starts at a process boundary, that every load a
-non-empty on-process block issues (the kernels' own clamp) stays among the
-block's entries, whose columns the block's process owns."""
+blocks (sorted in the order the kernel's loads visit positions, plain or
+laid out by runs of 2 and 4 entries per lane; slots a permutation pointing
+at each entry's stored position; long single-row blocks left in stored
+order), the vector loads of the run kernels (inside the padded arrays, every
+entry of a block used exactly once, LDS indices below the block capacity,
+aligned spans within the capacity for blocks cut at capacity - 7), and, on
+saddle-point matrices whose zero block starts at a process boundary, that
+every load a non-empty on-process block issues (the kernels' own clamp)
+stays among the block's entries, whose columns the block's process owns."""
 import os
 import shutil
 import subprocess
