@@ -460,10 +460,13 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
  * flight.
  *   BLOCK_NNZ     entries per row block of the on-process product (a block
  *                 of several rows holds at most BLOCK_NNZ - 7, so that its
- *                 aligned vector loads stay within BLOCK_NNZ), and columns
- *                 of v per band of the exchange buffers: 1024, 2048, 4096,
- *                 8192 (automatic: 4096)
- *   REMOTE_NNZ    entries per row block of the off-process product: 1024,
+ *                 aligned vector loads stay within BLOCK_NNZ); the bands of
+ *                 the exchange buffers hold BLOCK_NNZ * 8 bytes of v
+ *                 (BLOCK_NNZ columns of a float64 vector, twice as many of
+ *                 a float32 one): 1024, 2048, 4096, 8192 (automatic: 4096
+ *                 for float64 values, 2048 for float32 and bfloat16)
+ *   REMOTE_NNZ    entries per row block of the off-process product (at
+ *                 most REMOTE_NNZ - 7 for a block of several rows): 1024,
  *                 2048, 4096, 8192 (automatic: 8192 when the plan has at
  *                 least 8192 off-process entries per process, else 4096)
  *   GATHER_ITEM   most entries of one exchange work item (a slice of one

@@ -690,18 +690,27 @@ __device__ __forceinline__ void local_block(const LocalView<VT, XT> &L, int32_t 
                                                       prod, wbuf);
 }
 
+// LDS elements of the first launch: a band of v (exchange items), or a row
+// block's products followed by its window of v (on-process blocks).
+template <typename XT, int CAP, int W>
+constexpr int local_lds() {
+    constexpr int band = band_columns(CAP, (int)sizeof(XT));
+    return band > CAP + W ? band : CAP + W;
+}
+
 template <typename VT, typename XT, int CAP, int W>
-__device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t, XT *prod,
-                                           XT *wbuf) {
+__device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t, XT *lds) {
+    constexpr int BAND = band_columns(CAP, (int)sizeof(XT));
+    XT *prod = lds, *wbuf = lds + CAP;
     const int32_t task = L.tasks[t];
     if (task < 0) {
         const int4 it = L.items[~task];
         if (it.w == 1) {
-            pack_scatter_item<XT, CAP>(it, L.n, L.off, L.v, L.xdst, L.gband, L.s1band, L.s1src,
-                                       L.code, L.recv, L.ghost, prod, L.nt != 0);
+            pack_scatter_item<XT, BAND>(it, L.n, L.off, L.v, L.xdst, L.gband, L.s1band, L.s1src,
+                                       L.code, L.recv, L.ghost, lds, L.nt != 0);
             return;
         }
-        exchange_item<XT, CAP>(it, L.n, L.off, L.idx, L.dpos, L.v, L.xdst, prod, L.nt != 0);
+        exchange_item<XT, BAND>(it, L.n, L.off, L.idx, L.dpos, L.v, L.xdst, lds, L.nt != 0);
         return;
     }
     if (L.col16) {
@@ -752,9 +761,8 @@ __device__ __forceinline__ int32_t find_range(const int32_t *__restrict__ prefix
 // task list, so every CU runs both at once.
 template <typename VT, typename XT, int CAP, int W>
 __global__ __launch_bounds__(kBlock) void k_local(LocalView<VT, XT> L) {
-    __shared__ __align__(32) XT prod[CAP];
-    __shared__ XT wbuf[W > 0 ? W : 1];
-    local_task<VT, XT, CAP, W>(L, (int32_t)xcd_block(blockIdx.x, gridDim.x), prod, wbuf);
+    __shared__ __align__(32) XT lds[local_lds<XT, CAP, W>()];
+    local_task<VT, XT, CAP, W>(L, (int32_t)xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 // Second launch: the off-process product, added into the partial w.
@@ -770,11 +778,10 @@ template <typename VT, typename XT, int CAP, int W>
 __global__ __launch_bounds__(kBlock) void k_local_batch(const LocalView<VT, XT> *__restrict__ views,
                                                         const int32_t *__restrict__ prefix,
                                                         int32_t count) {
-    __shared__ __align__(32) XT prod[CAP];
-    __shared__ XT wbuf[W > 0 ? W : 1];
+    __shared__ __align__(32) XT lds[local_lds<XT, CAP, W>()];
     const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
     const int32_t i = find_range(prefix, count, b);
-    local_task<VT, XT, CAP, W>(views[i], b - prefix[i], prod, wbuf);
+    local_task<VT, XT, CAP, W>(views[i], b - prefix[i], lds);
 }
 
 template <typename VT, typename XT, int CAP>
@@ -790,8 +797,9 @@ __global__ __launch_bounds__(kBlock) void k_remote_batch(const RemoteView<VT, XT
 // NAP scatter: one band item per block.
 template <typename XT, int CAP>
 __global__ __launch_bounds__(kBlock) void k_scatter(ScatterView<XT> S) {
-    __shared__ XT lds[CAP];
-    scatter_item<XT, CAP>(S.items[xcd_block(blockIdx.x, gridDim.x)], S.n, S.which, S.code, S.v,
+    constexpr int BAND = band_columns(CAP, (int)sizeof(XT));
+    __shared__ XT lds[BAND];
+    scatter_item<XT, BAND>(S.items[xcd_block(blockIdx.x, gridDim.x)], S.n, S.which, S.code, S.v,
                           S.recv, S.ghost, lds);
 }
 
@@ -801,11 +809,12 @@ template <typename XT, int CAP>
 __global__ __launch_bounds__(kBlock) void k_scatter_batch(const ScatterView<XT> *__restrict__ views,
                                                           const int32_t *__restrict__ prefix,
                                                           int32_t count) {
-    __shared__ XT lds[CAP];
+    constexpr int BAND = band_columns(CAP, (int)sizeof(XT));
+    __shared__ XT lds[BAND];
     const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
     const int32_t i = find_range(prefix, count, b);
     const ScatterView<XT> &S = views[i];
-    scatter_item<XT, CAP>(S.items[b - prefix[i]], S.n, S.which, S.code, S.v, S.recv, S.ghost, lds);
+    scatter_item<XT, BAND>(S.items[b - prefix[i]], S.n, S.which, S.code, S.v, S.recv, S.ghost, lds);
 }
 
 }  // namespace napspmv

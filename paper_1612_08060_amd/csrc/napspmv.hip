@@ -530,8 +530,9 @@ void pack_segments(napspmv_plan_s *p, const int32_t *first_blk, int seg) {
 }
 
 // Band layout of the exchange buffers for bands of `cap` columns (the LDS
-// tile of the exchange kernels): ghost positions, band offsets, NAP send
-// positions and scatter codes; uploaded over the plan's device arrays.
+// tile of the exchange kernels, band_columns of the block size): ghost
+// positions, band offsets, NAP send positions and scatter codes; uploaded
+// over the plan's device arrays.
 void build_layout(napspmv_plan_s *p, int cap, const std::vector<int32_t> &offptr,
                   const std::vector<int32_t> &ndptr) {
     const HostPlan &hp = p->hp;
@@ -650,12 +651,13 @@ void refresh_schedules(napspmv_plan_s *p) {
     if (hp.three_way)
         napspmv::row_blocks_per_process(hp.rowptr_nd.data(), hp.starts, rcap - kQuadSlack,
                                         kMaxRowsPerBlock, ndblk, ndptr);
-    if (cap != p->layout_cap || rcap != p->sorted_remote_nnz) {
+    const int band = napspmv::band_columns(cap, (int)vec_bytes(hp.dtype));
+    if (band != p->layout_cap || rcap != p->sorted_remote_nnz) {
         // the exchange layout follows the band width and the off-process
         // block cuts; the entry order of the off-process blocks follows the
         // layout and the block cuts
         HIP_OK(hipDeviceSynchronize());
-        build_layout(p, cap, offptr, ndptr);
+        build_layout(p, band, offptr, ndptr);
         sort_upload(hp.col_off, hp.direct ? p->dmap : p->gpos, hp.val_off, (int)hp.value_size,
                     offptr, rcap, p->d_col_off, p->d_val_off, p->d_slot_off);
         if (hp.three_way)
@@ -1285,6 +1287,11 @@ int plan_create(const int64_t *rowptr, const int32_t *col, const void *val, int 
         // process's blocks share more ghost lines, but a process with fewer
         // off-process entries than it holds would leave half of its LDS idle
         p->auto_remote_nnz = p->hp.nnz_off >= (int64_t)8192 * p->hp.n_p ? 8192 : 4096;
+        // automatic on-process block size: 2048 entries for float32 and
+        // bfloat16 values (their bands still hold 16 KB of v) -- shorter
+        // blocks hold fewer registers and keep more of them in flight per
+        // CU; float64 blocks of 4096 entries
+        p->auto_block_nnz = p->hp.dtype == NAPSPMV_F64 ? 4096 : 2048;
         if (!(flags & NAPSPMV_HOST_ONLY)) {
             to_device(p);
             napspmv::release_device_arrays(p->hp);

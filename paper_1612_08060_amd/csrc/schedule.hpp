@@ -23,6 +23,15 @@ void row_blocks_per_process(const int32_t *rowptr, const std::vector<int64_t> &s
 // Lanes of a workgroup of the apply kernels.
 constexpr int kLanes = 256;
 
+// Columns of v per band of the exchange buffers for row blocks of `cap`
+// entries and `vec_bytes`-byte vector elements: cap * 8 bytes of v, the
+// slice an exchange item stages in LDS (cap columns of float64, 2 cap of
+// float32).  The first launch's LDS holds either such a slice or a row
+// block's products and window, so float32 bands take no more LDS than
+// float64 ones, and longer bands give each off-process block longer runs
+// of ghosts side by side.
+constexpr int band_columns(int cap, int vec_bytes) { return cap * 8 / vec_bytes; }
+
 // Entries per lane that the off-process product loads with one vector load
 // of columns, values and slots: 2 for 8-byte values (16-byte value loads), 4
 // for smaller ones, and no more than cap / kLanes.

@@ -11,7 +11,7 @@ import pytest
 import paper_1612_08060_amd as lib
 from oracle import plan_ref, plan_vec
 from tests.helpers import arrays_to_triples, example_2_1, triples
-from workloads import CSR, bf16_bits, config, kkt_like, random_pattern
+from workloads import CSR, bf16_bits, config, kkt_like, random_pattern, to_f32
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                       "include", "napspmv.h")
@@ -206,6 +206,10 @@ def test_tuning_parameters():
             p.set_param(name, bad)
     p.set_param("block_nnz", -1)
     assert p.get_param("block_nnz") == 4096
+    # reduced precision: shorter on-process blocks by default
+    for dt, conv in (("f32", to_f32), ("bf16", bf16_bits)):
+        with lib.Plan(a.rowptr, a.col, conv(a.val), a.n, 4, 2, dtype=dt, host_only=True) as q:
+            assert q.get_param("block_nnz") == 2048 and q.get_param("window") == 1024
 
 
 def test_duplicates_and_stored_zeros_are_structure():
