@@ -542,10 +542,10 @@ __device__ __forceinline__ void local_product_runs(int32_t r0, int32_t r1, int32
 // sum, as in product_block.  A block whose aligned span is longer than CAP,
 // or that is empty, goes to product_block (the host keeps plain gather
 // order, or stored order, for such blocks).  E > 1.
-template <typename VT, typename XT, int CAP, bool DIRECT, bool NTW, int E>
+template <typename VT, typename XT, typename CT, int CAP, bool DIRECT, bool NTW, int E>
 __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                                     const int32_t *__restrict__ rowptr,
-                                                    const int32_t *__restrict__ col,
+                                                    const CT *__restrict__ col, int32_t cbase,
                                                     const VT *__restrict__ val,
                                                     const uint16_t *__restrict__ slot,
                                                     const XT *__restrict__ xsrc,
@@ -553,8 +553,8 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
                                                     const XT *__restrict__ vsrc) {
     const int32_t k0a = k0 & -E;
     if (k1 == k0 || k1 - k0a > CAP) {
-        product_block<VT, XT, int32_t, CAP, 0, true, DIRECT, NTW>(
-            r0, r1, k0, k1, make_int2(0, 0), rowptr, col, 0, val, slot, xsrc, w, prod, nullptr,
+        product_block<VT, XT, CT, CAP, 0, true, DIRECT, NTW>(
+            r0, r1, k0, k1, make_int2(0, 0), rowptr, col, cbase, val, slot, xsrc, w, prod, nullptr,
             vsrc);
         return;
     }
@@ -568,12 +568,12 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
 #pragma unroll
     for (int u = 0; u < Q; ++u) {
         const int32_t e = min(k0a + run_offset(E, u, tid, 0), klast);
-        const Vec<int32_t, E> cq = load_vec<E>(col, e);
+        const Vec<CT, E> cq = load_vec<E>(col, e);
         const Vec<VT, E> aq = load_vec<E>(val, e);
         const Vec<uint16_t, E> sq = load_vec<E>(slot, e);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-            c[E * u + j] = cq[j];
+            c[E * u + j] = cbase + (int32_t)cq[j];
             a[E * u + j] = widen(aq[j]);
             sl[E * u + j] = sq[j];
         }
@@ -656,6 +656,10 @@ template <typename VT, typename XT>
 struct RemoteView {
     int32_t n_blocks;
     const int32_t *rowblk, *blkptr, *rowptr, *col;
+    // blocks whose ghost positions span less than 65536: cbase[b] >= 0 and
+    // col16 holds the positions as offsets from it (null: no such block)
+    const int32_t *cbase;
+    const uint16_t *col16;
     const VT *val;
     const uint16_t *slot;      // stored position of each entry inside its block
     const XT *ghost;           // ghost buffer, or the received buffer (direct reads)
@@ -726,21 +730,28 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
     }
 }
 
-template <typename VT, typename XT, int CAP, bool DIRECT, bool NT>
-__device__ __forceinline__ void remote_part(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
-    remote_product_runs<VT, XT, CAP, DIRECT, NT, remote_run((int)sizeof(VT), CAP)>(
-        R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], R.rowptr, R.col, R.val, R.slot,
-        R.ghost, R.w, prod, R.v);
+template <typename VT, typename XT, typename CT, int CAP, bool DIRECT, bool NT>
+__device__ __forceinline__ void remote_part(const RemoteView<VT, XT> &R, int32_t b, const CT *col,
+                                            int32_t cbase, XT *prod) {
+    remote_product_runs<VT, XT, CT, CAP, DIRECT, NT, remote_run((int)sizeof(VT), CAP)>(
+        R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], R.rowptr, col, cbase, R.val,
+        R.slot, R.ghost, R.w, prod, R.v);
 }
 
 template <typename VT, typename XT, int CAP>
 __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_t b, XT *prod) {
     if (R.v) {
-        if (R.nt) remote_part<VT, XT, CAP, true, true>(R, b, prod);
-        else remote_part<VT, XT, CAP, true, false>(R, b, prod);
+        if (R.nt) remote_part<VT, XT, int32_t, CAP, true, true>(R, b, R.col, 0, prod);
+        else remote_part<VT, XT, int32_t, CAP, true, false>(R, b, R.col, 0, prod);
+        return;
+    }
+    const int32_t base = R.cbase ? R.cbase[b] : -1;
+    if (base >= 0) {
+        if (R.nt) remote_part<VT, XT, uint16_t, CAP, false, true>(R, b, R.col16, base, prod);
+        else remote_part<VT, XT, uint16_t, CAP, false, false>(R, b, R.col16, base, prod);
     } else {
-        if (R.nt) remote_part<VT, XT, CAP, false, true>(R, b, prod);
-        else remote_part<VT, XT, CAP, false, false>(R, b, prod);
+        if (R.nt) remote_part<VT, XT, int32_t, CAP, false, true>(R, b, R.col, 0, prod);
+        else remote_part<VT, XT, int32_t, CAP, false, false>(R, b, R.col, 0, prod);
     }
 }
 

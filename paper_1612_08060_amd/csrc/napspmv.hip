@@ -94,6 +94,13 @@ struct napspmv_plan_s {
     void *d_val_nd = nullptr;
     // gather order of the off-process (and on_node) blocks; see sort_blocks
     uint16_t *d_slot_off = nullptr, *d_slot_nd = nullptr;
+    // off-process blocks whose ghost positions span less than 65536: their
+    // positions as 16-bit offsets (d_col16_off) from the block's first one
+    // (d_offbase[b]; -1 for a block that keeps 32-bit positions); null when
+    // no block qualifies or the plan reads ghosts directly
+    uint16_t *d_col16_off = nullptr;
+    int32_t *d_offbase = nullptr;
+    int64_t offbase_bytes = 0;
     hipStream_t helper = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void *d_ws = nullptr;            // the plan's own workspace (ghost, send, receive)
@@ -246,8 +253,11 @@ void free_device(napspmv_plan_s *p) {
                     p->d_val_off, p->d_off, p->d_code, p->d_pgcol, p->d_pgpos, p->d_ws,
                     p->d_l2pos, p->d_l2col,
                     p->d_rp_nd, p->d_col_nd, p->d_val_nd, p->d_slot_off, p->d_slot_nd,
-                    p->d_col16_on, p->d_s1src};
+                    p->d_col16_on, p->d_s1src, p->d_col16_off, p->d_offbase};
     for (void *q : ptrs) free_ptr(q);
+    p->d_col16_off = nullptr;
+    p->d_offbase = nullptr;
+    p->offbase_bytes = 0;
     p->d_rp_nd = p->d_col_nd = nullptr;
     p->d_val_nd = nullptr;
     p->d_slot_off = p->d_slot_nd = nullptr;
@@ -277,6 +287,7 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
                           hp.col_off.size()) * 4 + (int64_t)(hp.val_on.size() + hp.val_off.size());
     b += (int64_t)(hp.rowptr_nd.size() + hp.col_nd.size()) * 4 + (int64_t)hp.val_nd.size();
     b += (int64_t)(hp.col_off.size() + hp.col_nd.size()) * 2;   // gather-order slots
+    if (!hp.direct) b += (int64_t)hp.col_off.size() * 2;         // 16-bit positions (narrow blocks)
     b += (int64_t)kQuadPad * (4 + hp.value_size) * 3;             // padding for vector loads
     // band offsets (ghosts or send entries) and, for NAP, the scatter codes
     const int64_t gd = p->G + ghost_slack(p->G);
@@ -400,9 +411,19 @@ void build_partitions(napspmv_plan_s *p) {
 // Map the ghost positions of a block list to device positions (`map`),
 // reorder the entries of every block into gather order (sort_blocks) and
 // copy them, with their slots, over the device arrays (already allocated).
+// With `p` (the off-process part of a plan that fills a ghost buffer), also
+// lays out the blocks whose positions span less than 65536 with 16-bit
+// offsets from their first position (stencil-like halos: two bytes instead
+// of four per entry) in p->d_col16_off and p->d_offbase.
 void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &map,
                  const std::vector<uint8_t> &val, int vs, const std::vector<int32_t> &blkptr, int cap,
-                 int32_t *d_col, void *d_val, uint16_t *d_slot) {
+                 int32_t *d_col, void *d_val, uint16_t *d_slot, napspmv_plan_s *p = nullptr) {
+    if (p) {
+        free_ptr(p->d_offbase);
+        p->d_offbase = nullptr;
+        charge(p, -p->offbase_bytes);
+        p->offbase_bytes = 0;
+    }
     if (col.empty()) return;
     std::vector<int32_t> cm(col.size()), c2(col.size());
 #pragma omp parallel for schedule(static)
@@ -414,6 +435,38 @@ void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &ma
     HIP_OK(hipMemcpy(d_col, c2.data(), c2.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_val, v2.data(), v2.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_slot, s2.data(), s2.size() * 2, hipMemcpyHostToDevice));
+    if (!p) return;
+    const int64_t nb = (int64_t)blkptr.size() - 1;
+    std::vector<int32_t> base(nb, -1);
+    std::vector<uint16_t> c16(col.size(), 0);
+    int64_t narrow = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : narrow)
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t k0 = blkptr[b], k1 = blkptr[b + 1];
+        if (k1 == k0) continue;
+        int32_t lo = INT32_MAX, hi = -1;
+        for (int64_t k = k0; k < k1; ++k) {
+            lo = std::min(lo, c2[k]);
+            hi = std::max(hi, c2[k]);
+        }
+        if (hi - lo > 65535) continue;
+        base[b] = lo;
+        ++narrow;
+        for (int64_t k = k0; k < k1; ++k) c16[k] = (uint16_t)(c2[k] - lo);
+    }
+    if (narrow == 0) return;
+    int64_t total = 0;
+    if (!p->d_col16_off) {
+        // kept across re-sorts, like the other entry arrays
+        const size_t bytes = (col.size() + kQuadPad) * 2;
+        HIP_OK(hipMalloc(reinterpret_cast<void **>(&p->d_col16_off), bytes));
+        HIP_OK(hipMemset(p->d_col16_off, 0, bytes));
+        charge(p, (int64_t)bytes);
+    }
+    HIP_OK(hipMemcpy(p->d_col16_off, c16.data(), c16.size() * 2, hipMemcpyHostToDevice));
+    upload(p->d_offbase, base, total);
+    p->offbase_bytes = total;
+    charge(p, total);
 }
 
 // Stable sort of entries by the band of their column and then by `group`
@@ -659,7 +712,8 @@ void refresh_schedules(napspmv_plan_s *p) {
         HIP_OK(hipDeviceSynchronize());
         build_layout(p, band, offptr, ndptr);
         sort_upload(hp.col_off, hp.direct ? p->dmap : p->gpos, hp.val_off, (int)hp.value_size,
-                    offptr, rcap, p->d_col_off, p->d_val_off, p->d_slot_off);
+                    offptr, rcap, p->d_col_off, p->d_val_off, p->d_slot_off,
+                    hp.direct ? nullptr : p);
         if (hp.three_way)
             sort_upload(hp.col_nd, p->gpos, hp.val_nd, (int)hp.value_size, ndptr, rcap,
                         p->d_col_nd, p->d_val_nd, p->d_slot_nd);
@@ -850,6 +904,8 @@ napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules
     R.blkptr = (on_node ? s.ndptr : s.offptr) + blk0;
     R.rowptr = on_node ? p->d_rp_nd : p->d_rp_off;
     R.col = on_node ? p->d_col_nd : p->d_col_off;
+    R.cbase = on_node || !p->d_offbase ? nullptr : p->d_offbase + blk0;
+    R.col16 = p->d_col16_off;
     R.val = static_cast<const VT *>(on_node ? p->d_val_nd : p->d_val_off);
     R.slot = on_node ? p->d_slot_nd : p->d_slot_off;
     R.ghost = static_cast<const XT *>(p->hp.direct ? ws.recv : ws.ghost);
