@@ -33,10 +33,10 @@ constexpr int kLanes = 256;
 constexpr int band_columns(int cap, int vec_bytes) { return cap * 8 / vec_bytes; }
 
 // Entries per lane that the off-process product loads with one vector load
-// of columns, values and slots: 2 for 8-byte values (16-byte value loads), 4
-// for smaller ones, and no more than cap / kLanes.
+// of columns, values and slots: 16 bytes of values (2 float64, 4 float32, 8
+// bfloat16 entries), and no more than cap / kLanes.
 constexpr int remote_run(int value_size, int cap) {
-    return (value_size == 8 ? 2 : 4) <= cap / kLanes ? (value_size == 8 ? 2 : 4) : cap / kLanes;
+    return 16 / value_size <= cap / kLanes ? 16 / value_size : cap / kLanes;
 }
 
 // Offset from a = k0 & -run of the entry that lane t loads as component j of

@@ -192,8 +192,9 @@ static int check_blocks_and_sort() {
         for (int cap : {1024, 2048}) {
             std::vector<int32_t> rb, bp;
             napspmv::row_blocks_per_process(rowptr.data(), starts, cap - 7, 8, rb, bp);
-            for (int run : {2, 4})
-                if (check_sort(rng, rowptr, bp, cap, run, trial)) return 1;
+            for (int run : {2, 4, 8})
+                if (cap % (run * napspmv::kLanes) == 0 && check_sort(rng, rowptr, bp, cap, run, trial))
+                    return 1;
         }
     }
     return 0;

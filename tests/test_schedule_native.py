@@ -4,7 +4,7 @@ permutation of items and row blocks, proportional per XCD range, no item in
 a range's tail), per-process row blocks (cover, never span two processes,
 respect the entry and row limits) and the gather-order sort of off-process
 blocks (sorted in the order the kernel's loads visit positions, plain or
-laid out by runs of 2 and 4 entries per lane; slots a permutation pointing
+laid out by runs of 2, 4 and 8 entries per lane; slots a permutation pointing
 at each entry's stored position; long single-row blocks left in stored
 order), the vector loads of the run kernels (inside the padded arrays, every
 entry of a block used exactly once, LDS indices below the block capacity,
