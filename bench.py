@@ -7,9 +7,10 @@ workload (KKT-like random matrix, N = 2^22, n_p = 2048, ppn = 16, float64),
 inputs resident in HBM.  Prints ONE JSON line on stdout; progress goes to
 stderr.
 
-Timing protocol: HIP events around every apply on the stream it runs on
-(and around each of its two launches), after the warm-up applies; the
-median, 10th and 90th percentile over the timed applies.  "Cold" applies
+Timing protocol: HIP events around every apply on the stream it runs on,
+after the warm-up applies; the median, 10th and 90th percentile over the
+timed applies.  Per-launch times come from a second pass of as many
+applies with an event between the two launches as well.  "Cold" applies
 follow a 1 GiB scratch write that evicts the L2 caches and the 256 MB
 Infinity Cache, then a 1 GiB read of a second buffer, so that the caches
 hold neither data of the apply nor dirty lines of the flush (whose
@@ -148,15 +149,29 @@ class Flush:
 
 
 def time_applies(torch, plan, v, w, nap, steps, warmup, flush=None):
-    """Per-apply and per-launch HIP event times (ms) of `steps` applies after
-    `warmup` untimed ones; with `flush`, each apply follows a cache flush
-    (outside its events).  Returns (apply, local, remote, wall ms per apply)."""
+    """HIP event times (ms) on the apply's stream.  After `warmup` untimed
+    applies: `steps` applies, each bracketed by two events (with `flush`,
+    each after a cache flush outside its events), then `steps` more with a
+    third event between the two launches, for the per-launch times (an
+    event between the launches adds a small gap of its own, so the apply
+    times come from the first pass).  Returns (apply, local, remote, wall ms
+    per apply of the first pass)."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         plan.apply(v, w, stream=stream)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
     t0 = time.perf_counter()
+    for k in range(steps):
+        if flush is not None:
+            flush()
+        ev[k][0].record(stream)
+        plan.apply(v, w, stream=stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    apply_ = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     for k in range(steps):
         if flush is not None:
             flush()
@@ -166,8 +181,6 @@ def time_applies(torch, plan, v, w, nap, steps, warmup, flush=None):
         plan.apply_stage(nap.STAGE_REMOTE, v, w, stream=stream)
         ev[k][2].record(stream)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3 / steps
-    apply_ = [ev[k][0].elapsed_time(ev[k][2]) for k in range(steps)]
     local = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
     remote = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
     return apply_, local, remote, wall
