@@ -298,7 +298,7 @@ __device__ __forceinline__ void pack_scatter_item(int4 it, int32_t n, const uint
 constexpr int kMaxRows = 1024;
 
 template <typename VT, typename XT, typename CT, int CAP, int W, bool REMOTE, bool DIRECT = false,
-          bool NTW = false>
+          bool NTW = false, bool SLOT = REMOTE>
 __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                               int2 win, const int32_t *__restrict__ rowptr,
                                               const CT *__restrict__ col, int32_t cbase,
@@ -345,13 +345,13 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
     // discarded.
     int32_t c[U];
     XT a[U];
-    int32_t sl[REMOTE ? U : 1];
+    int32_t sl[SLOT ? U : 1];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t k = block_entry(k0, k1, u * kBlock + tid);
         c[u] = cbase + (int32_t)__builtin_nontemporal_load(col + k);
         a[u] = (XT)load_val(val, k);
-        if (REMOTE) sl[REMOTE ? u : 0] = __builtin_nontemporal_load(slot + k);
+        if (SLOT) sl[SLOT ? u : 0] = __builtin_nontemporal_load(slot + k);
     }
     XT t[W > 0 ? W / kBlock : 1];
     if (W > 0) {
@@ -395,7 +395,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
         const int32_t k = k0 + u * kBlock + tid;
         if (k < k1) {
             if (W > 0 && (uint32_t)(c[u] - win.x) < (uint32_t)win.y) x[u] = wbuf[c[u] - win.x];
-            prod[REMOTE ? sl[REMOTE ? u : 0] : k - k0] = a[u] * x[u];
+            prod[SLOT ? sl[SLOT ? u : 0] : k - k0] = a[u] * x[u];
         }
     }
     __syncthreads();
@@ -423,30 +423,32 @@ constexpr int product_run() {
     return e * kBlock <= CAP ? e : CAP / kBlock;
 }
 
-// On-process row block with E consecutive entries per lane: each lane loads
-// the columns and values of its entries as aligned runs (one vector load
-// each), so a wave moves E times the bytes per load instruction of
-// product_block's one entry per lane, and writes its E products to LDS with
-// one vector store.  The runs cover [k0 & -E, k1); LDS position q holds the
-// product of entry (k0 & -E) + q.  Entries of the runs outside [k0, k1) (a
-// neighbouring block's, or the arrays' zero padding past the last entry) are
-// loaded and discarded, and their columns are not used to read v.  Each row
-// adds its products in stored order, as in product_block, so the sums are
-// the same.  A block whose aligned span is longer than CAP (the schedules
-// leave only single rows so long) or that is empty goes to product_block.
-// E > 1.
-template <typename VT, typename XT, typename CT, int CAP, int W, bool NTW, int E>
-__device__ __forceinline__ void local_product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
-                                                   int2 win, const int32_t *__restrict__ rowptr,
-                                                   const CT *__restrict__ col, int32_t cbase,
-                                                   const VT *__restrict__ val,
-                                                   const XT *__restrict__ xsrc,
-                                                   XT *__restrict__ w, XT *prod, XT *wbuf) {
+// Row block in stored order with E consecutive entries per lane (the
+// on-process product; with REMOTE, an off-process block the host keeps in
+// stored order, adding into the partial w): each lane loads the columns and
+// values of its entries as aligned runs (one vector load each), so a wave
+// moves E times the bytes per load instruction of product_block's one entry
+// per lane, and writes its E products to LDS with one vector store.  The
+// runs cover [k0 & -E, k1); LDS position q holds the product of entry
+// (k0 & -E) + q.  Entries of the runs outside [k0, k1) (a neighbouring
+// block's, or the arrays' zero padding past the last entry) are loaded and
+// discarded, and their columns are not used to read x.  Each row adds its
+// products in stored order, as in product_block, so the sums are the same.
+// A block whose aligned span is longer than CAP (the schedules leave only
+// single rows so long) or that is empty goes to product_block.  E > 1.
+template <typename VT, typename XT, typename CT, int CAP, int W, bool NTW, int E,
+          bool REMOTE = false>
+__device__ __forceinline__ void product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
+                                             int2 win, const int32_t *__restrict__ rowptr,
+                                             const CT *__restrict__ col, int32_t cbase,
+                                             const VT *__restrict__ val,
+                                             const XT *__restrict__ xsrc, XT *__restrict__ w,
+                                             XT *prod, XT *wbuf) {
+    static_assert(!REMOTE || W == 0, "off-process blocks stage no window");
     const int32_t k0a = k0 & -E;
     if (k1 == k0 || k1 - k0a > CAP) {
-        product_block<VT, XT, CT, CAP, W, false, false, NTW>(r0, r1, k0, k1, win, rowptr, col,
-                                                              cbase, val, nullptr, xsrc, w, prod,
-                                                              wbuf);
+        product_block<VT, XT, CT, CAP, W, REMOTE, false, NTW, false>(
+            r0, r1, k0, k1, win, rowptr, col, cbase, val, nullptr, xsrc, w, prod, wbuf);
         return;
     }
     constexpr int Q = CAP / (E * kBlock);
@@ -475,11 +477,13 @@ __device__ __forceinline__ void local_product_runs(int32_t r0, int32_t r1, int32
         for (int u = 0; u < W / kBlock; ++u) t[u] = xsrc[win.x + min(u * kBlock + tid, qlast)];
     }
     int32_t rb[R], re[R];
+    XT s[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int32_t r = min(r0 + i * kBlock + tid, r1 - 1);
         rb[i] = rowptr[r];
         re[i] = rowptr[r + 1];
+        s[i] = REMOTE ? w[r] : (XT)0;
     }
     XT x[E * Q];
 #pragma unroll
@@ -488,7 +492,8 @@ __device__ __forceinline__ void local_product_runs(int32_t r0, int32_t r1, int32
         for (int j = 0; j < E; ++j) {
             const int32_t e = k0a + E * (u * kBlock + tid) + j;
             // a column outside the block may be another process's offset:
-            // read the block's own first column of v instead
+            // read the block's own base column instead (a column of v, or a
+            // ghost position of this block)
             if (e < k0 || e >= k1) c[E * u + j] = cbase;
             const int32_t cc = c[E * u + j];
             const bool inwin = W > 0 && (uint32_t)(cc - win.x) < (uint32_t)win.y;
@@ -522,8 +527,8 @@ __device__ __forceinline__ void local_product_runs(int32_t r0, int32_t r1, int32
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int32_t r = r0 + i * kBlock + tid;
-        if (r < r1) {
-            XT acc = (XT)0;
+        if (r < r1 && !(REMOTE && rb[i] == re[i])) {
+            XT acc = s[i];
             for (int32_t q = rb[i] - k0a; q < re[i] - k0a; ++q) acc = acc + prod[q];
             store_out<NTW>(acc, w + r);
         }
@@ -656,8 +661,9 @@ template <typename VT, typename XT>
 struct RemoteView {
     int32_t n_blocks;
     const int32_t *rowblk, *blkptr, *rowptr, *col;
-    // blocks whose ghost positions span less than 65536: cbase[b] >= 0 and
-    // col16 holds the positions as offsets from it (null: no such block)
+    // blocks whose ghost positions span less than 65536: cbase[b] >= 0,
+    // the block's entries stay in stored order and col16 holds their
+    // positions as offsets from it (null: no such block)
     const int32_t *cbase;
     const uint16_t *col16;
     const VT *val;
@@ -688,10 +694,9 @@ __device__ __forceinline__ void local_block(const LocalView<VT, XT> &L, int32_t 
             L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
             col, cbase, L.val, nullptr, L.v, L.w, prod, wbuf);
     else
-        local_product_runs<VT, XT, CT, CAP, W, NT, E>(L.rowblk[task], L.rowblk[task + 1],
-                                                      L.blkptr[task], L.blkptr[task + 1], wn,
-                                                      L.rowptr, col, cbase, L.val, L.v, L.w,
-                                                      prod, wbuf);
+        product_runs<VT, XT, CT, CAP, W, NT, E>(L.rowblk[task], L.rowblk[task + 1],
+                                                L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
+                                                col, cbase, L.val, L.v, L.w, prod, wbuf);
 }
 
 // LDS elements of the first launch: a band of v (exchange items), or a row
@@ -747,8 +752,16 @@ __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_
     }
     const int32_t base = R.cbase ? R.cbase[b] : -1;
     if (base >= 0) {
-        if (R.nt) remote_part<VT, XT, uint16_t, CAP, false, true>(R, b, R.col16, base, prod);
-        else remote_part<VT, XT, uint16_t, CAP, false, false>(R, b, R.col16, base, prod);
+        // a narrow block, kept in stored order (no slots)
+        constexpr int E = product_run<VT, CAP>();
+        if (R.nt)
+            product_runs<VT, XT, uint16_t, CAP, 0, true, E, true>(
+                R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], make_int2(0, 0),
+                R.rowptr, R.col16, base, R.val, R.ghost, R.w, prod, nullptr);
+        else
+            product_runs<VT, XT, uint16_t, CAP, 0, false, E, true>(
+                R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], make_int2(0, 0),
+                R.rowptr, R.col16, base, R.val, R.ghost, R.w, prod, nullptr);
     } else {
         if (R.nt) remote_part<VT, XT, int32_t, CAP, false, true>(R, b, R.col, 0, prod);
         else remote_part<VT, XT, int32_t, CAP, false, false>(R, b, R.col, 0, prod);

@@ -411,10 +411,12 @@ void build_partitions(napspmv_plan_s *p) {
 // Map the ghost positions of a block list to device positions (`map`),
 // reorder the entries of every block into gather order (sort_blocks) and
 // copy them, with their slots, over the device arrays (already allocated).
-// With `p` (the off-process part of a plan that fills a ghost buffer), also
-// lays out the blocks whose positions span less than 65536 with 16-bit
-// offsets from their first position (stencil-like halos: two bytes instead
-// of four per entry) in p->d_col16_off and p->d_offbase.
+// With `p` (the off-process part of a plan that fills a ghost buffer), the
+// blocks whose positions span less than 65536 (stencil-like halos) stay in
+// stored order instead, need no slots, and have their positions as 16-bit
+// offsets from their first one (p->d_col16_off, p->d_offbase): two bytes
+// instead of six per entry.  Their stored order already reads the ghosts
+// in short ascending runs (a row's neighbours in each halo plane).
 void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &map,
                  const std::vector<uint8_t> &val, int vs, const std::vector<int32_t> &blkptr, int cap,
                  int32_t *d_col, void *d_val, uint16_t *d_slot, napspmv_plan_s *p = nullptr) {
@@ -428,33 +430,41 @@ void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &ma
     std::vector<int32_t> cm(col.size()), c2(col.size());
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < (int64_t)col.size(); ++k) cm[k] = map[col[k]];
+    const int64_t nb = (int64_t)blkptr.size() - 1;
+    std::vector<int32_t> base;
+    std::vector<uint8_t> keep;
+    int64_t narrow = 0;
+    if (p) {
+        base.assign(nb, -1);
+        keep.assign(nb, 0);
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : narrow)
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t k0 = blkptr[b], k1 = blkptr[b + 1];
+            if (k1 == k0) continue;
+            int32_t lo = INT32_MAX, hi = -1;
+            for (int64_t k = k0; k < k1; ++k) {
+                lo = std::min(lo, cm[k]);
+                hi = std::max(hi, cm[k]);
+            }
+            if (hi - lo > 65535) continue;
+            base[b] = lo;
+            keep[b] = 1;
+            ++narrow;
+        }
+    }
     std::vector<uint8_t> v2(val.size());
     std::vector<uint16_t> s2(col.size());
     napspmv::sort_blocks(blkptr, cap, cm.data(), val.data(), vs, c2.data(), v2.data(), s2.data(),
-                         napspmv::remote_run(vs, cap));
+                         napspmv::remote_run(vs, cap), narrow ? keep.data() : nullptr);
     HIP_OK(hipMemcpy(d_col, c2.data(), c2.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_val, v2.data(), v2.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_slot, s2.data(), s2.size() * 2, hipMemcpyHostToDevice));
-    if (!p) return;
-    const int64_t nb = (int64_t)blkptr.size() - 1;
-    std::vector<int32_t> base(nb, -1);
-    std::vector<uint16_t> c16(col.size(), 0);
-    int64_t narrow = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : narrow)
-    for (int64_t b = 0; b < nb; ++b) {
-        const int64_t k0 = blkptr[b], k1 = blkptr[b + 1];
-        if (k1 == k0) continue;
-        int32_t lo = INT32_MAX, hi = -1;
-        for (int64_t k = k0; k < k1; ++k) {
-            lo = std::min(lo, c2[k]);
-            hi = std::max(hi, c2[k]);
-        }
-        if (hi - lo > 65535) continue;
-        base[b] = lo;
-        ++narrow;
-        for (int64_t k = k0; k < k1; ++k) c16[k] = (uint16_t)(c2[k] - lo);
-    }
     if (narrow == 0) return;
+    std::vector<uint16_t> c16(col.size(), 0);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < nb; ++b)
+        if (base[b] >= 0)
+            for (int64_t k = blkptr[b]; k < blkptr[b + 1]; ++k) c16[k] = (uint16_t)(c2[k] - base[b]);
     int64_t total = 0;
     if (!p->d_col16_off) {
         // kept across re-sorts, like the other entry arrays

@@ -48,7 +48,7 @@ void row_blocks_per_process(const int32_t *rowptr, const std::vector<int64_t> &s
 
 void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col,
                  const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
-                 uint16_t *slot_out, int run) {
+                 uint16_t *slot_out, int run, const uint8_t *keep) {
     const int64_t nb = (int64_t)blkptr.size() - 1;
 #pragma omp parallel
     {
@@ -58,7 +58,7 @@ void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col
             const int64_t k0 = blkptr[b], len = blkptr[b + 1] - k0;
             ord.resize((size_t)len);
             std::iota(ord.begin(), ord.end(), 0);
-            const bool sorted = len <= cap;
+            const bool sorted = len <= cap && !(keep && keep[b]);
             if (sorted)
                 std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
                     return col[k0 + x] < col[k0 + y];

@@ -55,10 +55,11 @@ constexpr int32_t run_offset(int run, int u, int t, int j) { return run * (u * k
 // instructions visit them (vector u, component j, lane t; see run_offset),
 // so that each load instruction still reads, across its lanes, consecutive
 // entries of gather order.  Other blocks of at most `cap` entries keep plain
-// gather order.
+// gather order.  Blocks with keep[b] != 0 (keep may be null) stay in stored
+// order, slot 0, like the long ones.
 void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col,
                  const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
-                 uint16_t *slot_out, int run = 1);
+                 uint16_t *slot_out, int run = 1, const uint8_t *keep = nullptr);
 
 // The window of v (first column, length <= `window`) each row block stages
 // in LDS, as interleaved pairs: the block's whole on-process column range if

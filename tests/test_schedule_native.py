@@ -5,8 +5,8 @@ a range's tail), per-process row blocks (cover, never span two processes,
 respect the entry and row limits) and the gather-order sort of off-process
 blocks (sorted in the order the kernel's loads visit positions, plain or
 laid out by runs of 2, 4 and 8 entries per lane; slots a permutation pointing
-at each entry's stored position; long single-row blocks left in stored
-order), the vector loads of the run kernels (inside the padded arrays, every
+at each entry's stored position; long single-row blocks and blocks flagged
+to keep their order left in stored order), the vector loads of the run kernels (inside the padded arrays, every
 entry of a block used exactly once, LDS indices below the block capacity,
 aligned spans within the capacity for blocks cut at capacity - 7), and, on
 saddle-point matrices whose zero block starts at a process boundary, that
