@@ -268,6 +268,32 @@ __device__ __forceinline__ void pack_scatter_item(int4 it, int32_t n, const uint
         scatter_values<T, false>(sit, 0, code, recv, ghost, lds);
 }
 
+// acc + p[q0] + p[q0 + 1] + ... + p[q1 - 1], added one at a time in that
+// order (the rounding of the sequential sum), with the LDS reads issued
+// eight (then four) at a time so that their latencies overlap instead of
+// adding up.
+template <typename XT>
+__device__ __forceinline__ XT sum_in_order(XT acc, const XT *p, int32_t q0, int32_t q1) {
+    int32_t q = q0;
+    for (; q + 8 <= q1; q += 8) {
+        XT t[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) t[i] = p[q + i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc = acc + t[i];
+    }
+    if (q + 4 <= q1) {
+        XT t[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t[i] = p[q + i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc = acc + t[i];
+        q += 4;
+    }
+    for (; q < q1; ++q) acc = acc + p[q];
+    return acc;
+}
+
 // One row block of a split CSR product.  The block owns rows [r0, r1) (at
 // most kMaxRows) and entries [k0, k1) of one of the two CSR parts, at most
 // CAP of them (else a single long row, walked in chunks of CAP).  Every
@@ -321,7 +347,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
             }
             __syncthreads();
             if (tid == 0)
-                for (int32_t q = 0; q < lim; ++q) s = s + prod[q];
+                s = sum_in_order(s, prod, 0, lim);
             __syncthreads();
         }
         if (tid == 0) w[r0] = s;
@@ -404,7 +430,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
         const int32_t r = r0 + i * kBlock + tid;
         if (r < r1 && !(REMOTE && rb[i] == re[i])) {
             XT acc = s[i];
-            for (int32_t q = rb[i] - k0; q < re[i] - k0; ++q) acc = acc + prod[q];
+            acc = sum_in_order(acc, prod, rb[i] - k0, re[i] - k0);
             store_out<NTW>(acc, w + r);
         }
     }
@@ -529,7 +555,7 @@ __device__ __forceinline__ void product_runs(int32_t r0, int32_t r1, int32_t k0,
         const int32_t r = r0 + i * kBlock + tid;
         if (r < r1 && !(REMOTE && rb[i] == re[i])) {
             XT acc = s[i];
-            for (int32_t q = rb[i] - k0a; q < re[i] - k0a; ++q) acc = acc + prod[q];
+            acc = sum_in_order(acc, prod, rb[i] - k0a, re[i] - k0a);
             store_out<NTW>(acc, w + r);
         }
     }
@@ -622,7 +648,7 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
         const int32_t r = r0 + i * kBlock + tid;
         if (r < r1 && rb[i] != re[i]) {
             XT acc = s[i];
-            for (int32_t q = rb[i] - k0; q < re[i] - k0; ++q) acc = acc + prod[q];
+            acc = sum_in_order(acc, prod, rb[i] - k0, re[i] - k0);
             store_out<NTW>(acc, w + r);
         }
     }
