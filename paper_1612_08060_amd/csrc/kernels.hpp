@@ -295,7 +295,7 @@ __device__ __forceinline__ XT sum_in_order(XT acc, const XT *p, int32_t q0, int3
 }
 
 // One row block of a split CSR product.  The block owns rows [r0, r1) (at
-// most kMaxRows) and entries [k0, k1) of one of the two CSR parts, at most
+// most ROWS) and entries [k0, k1) of one of the two CSR parts, at most
 // CAP of them (else a single long row, walked in chunks of CAP).  Every
 // thread first issues all its loads at once: its share of the entries
 // (coalesced, independent), of the block's v window, of the row pointers and,
@@ -321,10 +321,15 @@ __device__ __forceinline__ XT sum_in_order(XT acc, const XT *p, int32_t q0, int3
 // share cache lines); slot[k] is the stored position of entry k inside its
 // block, where its product lands in LDS, so the row sums still run in
 // stored order.
+//
+// Rows per block: on-process blocks hold at most kMaxRowsOn rows (two row
+// slots per thread: fewer registers, more blocks in flight), off-process
+// blocks, which cover a few rows' worth of entries each, kMaxRows.
 constexpr int kMaxRows = 1024;
+constexpr int kMaxRowsOn = 512;
 
 template <typename VT, typename XT, typename CT, int CAP, int W, bool REMOTE, bool DIRECT = false,
-          bool NTW = false, bool SLOT = REMOTE>
+          bool NTW = false, bool SLOT = REMOTE, int ROWS = kMaxRows>
 __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                               int2 win, const int32_t *__restrict__ rowptr,
                                               const CT *__restrict__ col, int32_t cbase,
@@ -334,7 +339,7 @@ __device__ __forceinline__ void product_block(int32_t r0, int32_t r1, int32_t k0
                                               XT *prod, XT *wbuf,
                                               const XT *__restrict__ vsrc = nullptr) {
     constexpr int U = CAP / kBlock;
-    constexpr int R = kMaxRows / kBlock;
+    constexpr int R = ROWS / kBlock;
     const int tid = threadIdx.x;
     if (k1 - k0 > CAP) {
         XT s = REMOTE ? w[r0] : (XT)0;
@@ -463,7 +468,7 @@ constexpr int product_run() {
 // A block whose aligned span is longer than CAP (the schedules leave only
 // single rows so long) or that is empty goes to product_block.  E > 1.
 template <typename VT, typename XT, typename CT, int CAP, int W, bool NTW, int E,
-          bool REMOTE = false>
+          bool REMOTE = false, int ROWS = kMaxRows>
 __device__ __forceinline__ void product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                              int2 win, const int32_t *__restrict__ rowptr,
                                              const CT *__restrict__ col, int32_t cbase,
@@ -473,12 +478,12 @@ __device__ __forceinline__ void product_runs(int32_t r0, int32_t r1, int32_t k0,
     static_assert(!REMOTE || W == 0, "off-process blocks stage no window");
     const int32_t k0a = k0 & -E;
     if (k1 == k0 || k1 - k0a > CAP) {
-        product_block<VT, XT, CT, CAP, W, REMOTE, false, NTW, false>(
+        product_block<VT, XT, CT, CAP, W, REMOTE, false, NTW, false, ROWS>(
             r0, r1, k0, k1, win, rowptr, col, cbase, val, nullptr, xsrc, w, prod, wbuf);
         return;
     }
     constexpr int Q = CAP / (E * kBlock);
-    constexpr int R = kMaxRows / kBlock;
+    constexpr int R = ROWS / kBlock;
     const int32_t tid = (int32_t)threadIdx.x;
     // lanes past the block load its last run (every load unconditional, as
     // in product_block)
@@ -716,13 +721,13 @@ __device__ __forceinline__ void local_block(const LocalView<VT, XT> &L, int32_t 
     const int2 wn = W > 0 ? L.win[task] : make_int2(0, 0);
     constexpr int E = product_run<VT, CAP>();
     if constexpr (E == 1)
-        product_block<VT, XT, CT, CAP, W, false, false, NT>(
+        product_block<VT, XT, CT, CAP, W, false, false, NT, false, kMaxRowsOn>(
             L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
             col, cbase, L.val, nullptr, L.v, L.w, prod, wbuf);
     else
-        product_runs<VT, XT, CT, CAP, W, NT, E>(L.rowblk[task], L.rowblk[task + 1],
-                                                L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
-                                                col, cbase, L.val, L.v, L.w, prod, wbuf);
+        product_runs<VT, XT, CT, CAP, W, NT, E, false, kMaxRowsOn>(
+            L.rowblk[task], L.rowblk[task + 1], L.blkptr[task], L.blkptr[task + 1], wn, L.rowptr,
+            col, cbase, L.val, L.v, L.w, prod, wbuf);
 }
 
 // LDS elements of the first launch: a band of v (exchange items), or a row

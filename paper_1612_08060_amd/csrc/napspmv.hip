@@ -28,7 +28,8 @@ using napspmv::HostPlan;
 namespace {
 constexpr int kIndexedItem = 4096;                  // entries of an indexed exchange item
 constexpr int kMinItem = 256, kMaxItem = 1 << 24;   // entries of a band exchange item
-constexpr int kMaxRowsPerBlock = napspmv::kMaxRows;  // rows of a product block
+constexpr int kMaxRowsPerBlock = napspmv::kMaxRows;  // rows of an off-process block
+constexpr int kMaxRowsOnBlock = napspmv::kMaxRowsOn;  // rows of an on-process block
 constexpr int64_t kAlign = 256;
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -368,7 +369,7 @@ void build_partitions(napspmv_plan_s *p) {
     for (int64_t t = 0; t < hp.n_p; ++t) {
         const int64_t r0 = hp.starts[t], r1 = hp.starts[t + 1];
         std::vector<int32_t> ob, op, fb, fp, it, ts, wn;
-        napspmv::row_blocks(hp.rowptr_on.data() + r0, r1 - r0, cap - kQuadSlack, kMaxRowsPerBlock,
+        napspmv::row_blocks(hp.rowptr_on.data() + r0, r1 - r0, cap - kQuadSlack, kMaxRowsOnBlock,
                             ob, op);
         napspmv::row_blocks(hp.rowptr_off.data() + r0, r1 - r0, cur_rcap(p) - kQuadSlack,
                             kMaxRowsPerBlock, fb, fp);
@@ -702,7 +703,7 @@ void refresh_schedules(napspmv_plan_s *p) {
     // on-process blocks never span two processes: each block's columns are
     // offsets from its process's first row
     napspmv::row_blocks_per_process(hp.rowptr_on.data(), hp.starts, cap - kQuadSlack,
-                                    kMaxRowsPerBlock, onblk, onptr);
+                                    kMaxRowsOnBlock, onblk, onptr);
     onbase.resize(onblk.size() - 1);
     for (size_t b = 0; b + 1 < onblk.size(); ++b)
         onbase[b] = (int32_t)hp.starts[(std::upper_bound(hp.starts.begin(), hp.starts.end(), onblk[b]) -
