@@ -58,15 +58,16 @@ void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col
             const int64_t k0 = blkptr[b], len = blkptr[b + 1] - k0;
             ord.resize((size_t)len);
             std::iota(ord.begin(), ord.end(), 0);
-            const bool sorted = len <= cap && !(keep && keep[b]);
+            const int64_t a = k0 & -(int64_t)run, lo = k0 - a, hi = lo + len;
+            const bool tiled = run > 1 && cap % (run * kLanes) == 0 && hi <= cap;
+            const bool sorted = len <= cap && !(keep && keep[b]) && (run == 1 || tiled);
             if (sorted)
                 std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
                     return col[k0 + x] < col[k0 + y];
                 });
             // at[q]: the position, from k0, of the q-th entry of gather order
             at.resize((size_t)len);
-            const int64_t a = k0 & -(int64_t)run, lo = k0 - a, hi = lo + len;
-            if (sorted && run > 1 && cap % (run * kLanes) == 0 && hi <= cap) {
+            if (sorted && tiled) {
                 int64_t q = 0;
                 for (int u = 0; u < cap / (run * kLanes); ++u)
                     for (int j = 0; j < run; ++j)

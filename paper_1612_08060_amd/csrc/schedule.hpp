@@ -50,13 +50,14 @@ constexpr int32_t run_offset(int run, int u, int t, int j) { return run * (u * k
 // single long row) keep stored order (slot 0).  `vs` = bytes of one value.
 // With run > 1 (cap a multiple of run * kLanes), a block whose aligned span
 // k1 - (k0 & -run) fits in `cap` is laid out for vector loads of `run`
-// entries per lane: the gather-ordered
-// entries fill the positions of [k0, k1) in the order the kernel's load
-// instructions visit them (vector u, component j, lane t; see run_offset),
-// so that each load instruction still reads, across its lanes, consecutive
-// entries of gather order.  Other blocks of at most `cap` entries keep plain
-// gather order.  Blocks with keep[b] != 0 (keep may be null) stay in stored
-// order, slot 0, like the long ones.
+// entries per lane: the gather-ordered entries fill the positions of
+// [k0, k1) in the order the kernel's load instructions visit them (vector u,
+// component j, lane t; see run_offset), so that each load instruction still
+// reads, across its lanes, consecutive entries of gather order; a block
+// whose aligned span does not fit (a single row, which the kernel walks in
+// chunks) stays in stored order, slot 0, like the long ones.  With run 1,
+// every block of at most `cap` entries is in plain gather order.  Blocks
+// with keep[b] != 0 (keep may be null) stay in stored order, slot 0.
 void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col,
                  const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
                  uint16_t *slot_out, int run = 1, const uint8_t *keep = nullptr);
@@ -81,15 +82,6 @@ constexpr int64_t kItemTail = 512;
 constexpr int64_t kPackScatterTail = 1024;
 void merge_tasks(int64_t n_items, int64_t n_blocks, std::vector<int32_t> &tasks,
                  int64_t tail = kItemTail);
-
-// Entry that lane position q (0 <= q < the block's capacity) of a non-empty
-// row block [k0, k1) loads: q's own entry, clamped to the block's last one,
-// so that every lane can issue its loads unconditionally and every load
-// stays inside the block (a 16-bit column is an offset from the block's own
-// process).  Empty blocks load nothing.  constexpr: the kernels use it too.
-constexpr int32_t block_entry(int32_t k0, int32_t k1, int32_t q) {
-    return k0 + q < k1 ? k0 + q : k1 - 1;
-}
 
 // Work items covering [0, total) in order, pieces of at most `max_len`.
 void flat_items(int64_t total, int max_len, std::vector<int32_t> &items);

@@ -85,7 +85,15 @@ static int check_sort(std::mt19937 &rng, const std::vector<int32_t> &rowptr,
         // positions in load order
         std::vector<int32_t> order;
         const int32_t a = k0 & -run;
-        if (run > 1 && k0 - a + len <= cap) {
+        if (run > 1 && !(cap % (run * napspmv::kLanes) == 0 && k0 - a + len <= cap)) {
+            // a single row whose aligned span does not fit: stored order
+            for (int32_t q = 0; q < len; ++q)
+                if (slot[k0 + q] != 0 || col_out[k0 + q] != col[k0 + q] ||
+                    val_out[k0 + q] != val[k0 + q])
+                    return fail("unfit run block moved", trial, q);
+            continue;
+        }
+        if (run > 1) {
             ++tiled;
             for (int u = 0; u < cap / (run * napspmv::kLanes); ++u)
                 for (int j = 0; j < run; ++j)
@@ -203,16 +211,28 @@ static int check_blocks_and_sort() {
                      check_sort(rng, rowptr, bp, cap, run, trial, true)))
                     return 1;
         }
+        // single rows of cap - 6 .. cap entries: blocks whose aligned span
+        // may exceed cap
+        for (int cap : {1024, 2048}) {
+            std::vector<int32_t> rp2(n + 1, 0);
+            for (int i = 0; i < n; ++i)
+                rp2[i + 1] = rp2[i] + (i % 7 == 3 ? cap - (int)(rng() % 7) : (int)(rng() % 30));
+            std::vector<int32_t> rb, bp;
+            napspmv::row_blocks_per_process(rp2.data(), starts, cap - 7, 8, rb, bp);
+            for (int run : {2, 4})
+                if (check_sort(rng, rp2, bp, cap, run, trial)) return 1;
+        }
     }
     return 0;
 }
 
 // Saddle-point matrix [[H, B^T], [B, 0]] (H: n1 x n1 banded, B: m x n1, m < n1)
 // with a process boundary at row n1: the B rows have no on-process entry, so
-// their on-process row blocks are empty.  Every load of a non-empty block
-// (block_entry, the clamp the kernels use) must stay among the block's own
-// entries, whose columns its own process owns: a 16-bit column offset from
-// the block's process then stays below n.  Returns the empty blocks seen.
+// their on-process row blocks are empty.  The runs of a non-empty block may
+// load a neighbouring block's entries (another process's 16-bit column
+// offsets), but every column the kernel uses to read v must be its own
+// process's, so that a 16-bit offset from the block's process stays below
+// n.  Returns the empty blocks seen.
 static int check_saddle_loads(int64_t &empty_blocks) {
     empty_blocks = 0;
     std::mt19937 rng(11);
@@ -243,22 +263,37 @@ static int check_saddle_loads(int64_t &empty_blocks) {
                 if (owner(j) == owner(i)) col.push_back(j);
             rowptr[i + 1] = (int32_t)col.size();
         }
-        for (int cap : {16, 64, 4096}) {
+        // the on-process product's loads: runs of E entries per lane
+        // (product_runs), blocks cut at cap - 7 entries and 512 rows;
+        // every column it uses to read v is the block's own (a loaded entry
+        // outside the block is replaced by the process's first row)
+        const int nnz = rowptr[n];
+        for (int cap : {1024, 4096}) {
             std::vector<int32_t> rb, bp;
-            napspmv::row_blocks_per_process(rowptr.data(), starts, cap, 1024, rb, bp);
-            for (size_t b = 0; b + 1 < rb.size(); ++b) {
-                const int32_t k0 = bp[b], k1 = bp[b + 1];
-                const int64_t t = owner(rb[b]);
-                if (k1 == k0) {
-                    ++empty_blocks;
-                    continue;
-                }
-                for (int32_t q = 0; q < cap; ++q) {
-                    const int32_t k = napspmv::block_entry(k0, k1, q);
-                    if (k < k0 || k >= k1) return fail("load outside the block", trial, q);
-                    const int64_t off = col[k] - starts[t];
-                    if (owner(col[k]) != t || starts[t] + off >= n)
-                        return fail("column outside the block's process", trial, k);
+            napspmv::row_blocks_per_process(rowptr.data(), starts, cap - 7, 512, rb, bp);
+            for (int run : {2, 4, 8}) {
+                for (size_t b = 0; b + 1 < rb.size(); ++b) {
+                    const int32_t k0 = bp[b], k1 = bp[b + 1], a = k0 & -run;
+                    const int64_t t = owner(rb[b]);
+                    if (k1 == k0) {
+                        if (run == 2 && cap == 1024) ++empty_blocks;
+                        continue;
+                    }
+                    if (k1 - a > cap) continue;     // a single long row, walked in chunks
+                    const int32_t last = (k1 - 1) & -run;
+                    for (int u = 0; u < cap / (run * napspmv::kLanes); ++u)
+                        for (int l = 0; l < napspmv::kLanes; ++l) {
+                            const int32_t e = std::min(a + napspmv::run_offset(run, u, l, 0), last);
+                            if (e < 0 || e + run > nnz + 8) return fail("load outside the arrays", trial, e);
+                            for (int j = 0; j < run; ++j) {
+                                const int32_t k = a + napspmv::run_offset(run, u, l, j);
+                                const bool used = k >= k0 && k < k1;
+                                const int64_t c = used ? col[k] : starts[t];
+                                if (used && owner(col[k]) != t)
+                                    return fail("column outside the block's process", trial, k);
+                                if (c < 0 || c >= n) return fail("v read outside v", trial, k);
+                            }
+                        }
                 }
             }
         }

@@ -4,14 +4,15 @@ permutation of items and row blocks, proportional per XCD range, no item in
 a range's tail), per-process row blocks (cover, never span two processes,
 respect the entry and row limits) and the gather-order sort of off-process
 blocks (sorted in the order the kernel's loads visit positions, plain or
-laid out by runs of 2, 4 and 8 entries per lane; slots a permutation pointing
-at each entry's stored position; long single-row blocks and blocks flagged
-to keep their order left in stored order), the vector loads of the run kernels (inside the padded arrays, every
-entry of a block used exactly once, LDS indices below the block capacity,
-aligned spans within the capacity for blocks cut at capacity - 7), and, on
-saddle-point matrices whose zero block starts at a process boundary, that
-every load a non-empty on-process block issues (the kernels' own clamp)
-stays among the block's entries, whose columns the block's process owns."""
+laid out by runs of 2, 4 and 8 entries per lane; slots a permutation
+pointing at each entry's stored position; long single-row blocks, single
+rows whose aligned span exceeds the capacity, and blocks flagged to keep
+their order left in stored order), the vector loads of the run kernels
+(inside the padded arrays, every entry of a block used exactly once, LDS
+indices below the block capacity, aligned spans within the capacity for
+blocks cut at capacity - 7), and, on saddle-point matrices whose zero block
+starts at a process boundary, that every column the on-process product's
+runs use to read v is the block's own process's."""
 import os
 import shutil
 import subprocess
