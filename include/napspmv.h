@@ -453,6 +453,19 @@ NAPSPMV_API int napspmv_plan_ghosts(napspmv_plan_t plan, int64_t *ghost_ptr, int
 NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *ws, void *out,
                                                void *stream);
 
+/* Layout of the off-process row blocks of a device plan (the
+ * local_spmv(A_off, ghosts) step of the split product, Algorithm 1), as
+ * counts written to the caller's host int64 array kinds_out[3]:
+ *   [0] plain   gather order, int32 ghost positions and 16-bit slots
+ *   [1] packed  gather order, position and slot in one 32-bit word whose
+ *               position is an offset from a base shared by 16 lanes
+ *   [2] narrow  stored order, 16-bit positions from a per-block base
+ * (blocks without entries are not counted).  The layout never changes a
+ * result bit;
+ * it follows BLOCK_NNZ and REMOTE_NNZ.  EINVAL for a NULL argument or a
+ * host-only plan. */
+NAPSPMV_API int napspmv_plan_block_kinds(napspmv_plan_t plan, int64_t *kinds_out);
+
 /* Tuning parameters of the apply kernels (NAPSPMV_PARAM_*); -1 restores the
  * automatic value.  No parameter changes any result bit.  Setting one on a
  * device plan rebuilds and re-uploads the launch schedules (it allocates and

@@ -67,6 +67,7 @@ _SIGS = {
     "napspmv_apply_stage": (I32, [P, I32, P, P, P]),
     "napspmv_plan_stats": (I32, [P, P]),
     "napspmv_plan_rows": (I32, [P, P]),
+    "napspmv_plan_block_kinds": (I32, [P, P]),
     "napspmv_plan_level_stats": (I32, [P, I64, P]),
     "napspmv_plan_export": (I32, [P, I32, P, P, P, P, P, P]),
     "napspmv_plan_ghosts": (I32, [P, P, P]),
@@ -261,6 +262,13 @@ class Plan:
         out = np.empty(self.n, np.int64)
         _check(load_library().napspmv_plan_rows(self._h, out.ctypes.data))
         return out
+
+    def block_kinds(self) -> dict:
+        """Counts of the off-process row blocks by layout: plain, packed,
+        narrow (device plans)."""
+        out = np.zeros(3, np.int64)
+        _check(load_library().napspmv_plan_block_kinds(self._h, out.ctypes.data))
+        return {"plain": int(out[0]), "packed": int(out[1]), "narrow": int(out[2])}
 
     def ghosts(self):
         """(ghost_ptr int64[n_p+1], ghost_col int32[G])."""

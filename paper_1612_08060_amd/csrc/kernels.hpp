@@ -500,7 +500,13 @@ __device__ __forceinline__ void product_runs(int32_t r0, int32_t r1, int32_t k0,
 // LDS at their slots and each row adds them in stored order to its partial
 // sum.  A block whose aligned span is longer than CAP (a
 // single row, which the host keeps in stored order) goes to row_in_chunks.
-template <typename VT, typename XT, typename CT, int CAP, bool DIRECT, bool NTW, int E>
+//
+// PACKED: the block's columns are packed words (pack_block): slot in the
+// high bits, the position's offset from its lane group's base in the low
+// bits; the bases (`pbase`, this block's) are wave-uniform scalar loads, and
+// no slot stream is read.
+template <typename VT, typename XT, typename CT, int CAP, bool DIRECT, bool NTW, int E,
+          bool PACKED = false>
 __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
                                                     const int32_t *__restrict__ rowptr,
                                                     const CT *__restrict__ col, int32_t cbase,
@@ -508,7 +514,9 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
                                                     const uint16_t *__restrict__ slot,
                                                     const XT *__restrict__ xsrc,
                                                     XT *__restrict__ w, XT *prod,
-                                                    const XT *__restrict__ vsrc) {
+                                                    const XT *__restrict__ vsrc,
+                                                    const int32_t *__restrict__ pbase = nullptr) {
+    static_assert(!PACKED || (!DIRECT && CAP <= (1 << kPackSlotBits)), "packed words");
     static_assert(kBlock == kLanes, "the host's run layout assumes the kernels' lane count");
     static_assert(E > 1 && CAP % (E * kBlock) == 0, "runs must tile the block");
     const int32_t k0a = k0 & -E;
@@ -528,15 +536,27 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
     // registers, more workgroups in flight
     int32_t c[E * Q];
     Vec<VT, E> aq[Q];
-    Vec<uint16_t, E> sq[Q];
+    Vec<uint16_t, PACKED ? 1 : E> sq[PACKED ? 1 : Q];
+    uint32_t pw[PACKED ? E * Q : 1];
 #pragma unroll
     for (int u = 0; u < Q; ++u) {
         const int32_t e = min(k0a + run_offset(E, u, tid, 0), klast);
         const Vec<CT, E> cq = load_vec<E>(col, e);
         aq[u] = load_vec<E>(val, e);
-        sq[u] = load_vec<E>(slot, e);
+        if (!PACKED) sq[PACKED ? 0 : u] = load_vec<PACKED ? 1 : E>(slot, e);
 #pragma unroll
-        for (int j = 0; j < E; ++j) c[E * u + j] = cbase + (int32_t)cq[j];
+        for (int j = 0; j < E; ++j) {
+            if (PACKED) pw[PACKED ? E * u + j : 0] = (uint32_t)cq[j];
+            else c[E * u + j] = cbase + (int32_t)cq[j];
+        }
+    }
+    if (PACKED) {
+        // lane t's base for load u * E + j: the lanes of a group read the
+        // same word, a wave's four groups one 16-byte piece
+        const int32_t *pb = pbase + pack_base_index(CAP, E, 0, tid, 0);
+#pragma unroll
+        for (int i = 0; i < E * Q; ++i)
+            c[i] = pb[i * (kWave / kPackLanes)] + (int32_t)(pw[i] & ((1u << kPackPosBits) - 1));
     }
     int32_t rb[R], re[R];
     XT s[R];
@@ -568,7 +588,9 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int32_t e = k0a + run_offset(E, u, tid, j);
-            if (e >= k0 && e < k1) prod[sq[u][j]] = widen(aq[u][j]) * x[E * u + j];
+            const uint32_t q = PACKED ? pw[PACKED ? E * u + j : 0] >> kPackPosBits
+                                      : (uint32_t)sq[PACKED ? 0 : u][PACKED ? 0 : j];
+            if (e >= k0 && e < k1) prod[q] = widen(aq[u][j]) * x[E * u + j];
         }
     }
     __syncthreads();
@@ -616,10 +638,13 @@ template <typename VT, typename XT>
 struct RemoteView {
     int32_t n_blocks;
     const int32_t *rowblk, *blkptr, *rowptr, *col;
-    // blocks whose ghost positions span less than 65536: cbase[b] >= 0,
-    // the block's entries stay in stored order and col16 holds their
-    // positions as offsets from it (null: no such block)
+    // per block (null: every block plain): cbase[b] >= 0, a block whose
+    // ghost positions span less than 65536, kept in stored order, col16
+    // holding its positions as offsets from cbase[b]; kPackedBlock, a block
+    // whose col holds packed words (pack_block) with its bases at
+    // pbase[b * (CAP / kPackLanes)]; kPlainBlock, int32 positions and slots
     const int32_t *cbase;
+    const int32_t *pbase;
     const uint16_t *col16;
     const VT *val;
     const uint16_t *slot;      // stored position of each entry inside its block
@@ -684,12 +709,13 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
     }
 }
 
-template <typename VT, typename XT, typename CT, int CAP, bool DIRECT, bool NT>
+template <typename VT, typename XT, typename CT, int CAP, bool DIRECT, bool NT, bool PACKED = false>
 __device__ __forceinline__ void remote_part(const RemoteView<VT, XT> &R, int32_t b, const CT *col,
                                             int32_t cbase, XT *prod) {
-    remote_product_runs<VT, XT, CT, CAP, DIRECT, NT, remote_run((int)sizeof(VT), CAP)>(
+    remote_product_runs<VT, XT, CT, CAP, DIRECT, NT, remote_run((int)sizeof(VT), CAP), PACKED>(
         R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], R.rowptr, col, cbase, R.val,
-        R.slot, R.ghost, R.w, prod, R.v);
+        R.slot, R.ghost, R.w, prod, R.v,
+        PACKED ? R.pbase + (int64_t)b * (CAP / kPackLanes) : nullptr);
 }
 
 template <typename VT, typename XT, int CAP>
@@ -699,7 +725,7 @@ __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_
         else remote_part<VT, XT, int32_t, CAP, true, false>(R, b, R.col, 0, prod);
         return;
     }
-    const int32_t base = R.cbase ? R.cbase[b] : -1;
+    const int32_t base = R.cbase ? R.cbase[b] : kPlainBlock;
     if (base >= 0) {
         // a narrow block, kept in stored order (no slots)
         constexpr int E = product_run<VT, CAP>();
@@ -711,6 +737,11 @@ __device__ __forceinline__ void remote_block(const RemoteView<VT, XT> &R, int32_
             product_runs<VT, XT, uint16_t, CAP, 0, false, E, true>(
                 R.rowblk[b], R.rowblk[b + 1], R.blkptr[b], R.blkptr[b + 1], make_int2(0, 0),
                 R.rowptr, R.col16, base, R.val, R.ghost, R.w, prod, nullptr);
+    } else if (base == kPackedBlock) {
+        if constexpr (CAP <= (1 << kPackSlotBits)) {
+            if (R.nt) remote_part<VT, XT, int32_t, CAP, false, true, true>(R, b, R.col, 0, prod);
+            else remote_part<VT, XT, int32_t, CAP, false, false, true>(R, b, R.col, 0, prod);
+        }
     } else {
         if (R.nt) remote_part<VT, XT, int32_t, CAP, false, true>(R, b, R.col, 0, prod);
         else remote_part<VT, XT, int32_t, CAP, false, false>(R, b, R.col, 0, prod);

@@ -101,7 +101,12 @@ struct napspmv_plan_s {
     // no block qualifies or the plan reads ghosts directly
     uint16_t *d_col16_off = nullptr;
     int32_t *d_offbase = nullptr;
+    // off-process blocks in gather order whose d_col_off entries are packed
+    // words (d_offbase[b] = kPackedBlock): their lane-group bases, cap /
+    // kPackLanes per block (napspmv::pack_block)
+    int32_t *d_pbase = nullptr;
     int64_t offbase_bytes = 0;
+    int64_t block_kinds[3] = {0, 0, 0};  // off-process blocks: plain, packed, narrow
     hipStream_t helper = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void *d_ws = nullptr;            // the plan's own workspace (ghost, send, receive)
@@ -254,10 +259,11 @@ void free_device(napspmv_plan_s *p) {
                     p->d_val_off, p->d_off, p->d_code, p->d_pgcol, p->d_pgpos, p->d_ws,
                     p->d_l2pos, p->d_l2col,
                     p->d_rp_nd, p->d_col_nd, p->d_val_nd, p->d_slot_off, p->d_slot_nd,
-                    p->d_col16_on, p->d_s1src, p->d_col16_off, p->d_offbase};
+                    p->d_col16_on, p->d_s1src, p->d_col16_off, p->d_offbase, p->d_pbase};
     for (void *q : ptrs) free_ptr(q);
     p->d_col16_off = nullptr;
     p->d_offbase = nullptr;
+    p->d_pbase = nullptr;
     p->offbase_bytes = 0;
     p->d_rp_nd = p->d_col_nd = nullptr;
     p->d_val_nd = nullptr;
@@ -289,6 +295,9 @@ int64_t planned_device_bytes(const napspmv_plan_s *p) {
     b += (int64_t)(hp.rowptr_nd.size() + hp.col_nd.size()) * 4 + (int64_t)hp.val_nd.size();
     b += (int64_t)(hp.col_off.size() + hp.col_nd.size()) * 2;   // gather-order slots
     if (!hp.direct) b += (int64_t)hp.col_off.size() * 2;         // 16-bit positions (narrow blocks)
+    // lane-group bases of packed blocks: 8192 / 16 per block at most, blocks
+    // cut by entries or by 1024 rows
+    if (!hp.direct) b += (hp.n_p + hp.n / 1024 + 1) * 2048 + (int64_t)hp.col_off.size() / 2;
     b += (int64_t)kQuadPad * (4 + hp.value_size) * 3;             // padding for vector loads
     // band offsets (ghosts or send entries) and, for NAP, the scatter codes
     const int64_t gd = p->G + ghost_slack(p->G);
@@ -417,13 +426,17 @@ void build_partitions(napspmv_plan_s *p) {
 // stored order instead, need no slots, and have their positions as 16-bit
 // offsets from their first one (p->d_col16_off, p->d_offbase): two bytes
 // instead of six per entry.  Their stored order already reads the ghosts
-// in short ascending runs (a row's neighbours in each halo plane).
+// in short ascending runs (a row's neighbours in each halo plane).  The
+// other gather-ordered blocks carry position and slot in one packed word
+// where pack_block allows it (p->d_pbase): four bytes instead of six.
 void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &map,
                  const std::vector<uint8_t> &val, int vs, const std::vector<int32_t> &blkptr, int cap,
                  int32_t *d_col, void *d_val, uint16_t *d_slot, napspmv_plan_s *p = nullptr) {
     if (p) {
         free_ptr(p->d_offbase);
+        free_ptr(p->d_pbase);
         p->d_offbase = nullptr;
+        p->d_pbase = nullptr;
         charge(p, -p->offbase_bytes);
         p->offbase_bytes = 0;
     }
@@ -436,7 +449,7 @@ void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &ma
     std::vector<uint8_t> keep;
     int64_t narrow = 0;
     if (p) {
-        base.assign(nb, -1);
+        base.assign(nb, napspmv::kPlainBlock);
         keep.assign(nb, 0);
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : narrow)
         for (int64_t b = 0; b < nb; ++b) {
@@ -455,18 +468,49 @@ void sort_upload(const std::vector<int32_t> &col, const std::vector<int32_t> &ma
     }
     std::vector<uint8_t> v2(val.size());
     std::vector<uint16_t> s2(col.size());
+    const int run = napspmv::remote_run(vs, cap);
     napspmv::sort_blocks(blkptr, cap, cm.data(), val.data(), vs, c2.data(), v2.data(), s2.data(),
-                         napspmv::remote_run(vs, cap), narrow ? keep.data() : nullptr);
+                         run, narrow ? keep.data() : nullptr);
+    // packed words, written over the positions of each block that takes them
+    int64_t packed = 0;
+    std::vector<int32_t> pbase;
+    if (p) {
+        const int64_t per = cap / napspmv::kPackLanes;
+        pbase.assign((size_t)(nb * per), 0);
+        uint32_t *words = reinterpret_cast<uint32_t *>(c2.data());
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : packed)
+        for (int64_t b = 0; b < nb; ++b)
+            if (base[b] == napspmv::kPlainBlock && blkptr[b + 1] > blkptr[b] &&
+                napspmv::pack_block(blkptr[b], blkptr[b + 1], cap, run, c2.data(), s2.data(),
+                                    words, pbase.data() + b * per)) {
+                base[b] = napspmv::kPackedBlock;
+                ++packed;
+            }
+    }
     HIP_OK(hipMemcpy(d_col, c2.data(), c2.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_val, v2.data(), v2.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(d_slot, s2.data(), s2.size() * 2, hipMemcpyHostToDevice));
-    if (narrow == 0) return;
+    if (p) {
+        int64_t empty = 0;
+        for (int64_t b = 0; b < nb; ++b) empty += blkptr[b + 1] == blkptr[b];
+        p->block_kinds[0] = nb - packed - narrow - empty;
+        p->block_kinds[1] = packed;
+        p->block_kinds[2] = narrow;
+    }
+    if (narrow == 0 && packed == 0) return;
+    int64_t total = 0;
+    if (packed) upload(p->d_pbase, pbase, total);
+    if (narrow == 0) {
+        upload(p->d_offbase, base, total);
+        p->offbase_bytes = total;
+        charge(p, total);
+        return;
+    }
     std::vector<uint16_t> c16(col.size(), 0);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t b = 0; b < nb; ++b)
         if (base[b] >= 0)
             for (int64_t k = blkptr[b]; k < blkptr[b + 1]; ++k) c16[k] = (uint16_t)(c2[k] - base[b]);
-    int64_t total = 0;
     if (!p->d_col16_off) {
         // kept across re-sorts, like the other entry arrays
         const size_t bytes = (col.size() + kQuadPad) * 2;
@@ -725,6 +769,11 @@ void refresh_schedules(napspmv_plan_s *p) {
         sort_upload(hp.col_off, hp.direct ? p->dmap : p->gpos, hp.val_off, (int)hp.value_size,
                     offptr, rcap, p->d_col_off, p->d_val_off, p->d_slot_off,
                     hp.direct ? nullptr : p);
+        if (hp.direct) {
+            // direct reads keep int32 sources in gather order
+            p->block_kinds[0] = p->block_kinds[1] = p->block_kinds[2] = 0;
+            for (size_t b = 0; b + 1 < offptr.size(); ++b) p->block_kinds[0] += offptr[b + 1] > offptr[b];
+        }
         if (hp.three_way)
             sort_upload(hp.col_nd, p->gpos, hp.val_nd, (int)hp.value_size, ndptr, rcap,
                         p->d_col_nd, p->d_val_nd, p->d_slot_nd);
@@ -916,6 +965,7 @@ napspmv::RemoteView<VT, XT> remote_view(const napspmv_plan_s *p, const Schedules
     R.rowptr = on_node ? p->d_rp_nd : p->d_rp_off;
     R.col = on_node ? p->d_col_nd : p->d_col_off;
     R.cbase = on_node || !p->d_offbase ? nullptr : p->d_offbase + blk0;
+    R.pbase = on_node || !p->d_pbase ? nullptr : p->d_pbase + blk0 * (p->cur_remote_nnz / napspmv::kPackLanes);
     R.col16 = p->d_col16_off;
     R.val = static_cast<const VT *>(on_node ? p->d_val_nd : p->d_val_off);
     R.slot = on_node ? p->d_slot_nd : p->d_slot_off;
@@ -1729,6 +1779,13 @@ int napspmv_plan_rows(napspmv_plan_t plan, int64_t *rows_out) {
         for (int64_t k = 0; k < hp.n; ++k) rows_out[k] = hp.rows_natural[k];
     else
         for (int64_t k = 0; k < hp.n; ++k) rows_out[k] = k;
+    return NAPSPMV_OK;
+}
+
+int napspmv_plan_block_kinds(napspmv_plan_t plan, int64_t *kinds_out) {
+    if (!plan || !kinds_out) return fail(NAPSPMV_EINVAL, "plan or kinds_out is NULL");
+    if (!plan->on_device) return fail(NAPSPMV_EINVAL, "host-only plan");
+    for (int i = 0; i < 3; ++i) kinds_out[i] = plan->block_kinds[i];
     return NAPSPMV_OK;
 }
 

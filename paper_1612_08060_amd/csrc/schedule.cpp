@@ -88,6 +88,37 @@ void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col
     }
 }
 
+bool pack_block(int64_t k0, int64_t k1, int cap, int run, const int32_t *pos,
+                const uint16_t *slot, uint32_t *word, int32_t *base) {
+    const int64_t a = k0 & -(int64_t)run;
+    if (run < 1 || cap % (run * kLanes) != 0 || k1 - a > cap || cap > (1 << kPackSlotBits))
+        return false;
+    const int nbase = cap / kPackLanes;
+    std::vector<int32_t> lo((size_t)nbase, INT32_MAX), hi((size_t)nbase, -1);
+    for (int u = 0; u < cap / (run * kLanes); ++u)
+        for (int t = 0; t < kLanes; ++t)
+            for (int j = 0; j < run; ++j) {
+                const int64_t k = a + run_offset(run, u, t, j);
+                if (k < k0 || k >= k1) continue;
+                const int32_t i = pack_base_index(cap, run, u, t, j);
+                lo[(size_t)i] = std::min(lo[(size_t)i], pos[k]);
+                hi[(size_t)i] = std::max(hi[(size_t)i], pos[k]);
+            }
+    for (int i = 0; i < nbase; ++i)
+        if (hi[(size_t)i] >= 0 && (int64_t)hi[(size_t)i] - lo[(size_t)i] >= (int64_t(1) << kPackPosBits))
+            return false;
+    for (int i = 0; i < nbase; ++i) base[i] = hi[(size_t)i] >= 0 ? lo[(size_t)i] : 0;
+    for (int u = 0; u < cap / (run * kLanes); ++u)
+        for (int t = 0; t < kLanes; ++t)
+            for (int j = 0; j < run; ++j) {
+                const int64_t k = a + run_offset(run, u, t, j);
+                if (k < k0 || k >= k1) continue;
+                const int32_t i = pack_base_index(cap, run, u, t, j);
+                word[k] = ((uint32_t)slot[k] << kPackPosBits) | (uint32_t)(pos[k] - base[i]);
+            }
+    return true;
+}
+
 void row_block_windows(const std::vector<int32_t> &rowblk, const std::vector<int32_t> &on_lo,
                        const std::vector<int32_t> &on_hi, int64_t n, int window,
                        std::vector<int32_t> &win) {

@@ -62,6 +62,42 @@ void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col
                  const uint8_t *val, int vs, int32_t *col_out, uint8_t *val_out,
                  uint16_t *slot_out, int run = 1, const uint8_t *keep = nullptr);
 
+// Packed off-process words.  An off-process block laid out by runs for the
+// gather (sort_blocks with run > 1) can carry each entry's ghost position
+// and slot in one 32-bit word instead of an int32 position and a 16-bit
+// slot: the slot (below 2^kPackSlotBits) in the high bits, and in the low
+// kPackPosBits bits the position's offset from a base shared by the
+// kPackLanes consecutive lanes of one wave load instruction (the smallest
+// position those lanes read).  In gather order such lanes read positions of
+// one or two bands of the ghost buffer, so the offsets stay small.  The
+// bases of a block sit at [wave][u * run + j][group] (wave = lane / kWave,
+// group = lane % kWave / kPackLanes): cap / kPackLanes of them.
+constexpr int kWave = 64;
+constexpr int kPackLanes = 16;
+constexpr int kPackPosBits = 19;
+constexpr int kPackSlotBits = 32 - kPackPosBits;
+
+// Per-block kinds of the off-process product (a block's base entry; >= 0:
+// the first ghost position of a narrow block, kept in stored order).
+constexpr int32_t kPlainBlock = -1;
+constexpr int32_t kPackedBlock = -2;
+
+// Index of the base that lane t's component j of vector u reads.
+constexpr int32_t pack_base_index(int cap, int run, int u, int t, int j) {
+    return ((t / kWave) * (cap / kLanes) + u * run + j) * (kWave / kPackLanes) +
+           (t % kWave) / kPackLanes;
+}
+
+// Pack block [k0, k1) of `pos` and `slot` (in load order, as sort_blocks
+// wrote them) into word[k0..k1) and base[0 .. cap / kPackLanes).  Returns
+// false, writing nothing, when the block is not laid out by runs (its
+// aligned span k1 - (k0 & -run) exceeds cap, or cap is not a multiple of
+// run * kLanes), when cap exceeds 2^kPackSlotBits, or when the positions of
+// some lane group span 2^kPackPosBits or more.  Groups that read no entry
+// of the block get base 0.
+bool pack_block(int64_t k0, int64_t k1, int cap, int run, const int32_t *pos,
+                const uint16_t *slot, uint32_t *word, int32_t *base);
+
 // The window of v (first column, length <= `window`) each row block stages
 // in LDS, as interleaved pairs: the block's whole on-process column range if
 // it fits, otherwise `window` columns centred on the block's rows inside that

@@ -170,6 +170,101 @@ static int check_run_loads() {
     return 0;
 }
 
+// Packed words (pack_block): decoded the way remote_product_runs decodes
+// them (lane t's base for load u * run + j at pack_base_index(cap, run, 0,
+// t, 0) + 4 (u * run + j)), every entry of a packed block gives back its
+// position and slot; a block with a lane group whose positions span
+// 2^kPackPosBits or more, a block whose aligned span exceeds cap and a cap
+// above 2^kPackSlotBits are refused with nothing written.
+static int check_pack() {
+    using namespace napspmv;
+    std::mt19937 rng(11);
+    for (int cap : {1024, 2048, 4096, 8192})
+        for (int run : {2, 4, 8})
+            for (int u = 0; u < cap / (run * kLanes); ++u)
+                for (int t = 0; t < kLanes; ++t)
+                    for (int j = 0; j < run; ++j)
+                        if (pack_base_index(cap, run, 0, t, 0) + (u * run + j) * (kWave / kPackLanes) !=
+                            pack_base_index(cap, run, u, t, j))
+                            return fail("kernel base index", cap, t);
+    int64_t packed = 0, refused = 0;
+    for (int trial = 0; trial < 60; ++trial) {
+        const int cap = 1024 << (trial % 4), run = 2 << (trial % 3);
+        if (cap < run * kLanes) continue;
+        const int n = 3000 + (int)(rng() % 4000);
+        std::vector<int32_t> rowptr(n + 1, 0);
+        for (int i = 0; i < n; ++i) rowptr[i + 1] = rowptr[i] + (int32_t)(rng() % 30);
+        const int nnz = rowptr[n];
+        std::vector<int64_t> starts = {0, n / 3, n};
+        std::vector<int32_t> rb, bp;
+        row_blocks_per_process(rowptr.data(), starts, cap - 7, 1024, rb, bp);
+        // positions: a few bands of a large buffer (packable), or, in every
+        // third trial, some blocks spread over 2^22 (refused)
+        std::vector<int32_t> col(nnz), pos(nnz);
+        std::vector<double> val(nnz), val2(nnz);
+        for (size_t b = 0; b + 1 < bp.size(); ++b) {
+            const bool wide = trial % 3 == 2 && b % 2 == 1;
+            for (int32_t k = bp[b]; k < bp[b + 1]; ++k) {
+                col[k] = wide ? (int32_t)(rng() % (1u << 22))
+                              : (int32_t)((rng() % 64) * 40000 + rng() % 9000);
+                val[k] = k;
+            }
+        }
+        std::vector<uint16_t> slot(nnz);
+        sort_blocks(bp, cap, col.data(), reinterpret_cast<const uint8_t *>(val.data()), 8, pos.data(),
+                    reinterpret_cast<uint8_t *>(val2.data()), slot.data(), run);
+        std::vector<uint32_t> word(nnz, 0xdeadbeefu);
+        std::vector<int32_t> base(cap / kPackLanes);
+        for (size_t b = 0; b + 1 < bp.size(); ++b) {
+            const int32_t k0 = bp[b], k1 = bp[b + 1], a = k0 & -run;
+            if (k1 == k0) continue;
+            int32_t span = 0;
+            for (int u = 0; u < cap / (run * kLanes); ++u)
+                for (int t = 0; t < kLanes; t += kPackLanes)
+                    for (int j = 0; j < run; ++j) {
+                        int32_t lo = INT32_MAX, hi = -1;
+                        for (int l = t; l < t + kPackLanes; ++l) {
+                            const int32_t k = a + run_offset(run, u, l, j);
+                            if (k >= k0 && k < k1) { lo = std::min(lo, pos[k]); hi = std::max(hi, pos[k]); }
+                        }
+                        if (hi >= 0) span = std::max(span, hi - lo);
+                    }
+            std::fill(base.begin(), base.end(), -7);
+            const bool fits = k1 - a <= cap;
+            const bool ok = pack_block(k0, k1, cap, run, pos.data(), slot.data(), word.data(), base.data());
+            if (ok != (fits && span < (1 << kPackPosBits))) return fail("pack decision", trial, (long long)b);
+            if (!ok) {
+                ++refused;
+                for (int32_t k = k0; k < k1; ++k)
+                    if (word[k] != 0xdeadbeefu) return fail("refused block written", trial, k);
+                for (int32_t x : base)
+                    if (x != -7) return fail("refused block wrote bases", trial, (long long)b);
+                continue;
+            }
+            ++packed;
+            for (int u = 0; u < cap / (run * kLanes); ++u)
+                for (int t = 0; t < kLanes; ++t)
+                    for (int j = 0; j < run; ++j) {
+                        const int32_t k = a + run_offset(run, u, t, j);
+                        if (k < k0 || k >= k1) continue;
+                        const int32_t bi = pack_base_index(cap, run, 0, t, 0) + (u * run + j) * (kWave / kPackLanes);
+                        const int32_t p = base[bi] + (int32_t)(word[k] & ((1u << kPackPosBits) - 1));
+                        if (p != pos[k]) return fail("packed position", trial, k);
+                        if ((word[k] >> kPackPosBits) != slot[k]) return fail("packed slot", trial, k);
+                    }
+        }
+    }
+    if (packed == 0 || refused == 0) return fail("pack cases", packed, refused);
+    // a cap whose slots need more than kPackSlotBits bits
+    std::vector<int32_t> pos(16, 1);
+    std::vector<uint16_t> slot(16, 0);
+    std::vector<uint32_t> word(16, 0);
+    std::vector<int32_t> base(65536 / kPackLanes, 0);
+    if (pack_block(0, 16, 65536, 2, pos.data(), slot.data(), word.data(), base.data()))
+        return fail("cap over the slot bits packed", 0, 0);
+    return 0;
+}
+
 static int check_blocks_and_sort() {
     std::mt19937 rng(7);
     for (int trial = 0; trial < 60; ++trial) {
@@ -304,7 +399,7 @@ static int check_saddle_loads(int64_t &empty_blocks) {
 int main() {
     int64_t empty = 0;
     if (check_merge(napspmv::kItemTail) || check_merge(napspmv::kPackScatterTail) ||
-        check_blocks_and_sort() || check_run_loads() || check_saddle_loads(empty))
+        check_blocks_and_sort() || check_run_loads() || check_pack() || check_saddle_loads(empty))
         return 1;
     if (empty == 0) return fail("saddle matrices produced no empty block", 0, 0);
     std::printf("ok\n");

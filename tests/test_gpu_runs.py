@@ -148,3 +148,66 @@ def test_narrow_and_wide_blocks_reduced(mixed, dtype):
     for rcap in (2048, 8192):
         w = _apply(a, v, n_p, 4, "standard", dtype, {"remote_nnz": rcap})
         assert _relerr(w, ref) <= TOL[dtype], rcap
+
+
+def _packed_and_plain_matrix(seed):
+    """8 processes of 196,608 rows (n = 1,572,864).  Every row has its
+    diagonal and one neighbour.  Rows of processes 0-3 also read 4 columns
+    drawn from the whole matrix: their off-process blocks read ghosts of
+    every band densely, each lane group of 16 within a short stretch of the
+    ghost buffer (packed words).  In processes 4-7 only every 997th row
+    reads 24 columns drawn from the whole matrix (about 2.4 million ghost
+    positions), so a block of 1024 rows holds one or two such rows, and with
+    two entries per lane (float64) a lane group reads a dozen of them, more
+    than 2^19 positions apart (plain int32 positions with slots)."""
+    rng = np.random.default_rng(seed)
+    n_p, per = 8, 196608
+    n = n_p * per
+    i = np.arange(n, dtype=np.int64)
+    t = i // per
+    nb = np.where(i % per == per - 1, i - 1, i + 1)
+    far_n = np.where(t < 4, 4, np.where(i % 997 == 0, 24, 0))
+    lens = 2 + far_n
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=rowptr[1:])
+    col = np.empty(int(rowptr[-1]), dtype=np.int64)
+    col[rowptr[:-1]] = i
+    col[rowptr[:-1] + 1] = nb
+    rows_far = np.repeat(i, far_n)
+    pos_far = np.repeat(rowptr[:-1] + 2, far_n) + (np.arange(rows_far.size) -
+                                                   np.repeat(np.cumsum(far_n) - far_n, far_n))
+    col[pos_far] = rng.integers(0, n, size=rows_far.size)
+    return CSR(n, rowptr, col.astype(np.int32), vec_normal(int(rowptr[-1]), seed + 1)), n_p
+
+
+@pytest.fixture(scope="module")
+def packed_plain():
+    a, n_p = _packed_and_plain_matrix(21)
+    v = vec_normal(a.n, 22)
+    return a, n_p, v, oracle_spmv.spmv_split(a, v, n_p), oracle_spmv.spmv(a, v)
+
+
+@pytest.mark.parametrize("rcap", [2048, 8192])
+def test_packed_and_plain_blocks(packed_plain, rcap):
+    """One plan with packed and plain off-process blocks (float64; float32
+    and bfloat16 plans, with 4 and 8 entries per lane, pack more of them):
+    float64 w bitwise the oracle's split-order product in both modes,
+    float32 and bfloat16 values within tolerance of the float64 oracle."""
+    a, n_p, v, split, ref = packed_plain
+    for mode, dtype in (("standard", "f64"), ("nap", "f64"), ("standard", "f32"),
+                        ("standard", "bf16")):
+        vals = {"f64": a.val, "f32": to_f32(a.val), "bf16": bf16_bits(a.val)}[dtype]
+        p = nap.Plan(a.rowptr, a.col, vals, a.n, n_p, 4, mode=mode, dtype=dtype)
+        p.set_param("remote_nnz", rcap)
+        kinds = p.block_kinds()
+        assert kinds["packed"] > 0 and (kinds["plain"] > 0 or dtype != "f64"), kinds
+        tv = torch.from_numpy(v if dtype == "f64" else to_f32(v)).to(DEV)
+        w = torch.full_like(tv, float("nan"))
+        p.apply(tv, w)
+        torch.cuda.synchronize()
+        p.close()
+        w = w.cpu().numpy().astype(np.float64)
+        if dtype == "f64":
+            assert np.array_equal(w, split), (rcap, mode)
+        else:
+            assert _relerr(w, ref) <= TOL[dtype], (rcap, dtype)
