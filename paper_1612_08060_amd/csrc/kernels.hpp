@@ -625,6 +625,7 @@ struct LocalView {
     const XT *v;
     XT *w;
     int32_t nt;                // stores past the caches (see stream_out)
+    int32_t nt_band;           // with nt, exchange items of lower bands store plainly
     // NAP pack-and-scatter items (item.w = 1): ghost band boundaries, the
     // scatter codes, the received buffer and the ghost buffer
     const int32_t *gband;
@@ -693,7 +694,8 @@ __device__ __forceinline__ void local_task(const LocalView<VT, XT> &L, int32_t t
                                        L.code, L.recv, L.ghost, lds, L.nt != 0);
             return;
         }
-        exchange_item<XT, BAND>(it, L.n, L.off, L.idx, L.dpos, L.v, L.xdst, lds, L.nt != 0);
+        exchange_item<XT, BAND>(it, L.n, L.off, L.idx, L.dpos, L.v, L.xdst, lds,
+                                L.nt != 0 && it.x >= L.nt_band);
         return;
     }
     if (L.col16) {
