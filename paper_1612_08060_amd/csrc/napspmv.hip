@@ -107,6 +107,7 @@ struct napspmv_plan_s {
     int32_t *d_pbase = nullptr;
     int64_t offbase_bytes = 0;
     int64_t block_kinds[3] = {0, 0, 0};  // off-process blocks: plain, packed, narrow
+    int32_t plain_band = 0;          // exchange bands below it use plain stores (plain_bands)
     hipStream_t helper = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void *d_ws = nullptr;            // the plan's own workspace (ghost, send, receive)
@@ -730,6 +731,35 @@ void band_items(const std::vector<int64_t> &bstart, int item, std::vector<int32_
         }
 }
 
+// The first launch's exchange buffer and both launches' w are written with
+// non-temporal stores when that buffer is larger than the 256 MB Infinity
+// Cache: the second launch cannot find it there anyway, and lines left dirty
+// in L2 would be written back while the second launch runs.  (Smaller
+// buffers are read back from the cache, and plain stores are faster.)
+int32_t stream_out(const napspmv_plan_s *p) {
+    const int64_t x = (p->hp.mode == NAPSPMV_STANDARD ? p->G : p->E) * vec_bytes(p->hp.dtype);
+    return x > ((int64_t)256 << 20) ? 1 : 0;
+}
+
+// Except, in a standard plan whose ghost buffer is at most twice that
+// cache, the bands of its first 160 MB: those the exchange stores plainly.
+// Their write-back then overlaps the end of the first launch and the second
+// launch, and the first launch gains more than the second loses (KKT-like
+// float64 apply, plain stores for the first 79 / 158 / 237 MB of the 316 MB
+// ghost buffer: 0.4565 / 0.452 / 0.4625 ms against 0.458 ms).  With a much
+// larger buffer the second launch loses more (the strided partition of the
+// same matrix, 996 MB of ghosts: 0.916 -> 0.929 ms).  Returns the first band
+// stored non-temporally; computed when the bands are laid out.
+int32_t plain_bands(const napspmv_plan_s *p) {
+    constexpr int64_t kPlainBytes = (int64_t)160 << 20;
+    const int64_t vb = vec_bytes(p->hp.dtype);
+    if (p->hp.mode != NAPSPMV_STANDARD || !stream_out(p) || p->G * vb > ((int64_t)512 << 20))
+        return 0;
+    int32_t b = 0;
+    while (b + 1 < (int32_t)p->gband.size() && p->gband[b + 1] * vb <= kPlainBytes) ++b;
+    return b;
+}
+
 // (Re)build the launch schedules for the current tuning: on-process row
 // blocks with their v windows and process bases, off-process row blocks,
 // the band items of the exchange (standard: the ghost buffer; NAP: the send
@@ -766,6 +796,7 @@ void refresh_schedules(napspmv_plan_s *p) {
         // layout and the block cuts
         HIP_OK(hipDeviceSynchronize());
         build_layout(p, band, offptr, ndptr);
+        p->plain_band = plain_bands(p);
         sort_upload(hp.col_off, hp.direct ? p->dmap : p->gpos, hp.val_off, (int)hp.value_size,
                     offptr, rcap, p->d_col_off, p->d_val_off, p->d_slot_off,
                     hp.direct ? nullptr : p);
@@ -909,31 +940,6 @@ inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + napspmv::kBlock -
 
 // ---- views -------------------------------------------------------------------
 
-// The first launch's exchange buffer and both launches' w are written with
-// non-temporal stores when that buffer is larger than the 256 MB Infinity
-// Cache: the second launch cannot find it there anyway, and lines left dirty
-// in L2 would be written back while the second launch runs.  (Smaller
-// buffers are read back from the cache, and plain stores are faster.)
-int32_t stream_out(const napspmv_plan_s *p) {
-    const int64_t x = (p->hp.mode == NAPSPMV_STANDARD ? p->G : p->E) * vec_bytes(p->hp.dtype);
-    return x > ((int64_t)256 << 20) ? 1 : 0;
-}
-
-// Except the ghost bands of a standard plan's first 160 MB: those the
-// exchange stores plainly.  Their write-back then overlaps the end of the
-// first launch and the second launch, and the first launch runs faster than
-// with every store non-temporal (KKT-like float64 apply, plain stores for
-// the first 79 / 158 / 237 MB of the 316 MB ghost buffer: 0.4565 / 0.452 /
-// 0.4625 ms against 0.458 ms).  Returns the first band stored non-temporally.
-int32_t plain_bands(const napspmv_plan_s *p) {
-    constexpr int64_t kPlainBytes = (int64_t)160 << 20;
-    if (p->hp.mode != NAPSPMV_STANDARD || !stream_out(p)) return 0;
-    const int64_t vb = vec_bytes(p->hp.dtype);
-    int32_t b = 0;
-    while (b + 1 < (int32_t)p->gband.size() && p->gband[b + 1] * vb <= kPlainBytes) ++b;
-    return b;
-}
-
 template <typename VT, typename XT>
 napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &s, const Ws &ws,
                                       const XT *v, XT *w, int64_t task0, int64_t n_tasks) {
@@ -958,7 +964,7 @@ napspmv::LocalView<VT, XT> local_view(const napspmv_plan_s *p, const Schedules &
     L.v = v;
     L.w = w;
     L.nt = stream_out(p);
-    L.nt_band = plain_bands(p);
+    L.nt_band = p->plain_band;
     L.gband = s.gband;
     L.s1band = s.s1band;
     L.s1src = p->d_s1src;
