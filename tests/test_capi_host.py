@@ -180,6 +180,12 @@ def test_host_only_plan_refuses_apply():
     rc = so.napspmv_apply(p._h, 1, 2, None)
     assert rc == -1 and b"HOST_ONLY" in so.napspmv_last_error()
     assert so.napspmv_apply(None, 1, 2, None) == -1
+    # the off-process block layout exists only on the device
+    kinds = np.zeros(3, np.int64)
+    assert so.napspmv_plan_block_kinds(p._h, kinds.ctypes.data) == -1
+    assert b"host-only" in so.napspmv_last_error()
+    assert so.napspmv_plan_block_kinds(None, kinds.ctypes.data) == -1
+    assert so.napspmv_plan_block_kinds(p._h, None) == -1
     p.close()
     assert so.napspmv_plan_destroy(None) == 0
 
