@@ -538,49 +538,94 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
     Vec<VT, E> aq[Q];
     Vec<uint16_t, PACKED ? 1 : E> sq[PACKED ? 1 : Q];
     uint32_t pw[PACKED ? E * Q : 1];
-#pragma unroll
-    for (int u = 0; u < Q; ++u) {
-        const int32_t e = min(k0a + run_offset(E, u, tid, 0), klast);
-        const Vec<CT, E> cq = load_vec<E>(col, e);
-        aq[u] = load_vec<E>(val, e);
-        if (!PACKED) sq[PACKED ? 0 : u] = load_vec<PACKED ? 1 : E>(slot, e);
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            if (PACKED) pw[PACKED ? E * u + j : 0] = (uint32_t)cq[j];
-            else c[E * u + j] = cbase + (int32_t)cq[j];
-        }
-    }
-    if (PACKED) {
-        // lane t's base for load u * E + j: the lanes of a group read the
-        // same word, a wave's four groups one 16-byte piece
-        const int32_t *pb = pbase + pack_base_index(CAP, E, 0, tid, 0);
-#pragma unroll
-        for (int i = 0; i < E * Q; ++i)
-            c[i] = pb[i * (kWave / kPackLanes)] + (int32_t)(pw[i] & ((1u << kPackPosBits) - 1));
-    }
     int32_t rb[R], re[R];
     XT s[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int32_t r = min(r0 + i * kBlock + tid, r1 - 1);
-        rb[i] = rowptr[r];
-        re[i] = rowptr[r + 1];
-        s[i] = w[r];
-    }
-    // a discarded position reads element 0 of v (direct reads) or of the
-    // ghost buffer (not empty: this block has entries)
     XT x[E * Q];
+    // lane t's base for load u * E + j: the lanes of a group read the same
+    // word, a wave's four groups one 16-byte piece
+    const int32_t *pb = PACKED ? pbase + pack_base_index(CAP, E, 0, tid, 0) : nullptr;
+    if constexpr (PACKED && sizeof(VT) == 8) {
+        // float64: positions first (each load's words, then its bases), then
+        // the rows and values, then the gathers one by one, each as soon as
+        // its position has arrived -- the scheduling barriers keep the
+        // compiler from computing every position before the first gather
+        // (off-process launch on the KKT-like matrix 0.213 -> 0.206 ms; the
+        // same order costs float32 and bfloat16 3-4%)
+        int32_t bs[E * Q];
 #pragma unroll
-    for (int u = 0; u < Q; ++u) {
+        for (int u = 0; u < Q; ++u) {
+            const int32_t e = min(k0a + run_offset(E, u, tid, 0), klast);
+            const Vec<CT, E> cq = load_vec<E>(col, e);
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
-            const int32_t e = k0a + run_offset(E, u, tid, j);
-            int32_t &cc = c[E * u + j];
-            if (e < k0 || e >= k1) cc = DIRECT ? INT32_MIN : 0;
-            if (DIRECT)
-                x[E * u + j] = (cc < 0 ? vsrc : xsrc)[cc & 0x7fffffff];
-            else
+            for (int j = 0; j < E; ++j) {
+                pw[PACKED ? E * u + j : 0] = (uint32_t)cq[j];
+                bs[E * u + j] = pb[(E * u + j) * (kWave / kPackLanes)];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int32_t r = min(r0 + i * kBlock + tid, r1 - 1);
+            rb[i] = rowptr[r];
+            re[i] = rowptr[r + 1];
+            s[i] = w[r];
+        }
+#pragma unroll
+        for (int u = 0; u < Q; ++u)
+            aq[u] = load_vec<E>(val, min(k0a + run_offset(E, u, tid, 0), klast));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int32_t e = k0a + run_offset(E, u, tid, j);
+                int32_t cc = bs[E * u + j] +
+                             (int32_t)(pw[PACKED ? E * u + j : 0] & ((1u << kPackPosBits) - 1));
+                // a discarded position reads element 0 of the ghost buffer
+                if (e < k0 || e >= k1) cc = 0;
                 x[E * u + j] = xsrc[cc];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            const int32_t e = min(k0a + run_offset(E, u, tid, 0), klast);
+            const Vec<CT, E> cq = load_vec<E>(col, e);
+            aq[u] = load_vec<E>(val, e);
+            if (!PACKED) sq[PACKED ? 0 : u] = load_vec<PACKED ? 1 : E>(slot, e);
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                if (PACKED) pw[PACKED ? E * u + j : 0] = (uint32_t)cq[j];
+                else c[E * u + j] = cbase + (int32_t)cq[j];
+            }
+        }
+        if (PACKED) {
+#pragma unroll
+            for (int i = 0; i < E * Q; ++i)
+                c[i] = pb[i * (kWave / kPackLanes)] + (int32_t)(pw[i] & ((1u << kPackPosBits) - 1));
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int32_t r = min(r0 + i * kBlock + tid, r1 - 1);
+            rb[i] = rowptr[r];
+            re[i] = rowptr[r + 1];
+            s[i] = w[r];
+        }
+        // a discarded position reads element 0 of v (direct reads) or of the
+        // ghost buffer (not empty: this block has entries)
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int32_t e = k0a + run_offset(E, u, tid, j);
+                int32_t &cc = c[E * u + j];
+                if (e < k0 || e >= k1) cc = DIRECT ? INT32_MIN : 0;
+                if (DIRECT)
+                    x[E * u + j] = (cc < 0 ? vsrc : xsrc)[cc & 0x7fffffff];
+                else
+                    x[E * u + j] = xsrc[cc];
+            }
         }
     }
 #pragma unroll
