@@ -503,8 +503,8 @@ __device__ __forceinline__ void product_runs(int32_t r0, int32_t r1, int32_t k0,
 //
 // PACKED: the block's columns are packed words (pack_block): slot in the
 // high bits, the position's offset from its lane group's base in the low
-// bits; the bases (`pbase`, this block's) are wave-uniform scalar loads, and
-// no slot stream is read.
+// bits; each lane loads its group's base (`pbase`, this block's: the 16
+// lanes of a group read one word), and no slot stream is read.
 template <typename VT, typename XT, typename CT, int CAP, bool DIRECT, bool NTW, int E,
           bool PACKED = false>
 __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int32_t k0, int32_t k1,
@@ -549,7 +549,7 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
         // the rows and values, then the gathers one by one, each as soon as
         // its position has arrived -- the scheduling barriers keep the
         // compiler from computing every position before the first gather
-        // (off-process launch on the KKT-like matrix 0.213 -> 0.206 ms; the
+        // (off-process launch on the KKT-like matrix 0.213 -> 0.208 ms; the
         // same order costs float32 and bfloat16 3-4%)
         int32_t bs[E * Q];
 #pragma unroll
