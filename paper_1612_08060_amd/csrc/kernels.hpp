@@ -541,8 +541,9 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
     int32_t rb[R], re[R];
     XT s[R];
     XT x[E * Q];
-    // lane t's base for load u * E + j: the lanes of a group read the same
-    // word, a wave's four groups one 16-byte piece
+    // lane t's bases (pack_base_index): for runs of 2 the two words of
+    // vector u side by side, for runs of 4 and 8 one word per load; the 16
+    // lanes of a group read the same words
     const int32_t *pb = PACKED ? pbase + pack_base_index(CAP, E, 0, tid, 0) : nullptr;
     if constexpr (PACKED && sizeof(VT) == 8) {
         // float64: positions first (each load's words, then its bases), then
@@ -556,10 +557,12 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
         for (int u = 0; u < Q; ++u) {
             const int32_t e = min(k0a + run_offset(E, u, tid, 0), klast);
             const Vec<CT, E> cq = load_vec<E>(col, e);
+            static_assert(pack_base_stride(E) == 1, "float64 runs load their bases as vectors");
+            const Vec<int32_t, E> bv = *reinterpret_cast<const Vec<int32_t, E> *>(pb + E * u);
 #pragma unroll
             for (int j = 0; j < E; ++j) {
                 pw[PACKED ? E * u + j : 0] = (uint32_t)cq[j];
-                bs[E * u + j] = pb[(E * u + j) * (kWave / kPackLanes)];
+                bs[E * u + j] = bv[j];
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -600,10 +603,18 @@ __device__ __forceinline__ void remote_product_runs(int32_t r0, int32_t r1, int3
                 else c[E * u + j] = cbase + (int32_t)cq[j];
             }
         }
-        if (PACKED) {
+        if constexpr (PACKED && pack_base_stride(E) == 1) {
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const Vec<int32_t, E> bv = *reinterpret_cast<const Vec<int32_t, E> *>(pb + E * u);
+#pragma unroll
+                for (int j = 0; j < E; ++j)
+                    c[E * u + j] = bv[j] + (int32_t)(pw[PACKED ? E * u + j : 0] & ((1u << kPackPosBits) - 1));
+            }
+        } else if constexpr (PACKED) {
 #pragma unroll
             for (int i = 0; i < E * Q; ++i)
-                c[i] = pb[i * (kWave / kPackLanes)] + (int32_t)(pw[i] & ((1u << kPackPosBits) - 1));
+                c[i] = pb[i * pack_base_stride(E)] + (int32_t)(pw[PACKED ? i : 0] & ((1u << kPackPosBits) - 1));
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {

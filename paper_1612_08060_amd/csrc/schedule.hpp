@@ -70,8 +70,13 @@ void sort_blocks(const std::vector<int32_t> &blkptr, int cap, const int32_t *col
 // kPackLanes consecutive lanes of one wave load instruction (the smallest
 // position those lanes read).  In gather order such lanes read positions of
 // one or two bands of the ghost buffer, so the offsets stay small.  The
-// bases of a block sit at [wave][u * run + j][group] (wave = lane / kWave,
-// group = lane % kWave / kPackLanes): cap / kPackLanes of them.
+// bases of a block (cap / kPackLanes of them; wave = lane / kWave, group =
+// lane % kWave / kPackLanes) sit at [wave][group][u * run + j] for runs of
+// 2 (float64), so that a lane loads its bases for one vector of the run
+// with one vector load (off-process launch 0.2075 -> 0.2029 ms), and at
+// [wave][u * run + j][group] for runs of 4 and 8, whose lanes load them one
+// by one, a wave's four groups from one 16-byte piece (float32 and
+// bfloat16 lost 2-3% with the vector form).
 constexpr int kWave = 64;
 constexpr int kPackLanes = 16;
 constexpr int kPackPosBits = 19;
@@ -82,10 +87,15 @@ constexpr int kPackSlotBits = 32 - kPackPosBits;
 constexpr int32_t kPlainBlock = -1;
 constexpr int32_t kPackedBlock = -2;
 
+// Distance between the bases of consecutive loads of one lane.
+constexpr int32_t pack_base_stride(int run) { return run < 4 ? 1 : kWave / kPackLanes; }
+
 // Index of the base that lane t's component j of vector u reads.
 constexpr int32_t pack_base_index(int cap, int run, int u, int t, int j) {
-    return ((t / kWave) * (cap / kLanes) + u * run + j) * (kWave / kPackLanes) +
-           (t % kWave) / kPackLanes;
+    return run < 4 ? ((t / kWave) * (kWave / kPackLanes) + (t % kWave) / kPackLanes) * (cap / kLanes) +
+                         u * run + j
+                   : ((t / kWave) * (cap / kLanes) + u * run + j) * (kWave / kPackLanes) +
+                         (t % kWave) / kPackLanes;
 }
 
 // Pack block [k0, k1) of `pos` and `slot` (in load order, as sort_blocks

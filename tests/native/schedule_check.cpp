@@ -172,10 +172,10 @@ static int check_run_loads() {
 
 // Packed words (pack_block): decoded the way remote_product_runs decodes
 // them (lane t's base for load u * run + j at pack_base_index(cap, run, 0,
-// t, 0) + 4 (u * run + j)), every entry of a packed block gives back its
-// position and slot; a block with a lane group whose positions span
-// 2^kPackPosBits or more, a block whose aligned span exceeds cap and a cap
-// above 2^kPackSlotBits are refused with nothing written.
+// t, 0) + (u * run + j) * pack_base_stride(run)), every entry of a packed
+// block gives back its position and slot; a block with a lane group whose
+// positions span 2^kPackPosBits or more, a block whose aligned span exceeds
+// cap and a cap above 2^kPackSlotBits are refused with nothing written.
 static int check_pack() {
     using namespace napspmv;
     std::mt19937 rng(11);
@@ -184,7 +184,7 @@ static int check_pack() {
             for (int u = 0; u < cap / (run * kLanes); ++u)
                 for (int t = 0; t < kLanes; ++t)
                     for (int j = 0; j < run; ++j)
-                        if (pack_base_index(cap, run, 0, t, 0) + (u * run + j) * (kWave / kPackLanes) !=
+                        if (pack_base_index(cap, run, 0, t, 0) + (u * run + j) * pack_base_stride(run) !=
                             pack_base_index(cap, run, u, t, j))
                             return fail("kernel base index", cap, t);
     int64_t packed = 0, refused = 0;
@@ -247,7 +247,7 @@ static int check_pack() {
                     for (int j = 0; j < run; ++j) {
                         const int32_t k = a + run_offset(run, u, t, j);
                         if (k < k0 || k >= k1) continue;
-                        const int32_t bi = pack_base_index(cap, run, 0, t, 0) + (u * run + j) * (kWave / kPackLanes);
+                        const int32_t bi = pack_base_index(cap, run, 0, t, 0) + (u * run + j) * pack_base_stride(run);
                         const int32_t p = base[bi] + (int32_t)(word[k] & ((1u << kPackPosBits) - 1));
                         if (p != pos[k]) return fail("packed position", trial, k);
                         if ((word[k] >> kPackPosBits) != slot[k]) return fail("packed slot", trial, k);
