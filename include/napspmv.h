@@ -460,10 +460,10 @@ NAPSPMV_API int napspmv_plan_read_ghost_values(napspmv_plan_t plan, const void *
  *   [1] packed  gather order, position and slot in one 32-bit word whose
  *               position is an offset from a base shared by 16 lanes
  *   [2] narrow  stored order, 16-bit positions from a per-block base
- * (blocks without entries are not counted).  The layout never changes a
- * result bit;
- * it follows BLOCK_NNZ and REMOTE_NNZ.  EINVAL for a NULL argument or a
- * host-only plan. */
+ * (blocks without entries are not counted; plans with direct reads count
+ * every block as plain).  The layout never changes a result bit; it follows
+ * BLOCK_NNZ and REMOTE_NNZ.  EINVAL for a NULL argument or a host-only
+ * plan. */
 NAPSPMV_API int napspmv_plan_block_kinds(napspmv_plan_t plan, int64_t *kinds_out);
 
 /* Tuning parameters of the apply kernels (NAPSPMV_PARAM_*); -1 restores the
