@@ -2,18 +2,22 @@
 
 The on-process product loads aligned runs of 2, 4 or 8 entries per lane
 (float64, float32, bfloat16 values), the off-process product runs of 16
-bytes of values laid out by the host in load order, and off-process blocks
-whose ghost positions span less than 65536 read 16-bit offsets from a
-per-block base.  These tests aim at the edges of those layouts:
+bytes of values laid out by the host in load order, with each entry's ghost
+position and slot packed in one word where the block allows it, and
+off-process blocks whose ghost positions span less than 65536 read 16-bit
+offsets from a per-block base.  These tests aim at the edges of those
+layouts:
 
 * row blocks whose first entry is not aligned, rows of exactly the block
   capacity and a few entries either side of it (single-row blocks whose
-  aligned span exceeds the capacity take the one-entry-per-lane path; longer
-  rows the chunked path), empty rows and processes without off-process
-  entries, at every block size;
+  aligned span exceeds the capacity, and longer rows, take the chunked
+  path), empty rows and processes without off-process entries, at every
+  block size;
 * one plan holding both narrow off-process blocks (halos read from the
   neighbouring process only) and wide ones (columns drawn from the whole
   matrix, more than 65536 ghost positions apart);
+* one plan holding packed blocks and blocks whose lane groups read ghost
+  positions 2^19 or more apart (int32 positions and slots);
 
 float64 w bitwise equal to the oracle's split-order product (both modes),
 float32 and bfloat16 values within 1e-5 and 2e-2 normwise of the float64
